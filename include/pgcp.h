@@ -1,0 +1,199 @@
+/*
+ * pgcp.h -- C ABI of the MI355X (gfx950) implementation of parallelizable
+ * global conformal parameterization via partial welding (PGCP; Choi,
+ * Leung-Liu, Gu, Lui).  Algorithm 3 of the paper, stage by stage:
+ *
+ *   pgcp_partition       Section 4.1   cut the mesh into simply-connected pieces
+ *   pgcp_assemble_cotan  Section 4.2   cotangent Laplacian of every piece
+ *   pgcp_local_param     Section 4.2   DNCP free-boundary flattening of every piece
+ *   pgcp_weld            Sections 4.3, 4.4   partial welding (+ disk / sphere step)
+ *   pgcp_harmonic_solve  Section 4.5   Laplace equation with the welded boundary
+ *   pgcp_distortion      Sections 3.5, 5   angle distortion, Beltrami |mu|, flips
+ *
+ * Conventions
+ *  - Plain C types only; no exceptions cross this boundary.  Every call returns
+ *    a pgcp_status; pgcp_last_error(ctx) gives a message for the last failure.
+ *  - "_host" pointers are host memory, "_dev" pointers are device memory on the
+ *    context's device.  The caller owns every array it passes; the library never
+ *    frees them.  Device arrays must stay valid until the context's stream has
+ *    passed the call.
+ *  - The library owns pgcp_ctx and pgcp_part; release them with the matching
+ *    *_destroy call.
+ *  - Device work is enqueued on the context's stream.  Calls that return host
+ *    results (partition, query/export, weld, and any call given a non-NULL stats
+ *    pointer) synchronise that stream before returning.
+ *  - Coordinates are float64.  Indices are int32.  Planar coordinates are stored
+ *    as interleaved (x, y) pairs; spherical ones as (x, y, z) triples.
+ *  - Boundary arrays ("bdy") list every piece's boundary loop, piece by piece
+ *    in piece order, each loop counter-clockwise (the piece on its left) from
+ *    its smallest global vertex index.  Seam arrays list every vertex that lies
+ *    on some piece's boundary once, in ascending global index.
+ */
+#ifndef PGCP_H
+#define PGCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PGCP_OK = 0,
+    PGCP_E_INVALID = -1,    /* bad argument, shape or call order                        */
+    PGCP_E_TOPOLOGY = -2,   /* a piece is not a disk: non-manifold edge, pinched vertex,
+                               several boundary loops, wrong Euler characteristic        */
+    PGCP_E_DEGENERATE = -3, /* zero-area triangle                                        */
+    PGCP_E_NOCONV = -4,     /* some piece missed the residual tolerance (see stats)       */
+    PGCP_E_BREAKDOWN = -5,  /* CG breakdown (p.Ap <= 0 or not finite)                     */
+    PGCP_E_WELD = -6,       /* welding precondition failed (arc order, short arc, ...)    */
+    PGCP_E_HIP = -7,        /* HIP runtime error                                          */
+    PGCP_E_NOMEM = -8
+} pgcp_status;
+
+typedef enum { PGCP_FREE = 0, PGCP_DISK = 1, PGCP_SPHERE = 2 } pgcp_mode;
+typedef enum { PGCP_FP64 = 0, PGCP_FP32_REFINE = 1 } pgcp_precision;
+
+typedef struct pgcp_ctx pgcp_ctx;
+typedef struct pgcp_part pgcp_part;
+
+/* Solver options.  tol: relative residual ||b - A x||_2 / ||b||_2 in FP64 with
+ * the FP64 matrix, per piece (per coordinate for the harmonic solve).
+ * inner_tol: relative residual reduction of each FP32 inner solve (FP32_REFINE).
+ * max_iter: cap on CG iterations per inner solve; max_refine: cap on FP64
+ * residual evaluations.  Zero fields take the defaults (1e-10, 1e-4, 20000, 30). */
+typedef struct {
+    int32_t precision;        /* pgcp_precision */
+    int32_t max_iter;
+    int32_t max_refine;
+    int32_t reserved;
+    double tol;
+    double inner_tol;
+} pgcp_solve_opts;
+
+/* Per-call solver report.  Arrays are optional (NULL = not wanted), sized n_sub. */
+typedef struct {
+    int32_t n_sub;            /* out */
+    int32_t refine_steps;     /* out: FP64 residual evaluations performed            */
+    int64_t total_iters;      /* out: CG iterations summed over pieces and passes    */
+    int32_t* iters;           /* in/out [n_sub] CG iterations per piece (all passes) */
+    double* relres;           /* in/out [n_sub*2] final FP64 relative residual (x, y) */
+    int32_t* status;          /* in/out [n_sub] 0 = converged                         */
+    double seconds;           /* out: wall time of the call                          */
+    double cg_kernel_ms;      /* out: summed duration of the batched-CG launches (HIP events) */
+    double cg_bytes;          /* out: algorithmic bytes those launches move (see DESIGN)      */
+    int32_t cg_launches;      /* out: number of batched-CG launches                    */
+    int32_t rows_per_thread;  /* out: rows per thread of the batched-CG launch shape   */
+    int32_t cg_workgroups;    /* out: workgroups of the batched-CG launch              */
+    int32_t reserved2;
+} pgcp_solve_stats;
+
+/* Distortion statistics over all 3|F| angles (Table 5 of the paper). */
+typedef struct {
+    double mean_abs_d, sd_abs_d, max_abs_d;  /* degrees; sd with N-1 */
+    double median_abs_d, iqr_abs_d;          /* midpoint-rule percentiles; NaN unless requested */
+    double max_mu;                           /* max |mu| of the piecewise-linear map */
+    int64_t n_flipped;                       /* signed area (plane) or det (sphere) <= 0 */
+    int64_t n_mu_ge1;                        /* faces with |mu| >= 1 - 1e-8 */
+} pgcp_dist_stats;
+
+typedef struct {
+    int64_t nv, nf;
+    int32_t n_sub;
+    int32_t mode;
+    int64_t n_rows;           /* packed rows (piece vertices, each piece padded to 64) */
+    int64_t n_bdy;            /* total boundary-loop entries                            */
+    int64_t n_seam;           /* distinct boundary vertices                             */
+    int64_t nnz_offdiag;      /* stored off-diagonal entries (without padding)          */
+    int64_t sell_elems;       /* stored off-diagonal slots including SELL-64 padding    */
+    int32_t weld_rounds;      /* rounds of the balanced merge tree                      */
+    int32_t reserved;
+} pgcp_part_info;
+
+/* Context on device `hip_device`, enqueuing on `hip_stream` (hipStream_t; NULL =
+ * the null stream). */
+pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream);
+void pgcp_ctx_destroy(pgcp_ctx* ctx);
+const char* pgcp_last_error(const pgcp_ctx* ctx);
+/* Change the stream later calls enqueue on. */
+pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream);
+
+/* Section 4.1.  Cut edges are interior edges whose two faces carry different
+ * labels; the connected components of the face graph over the remaining
+ * interior edges are the pieces, numbered by their smallest face index.  Every
+ * piece must be a topological disk (one boundary loop, no pinched vertex,
+ * V - E + F = 1), else PGCP_E_TOPOLOGY.  Builds the full plan: piece vertex
+ * lists, SELL-64 matrix structure, boundary loops, DNCP pins, seam list and the
+ * weld merge tree, and uploads it to the device.
+ * V_host [nv][3] float64, F_host [nf][3] int32 (counter-clockwise), label_host
+ * [nf] int32.  Synchronous.  ctx may be NULL: the plan is then host-only (no
+ * device mirrors) and serves pgcp_part_query/export and pgcp_weld only. */
+pgcp_status pgcp_partition(pgcp_ctx* ctx, const double* V_host, int64_t nv,
+                           const int32_t* F_host, int64_t nf, const int32_t* label_host,
+                           int32_t mode, pgcp_part** out);
+pgcp_status pgcp_part_query(const pgcp_part* part, pgcp_part_info* info);
+/* Copy plan arrays to host buffers (each may be NULL):
+ * face_sub [nf], sub_nv [n_sub] (vertices per piece), loop_ptr [n_sub+1],
+ * loop_gv [n_bdy] (boundary loops), seam_gv [n_seam]. */
+pgcp_status pgcp_part_export(const pgcp_part* part, int32_t* face_sub, int32_t* sub_nv,
+                             int32_t* loop_ptr, int32_t* loop_gv, int32_t* seam_gv);
+void pgcp_part_destroy(pgcp_part* part);
+
+/* Copy the assembled FP64 cotangent Laplacian of one piece to host CSR arrays
+ * (local vertex order = ascending global index, columns ascending, diagonal
+ * included).  rowptr [n+1] with n = sub_nv[piece]; col/val sized rowptr[n]
+ * (call first with col = val = NULL to get rowptr).  Synchronous. */
+pgcp_status pgcp_laplacian_export(pgcp_ctx* ctx, const pgcp_part* part, int32_t piece,
+                                  int32_t* rowptr, int32_t* col, double* val);
+
+/* Section 4.2.  Cotangent Laplacian of every piece in its PSD form:
+ * L[p][q] = -(cot a_pq + cot b_pq)/2, L[p][p] = -sum_q L[p][q], cot of the
+ * angle at k in triangle (i,j,k) = (u.v)/|u x v|, u = v_i - v_k, v = v_j - v_k.
+ * Kept on the device in FP64 and FP32.  V_dev [nv][3].  Async. */
+pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* part, const double* V_dev);
+
+/* Section 4.2.  DNCP of every piece: solves (L (+) L - M/2) z = 0 with two
+ * pinned boundary vertices (the loop's smallest global index at (0,0), the
+ * loop vertex farthest from it in R^3 at (distance, 0)), by batched
+ * Jacobi-preconditioned CG on all pieces at once; then translates each piece
+ * so the mean of its boundary points is 0.  Writes bdy_uv_dev [n_bdy][2].
+ * Requires pgcp_assemble_cotan. */
+pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* part, const pgcp_solve_opts* opts,
+                             double* bdy_uv_dev, pgcp_solve_stats* stats);
+
+/* Sections 4.3-4.4.  Partial welding (Algorithms 1 and 2) of the boundary
+ * coordinates along the plan's balanced merge tree; in disk mode followed by
+ * the geodesic algorithm on the outer boundary and the Cayley map onto the unit
+ * disk; in sphere mode the last two components are closed-welded.  Host code.
+ * bdy_uv_host [n_bdy][2] in, welded_uv_host [n_seam][2] out (sphere mode: a
+ * point at infinity is written as (+inf, +inf)).  Synchronous. */
+pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* part, const double* bdy_uv_host,
+                      double* welded_uv_host);
+
+/* Section 4.5.  Harmonic map of every piece with the welded boundary as
+ * Dirichlet data (same L, boundary rows eliminated), batched CG; then the
+ * global gather: interior vertices from their piece, seam vertices from the
+ * weld.  Sphere mode solves each piece in its rotated chart and finishes with
+ * the stereographic projection (2Re w, -2Im w, |w|^2-1)/(|w|^2+1).
+ * welded_uv_dev [n_seam][2]; out_dev [nv][2] (free/disk) or [nv][3] (sphere).
+ * Requires pgcp_assemble_cotan and pgcp_weld. */
+pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* part, const double* welded_uv_dev,
+                                const pgcp_solve_opts* opts, double* out_dev,
+                                pgcp_solve_stats* stats);
+
+/* Sections 3.5 and 5.  Per face: the three angle distortions in degrees
+ * (parameter angle minus surface angle, atan2(|u x v|, u.v)), |mu| of the
+ * piecewise-linear map between isometric frames, and the flip flag (signed
+ * area <= 0 in the plane, det[phi_i, phi_j, phi_k] <= 0 on the sphere).
+ * V_dev [nv][3], F_dev [nf][3], param_dev [nv][dim], dim 2 or 3.  d_dev [nf][3],
+ * mu_dev [nf], flip_dev [nf] may be NULL.  want_quantiles != 0 also computes the
+ * median and IQR of |d| (device sort).  stats may be NULL (then async). */
+pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
+                            const int32_t* F_dev, int64_t nf, const double* param_dev,
+                            int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
+                            int32_t want_quantiles, pgcp_dist_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PGCP_H */

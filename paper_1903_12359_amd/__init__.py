@@ -1,0 +1,363 @@
+"""Python binding of libpgcp (ctypes): argument marshalling only.
+
+Every stage runs inside the C-ABI library (host C++ for the partition and the
+weld, HIP kernels on gfx950 for everything else).  PyTorch provides device
+memory and the stream.  If the built library is missing, importing the
+binding's entry points raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpgcp.so")
+
+PGCP_FREE, PGCP_DISK, PGCP_SPHERE = 0, 1, 2
+MODES = {"free": PGCP_FREE, "disk": PGCP_DISK, "sphere": PGCP_SPHERE}
+PGCP_FP64, PGCP_FP32_REFINE = 0, 1
+STATUS = {0: "OK", -1: "INVALID", -2: "TOPOLOGY", -3: "DEGENERATE", -4: "NOCONV", -5: "BREAKDOWN",
+          -6: "WELD", -7: "HIP", -8: "NOMEM"}
+
+
+class PGCPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pgcp {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("n_sub", ctypes.c_int32), ("refine_steps", ctypes.c_int32), ("total_iters", ctypes.c_int64),
+                ("iters", ctypes.POINTER(ctypes.c_int32)), ("relres", ctypes.POINTER(ctypes.c_double)),
+                ("status", ctypes.POINTER(ctypes.c_int32)), ("seconds", ctypes.c_double),
+                ("cg_kernel_ms", ctypes.c_double), ("cg_bytes", ctypes.c_double), ("cg_launches", ctypes.c_int32),
+                ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class DistStats(ctypes.Structure):
+    _fields_ = [("mean_abs_d", ctypes.c_double), ("sd_abs_d", ctypes.c_double), ("max_abs_d", ctypes.c_double),
+                ("median_abs_d", ctypes.c_double), ("iqr_abs_d", ctypes.c_double), ("max_mu", ctypes.c_double),
+                ("n_flipped", ctypes.c_int64), ("n_mu_ge1", ctypes.c_int64)]
+
+
+class PartInfo(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("nf", ctypes.c_int64), ("n_sub", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64), ("n_bdy", ctypes.c_int64), ("n_seam", ctypes.c_int64),
+                ("nnz_offdiag", ctypes.c_int64), ("sell_elems", ctypes.c_int64), ("weld_rounds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_set_stream", "pgcp_partition",
+           "pgcp_part_query", "pgcp_part_export", "pgcp_part_destroy", "pgcp_laplacian_export",
+           "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpgcp.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libpgcp.so not built ({path}); run `python -m paper_1903_12359_amd.build`")
+    L = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "pgcp_ctx_create": (I32, [ctypes.POINTER(P), ctypes.c_int, P]),
+        "pgcp_ctx_destroy": (None, [P]),
+        "pgcp_last_error": (ctypes.c_char_p, [P]),
+        "pgcp_ctx_set_stream": (I32, [P, P]),
+        "pgcp_partition": (I32, [P, P, I64, P, I64, P, I32, ctypes.POINTER(P)]),
+        "pgcp_part_query": (I32, [P, ctypes.POINTER(PartInfo)]),
+        "pgcp_part_export": (I32, [P, P, P, P, P, P]),
+        "pgcp_part_destroy": (None, [P]),
+        "pgcp_laplacian_export": (I32, [P, P, I32, P, P, P]),
+        "pgcp_assemble_cotan": (I32, [P, P, P]),
+        "pgcp_local_param": (I32, [P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
+        "pgcp_weld": (I32, [P, P, P, P]),
+        "pgcp_harmonic_solve": (I32, [P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
+        "pgcp_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P, P, I32, ctypes.POINTER(DistStats)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _opts(precision="fp64", tol=1e-10, inner_tol=0.0, max_iter=0, max_refine=0):
+    o = SolveOpts()
+    o.precision = PGCP_FP32_REFINE if precision in ("fp32", "fp32_refine", PGCP_FP32_REFINE) else PGCP_FP64
+    o.tol = tol
+    o.inner_tol = inner_tol
+    o.max_iter = max_iter
+    o.max_refine = max_refine
+    return o
+
+
+@dataclass
+class SolveReport:
+    n_sub: int
+    refine_steps: int
+    total_iters: int
+    iters: np.ndarray
+    relres: np.ndarray
+    status: np.ndarray
+    seconds: float
+    cg_kernel_ms: float = 0.0
+    cg_bytes: float = 0.0
+    cg_launches: int = 0
+    rows_per_thread: int = 0
+    cg_workgroups: int = 0
+
+
+class Context:
+    """A libpgcp context bound to a device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.pgcp_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise PGCPError(rc, "context creation failed")
+        self.h = h
+
+    def check(self, rc):
+        if rc != 0:
+            msg = self.lib.pgcp_last_error(self.h)
+            raise PGCPError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pgcp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HostOnly:
+    """Stand-in context for host-only plans (partition and weld without a GPU)."""
+
+    def __init__(self):
+        self.lib = load_library()
+        self.h = None
+
+    def check(self, rc):
+        if rc != 0:
+            raise PGCPError(rc, "host-only call failed")
+
+
+class Plan:
+    """A partition plan (pgcp_part) built on the host and mirrored on the device.
+
+    ctx=None builds a host-only plan (partition, export and weld only).
+    """
+
+    def __init__(self, ctx, V, F, label, mode="free"):
+        if ctx is None:
+            ctx = HostOnly()
+        self.ctx = ctx
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        F = np.ascontiguousarray(F, dtype=np.int32)
+        label = np.ascontiguousarray(label, dtype=np.int32)
+        self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.pgcp_partition(ctx.h, _ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(label),
+                                         self.mode, ctypes.byref(h)))
+        self.h = h
+        info = PartInfo()
+        ctx.check(ctx.lib.pgcp_part_query(h, ctypes.byref(info)))
+        self.info = info
+        self.nv, self.nf, self.K = info.nv, info.nf, info.n_sub
+        self.n_bdy, self.n_seam = info.n_bdy, info.n_seam
+
+    def export(self):
+        face_sub = np.empty(self.nf, np.int32)
+        sub_nv = np.empty(self.K, np.int32)
+        loop_ptr = np.empty(self.K + 1, np.int32)
+        loop_gv = np.empty(self.n_bdy, np.int32)
+        seam_gv = np.empty(self.n_seam, np.int32)
+        self.ctx.check(self.ctx.lib.pgcp_part_export(self.h, _ptr(face_sub), _ptr(sub_nv), _ptr(loop_ptr),
+                                                     _ptr(loop_gv), _ptr(seam_gv)))
+        return dict(face_sub=face_sub, sub_nv=sub_nv, loop_ptr=loop_ptr, loop_gv=loop_gv, seam_gv=seam_gv)
+
+    def laplacian(self, piece: int):
+        """Assembled FP64 Laplacian of one piece as scipy CSR (local order)."""
+        import scipy.sparse as sp
+        n = int(self.export()["sub_nv"][piece])
+        rowptr = np.empty(n + 1, np.int32)
+        self.ctx.check(self.ctx.lib.pgcp_laplacian_export(self.ctx.h, self.h, piece, _ptr(rowptr), None, None))
+        col = np.empty(rowptr[-1], np.int32)
+        val = np.empty(rowptr[-1], np.float64)
+        self.ctx.check(self.ctx.lib.pgcp_laplacian_export(self.ctx.h, self.h, piece, _ptr(rowptr), _ptr(col),
+                                                          _ptr(val)))
+        return sp.csr_matrix((val, col, rowptr), shape=(n, n))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.pgcp_part_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stats_struct(K):
+    st = SolveStats()
+    it = np.zeros(K, np.int32)
+    rr = np.zeros(2 * K, np.float64)
+    ss = np.zeros(K, np.int32)
+    st.iters = it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    st.relres = rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    st.status = ss.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    return st, (it, rr, ss)
+
+
+def _report(st, keep):
+    it, rr, ss = keep
+    return SolveReport(st.n_sub, st.refine_steps, st.total_iters, it.copy(), rr.reshape(-1, 2).copy(),
+                       ss.copy(), st.seconds, st.cg_kernel_ms, st.cg_bytes, st.cg_launches, st.rows_per_thread,
+                       st.cg_workgroups)
+
+
+def assemble_cotan(ctx: Context, plan: Plan, V_dev):
+    ctx.check(ctx.lib.pgcp_assemble_cotan(ctx.h, plan.h, _ptr(V_dev)))
+
+
+def local_param(ctx: Context, plan: Plan, out=None, stats=True, allow_noconv=False, **opts):
+    import torch
+    if out is None:
+        out = torch.empty((plan.n_bdy, 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    o = _opts(**opts)
+    rep = None
+    if stats:
+        st, keep = _stats_struct(plan.K)
+        rc = ctx.lib.pgcp_local_param(ctx.h, plan.h, ctypes.byref(o), _ptr(out), ctypes.byref(st))
+        rep = _report(st, keep)
+    else:
+        rc = ctx.lib.pgcp_local_param(ctx.h, plan.h, ctypes.byref(o), _ptr(out), None)
+    if not (allow_noconv and rc == -4):
+        ctx.check(rc)
+    return out, rep
+
+
+def weld(ctx, plan: Plan, bdy_host: np.ndarray, out=None):
+    """Host weld; ctx may be None (host-only plans)."""
+    if ctx is None:
+        ctx = plan.ctx
+    bdy_host = np.ascontiguousarray(bdy_host, dtype=np.float64)
+    if out is None:
+        out = np.empty((plan.n_seam, 2), np.float64)
+    ctx.check(ctx.lib.pgcp_weld(ctx.h, plan.h, _ptr(bdy_host), _ptr(out)))
+    return out
+
+
+def harmonic_solve(ctx: Context, plan: Plan, welded_dev, out=None, stats=True, allow_noconv=False, **opts):
+    import torch
+    dim = 3 if plan.mode == PGCP_SPHERE else 2
+    if out is None:
+        out = torch.empty((plan.nv, dim), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    o = _opts(**opts)
+    rep = None
+    if stats:
+        st, keep = _stats_struct(plan.K)
+        rc = ctx.lib.pgcp_harmonic_solve(ctx.h, plan.h, _ptr(welded_dev), ctypes.byref(o), _ptr(out),
+                                         ctypes.byref(st))
+        rep = _report(st, keep)
+    else:
+        rc = ctx.lib.pgcp_harmonic_solve(ctx.h, plan.h, _ptr(welded_dev), ctypes.byref(o), _ptr(out), None)
+    if not (allow_noconv and rc == -4):
+        ctx.check(rc)
+    return out, rep
+
+
+def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantiles=False, stats=True):
+    import torch
+    nv, nf = V_dev.shape[0], F_dev.shape[0]
+    dim = param_dev.shape[1]
+    dev = f"cuda:{ctx.device}"
+    d = mu = flip = None
+    if want_arrays:
+        d = torch.empty((nf, 3), dtype=torch.float64, device=dev)
+        mu = torch.empty(nf, dtype=torch.float64, device=dev)
+        flip = torch.empty(nf, dtype=torch.uint8, device=dev)
+    st = DistStats()
+    ctx.check(ctx.lib.pgcp_distortion(ctx.h, _ptr(V_dev), nv, _ptr(F_dev), nf, _ptr(param_dev), dim, _ptr(d),
+                                      _ptr(mu), _ptr(flip), 1 if quantiles else 0,
+                                      ctypes.byref(st) if stats else None))
+    out = {k: getattr(st, k) for k, _ in DistStats._fields_} if stats else None
+    return out, d, mu, flip
+
+
+def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,
+        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None):
+    """Algorithm 3 end to end; returns (phi_dev, dist_stats, reports).
+
+    V, F, label are host arrays (the partition runs on the host); V_dev/F_dev
+    are their device copies (made here if not given).
+    """
+    import torch
+    dev = f"cuda:{ctx.device}"
+    if times is None:
+        times = {}
+    sync = ctx.stream.synchronize
+    t = time.perf_counter()
+    if V_dev is None:
+        V_dev = torch.from_numpy(np.ascontiguousarray(V, np.float64)).to(dev)
+    if F_dev is None:
+        F_dev = torch.from_numpy(np.ascontiguousarray(F, np.int32)).to(dev)
+    own_plan = plan is None
+    if plan is None:
+        plan = Plan(ctx, V, F, label, mode)
+    times["partition"] = time.perf_counter() - t
+    t = time.perf_counter()
+    assemble_cotan(ctx, plan, V_dev)
+    bdy, rep1 = local_param(ctx, plan, precision=precision, tol=tol, inner_tol=inner_tol)
+    bdy_h = bdy.cpu().numpy()
+    times["assemble+dncp"] = time.perf_counter() - t
+    t = time.perf_counter()
+    welded = weld(ctx, plan, bdy_h)
+    times["weld"] = time.perf_counter() - t
+    t = time.perf_counter()
+    welded_dev = torch.from_numpy(welded).to(dev)
+    phi, rep2 = harmonic_solve(ctx, plan, welded_dev, precision=precision, tol=tol, inner_tol=inner_tol)
+    sync()
+    times["harmonic"] = time.perf_counter() - t
+    t = time.perf_counter()
+    st, _, _, _ = distortion(ctx, V_dev, F_dev, phi, quantiles=quantiles)
+    times["distortion"] = time.perf_counter() - t
+    if own_plan:
+        plan.close()
+    return phi, st, dict(dncp=rep1, harmonic=rep2, times=times, bdy=bdy_h, welded=welded)

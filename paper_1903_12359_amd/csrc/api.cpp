@@ -1,0 +1,172 @@
+// C ABI of libpgcp: argument checks, error strings and timing around the
+// host (partition, weld) and device (assembly, solves, distortion) stages.
+
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "pgcp_internal.h"
+
+using pgcp::Error;
+
+namespace {
+
+pgcp_status fail(pgcp_ctx* ctx, const Error& e) {
+    if (ctx && e.code != PGCP_OK) ctx->last_error = e.msg;
+    return e.code;
+}
+
+pgcp_status bad(pgcp_ctx* ctx, const char* m) { return fail(ctx, Error{PGCP_E_INVALID, m}); }
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream) {
+    if (!out) return PGCP_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return PGCP_E_HIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return PGCP_E_HIP;
+    pgcp_ctx* c = new (std::nothrow) pgcp_ctx();
+    if (!c) return PGCP_E_NOMEM;
+    c->device = hip_device;
+    c->stream = (hipStream_t)hip_stream;
+    (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    *out = c;
+    return PGCP_OK;
+}
+
+void pgcp_ctx_destroy(pgcp_ctx* ctx) { delete ctx; }
+
+const char* pgcp_last_error(const pgcp_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream) {
+    if (!ctx) return PGCP_E_INVALID;
+    ctx->stream = (hipStream_t)hip_stream;
+    return PGCP_OK;
+}
+
+pgcp_status pgcp_partition(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                           const int32_t* label, int32_t mode, pgcp_part** out) {
+    if (!V || !F || !label || !out) return bad(ctx, "null argument");
+    *out = nullptr;
+    pgcp_part* P = new (std::nothrow) pgcp_part();
+    if (!P) return fail(ctx, Error{PGCP_E_NOMEM, "out of host memory"});
+    Error e{PGCP_OK, ""};
+    try {
+        e = pgcp::build_plan(P, V, nv, F, nf, label, mode);
+    } catch (const std::bad_alloc&) {
+        e = Error{PGCP_E_NOMEM, "out of host memory"};
+    }
+    if (e.code == PGCP_OK && ctx) {
+        if (hipSetDevice(ctx->device) != hipSuccess) e = Error{PGCP_E_HIP, "hipSetDevice failed"};
+        else e = pgcp::upload_plan(ctx, P);
+        if (e.code == PGCP_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
+            e = Error{PGCP_E_HIP, "plan upload failed"};
+    }
+    if (e.code != PGCP_OK) {
+        pgcp::free_part_device(P);
+        delete P;
+        if (!ctx) return e.code;
+        return fail(ctx, e);
+    }
+    P->host_only = ctx == nullptr;
+    *out = P;
+    return PGCP_OK;
+}
+
+pgcp_status pgcp_part_query(const pgcp_part* P, pgcp_part_info* info) {
+    if (!P || !info) return PGCP_E_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->nv = P->nv;
+    info->nf = P->nf;
+    info->n_sub = P->K;
+    info->mode = P->mode;
+    info->n_rows = P->N;
+    info->n_bdy = P->n_bdy;
+    info->n_seam = P->n_seam;
+    info->nnz_offdiag = P->nnz_off;
+    info->sell_elems = P->sell_elems;
+    info->weld_rounds = (int32_t)P->weld_rounds.size();
+    return PGCP_OK;
+}
+
+pgcp_status pgcp_part_export(const pgcp_part* P, int32_t* face_sub, int32_t* sub_nv, int32_t* loop_ptr,
+                             int32_t* loop_gv, int32_t* seam_gv) {
+    if (!P) return PGCP_E_INVALID;
+    if (face_sub) std::memcpy(face_sub, P->face_sub.data(), P->face_sub.size() * 4);
+    if (sub_nv) std::memcpy(sub_nv, P->sub_nv.data(), P->sub_nv.size() * 4);
+    if (loop_ptr) std::memcpy(loop_ptr, P->loop_ptr.data(), P->loop_ptr.size() * 4);
+    if (loop_gv) std::memcpy(loop_gv, P->loop_gv.data(), P->loop_gv.size() * 4);
+    if (seam_gv) std::memcpy(seam_gv, P->seam_gv.data(), P->seam_gv.size() * 4);
+    return PGCP_OK;
+}
+
+void pgcp_part_destroy(pgcp_part* P) {
+    if (!P) return;
+    pgcp::free_part_device(P);
+    delete P;
+}
+
+pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev) {
+    if (!ctx || !P || !V_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    return fail(ctx, pgcp::launch_assemble(ctx, P, V_dev));
+}
+
+pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* opts, double* bdy_uv_dev,
+                             pgcp_solve_stats* stats) {
+    if (!ctx || !P || !bdy_uv_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    double t0 = now();
+    Error e = pgcp::assembled_ok(ctx, P);
+    if (e.code == PGCP_OK) e = pgcp::run_local_param(ctx, P, opts, bdy_uv_dev, stats);
+    if (stats) {
+        (void)hipStreamSynchronize(ctx->stream);
+        stats->seconds = now() - t0;
+    }
+    return fail(ctx, e);
+}
+
+pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv_host, double* welded_uv_host) {
+    if (!P || !bdy_uv_host || !welded_uv_host) return bad(ctx, "null argument");
+    return fail(ctx, pgcp::weld_all(P, bdy_uv_host, welded_uv_host));
+}
+
+pgcp_status pgcp_laplacian_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, int32_t* rowptr,
+                                  int32_t* col, double* val) {
+    if (!ctx || !P || !rowptr) return bad(ctx, "null argument");
+    if (P->host_only || !P->assembled) return bad(ctx, "plan has no assembled device matrix");
+    if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
+    return fail(ctx, pgcp::export_laplacian(ctx, P, piece, rowptr, col, val));
+}
+
+pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* P, const double* welded_uv_dev,
+                                const pgcp_solve_opts* opts, double* out_dev, pgcp_solve_stats* stats) {
+    if (!ctx || !P || !welded_uv_dev || !out_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    double t0 = now();
+    Error e = pgcp::run_harmonic(ctx, P, welded_uv_dev, opts, out_dev, stats);
+    if (stats) {
+        (void)hipStreamSynchronize(ctx->stream);
+        stats->seconds = now() - t0;
+    }
+    return fail(ctx, e);
+}
+
+pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
+                            const double* param_dev, int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
+                            int32_t want_quantiles, pgcp_dist_stats* stats) {
+    if (!ctx || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
+    if (dim != 2 && dim != 3) return bad(ctx, "dim must be 2 or 3");
+    if (nf <= 0 || nv <= 0) return bad(ctx, "empty mesh");
+    return fail(ctx, pgcp::run_distortion(ctx, V_dev, nv, F_dev, nf, param_dev, dim, d_dev, mu_dev, flip_dev,
+                                          want_quantiles, stats));
+}
+
+}  // extern "C"

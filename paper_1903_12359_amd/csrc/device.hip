@@ -1,0 +1,1454 @@
+// Device part of libpgcp (gfx950): cotangent assembly, batched persistent PCG
+// for the DNCP and harmonic systems of every piece at once, FP64 residual /
+// iterative refinement, boundary gathers and the distortion check.
+//
+// Data layout.  The vertices of every piece are packed into consecutive rows
+// ("packed rows"), each piece padded to a multiple of 64 rows so that one
+// 64-row slice (one wavefront) never straddles two pieces.  The off-diagonal
+// part of each piece's cotangent Laplacian is stored in SELL-64: slice s holds
+// width w_s columns, element (s, k, lane) at sl_ptr[s] + 64 k + lane, so lane l
+// of a wavefront reads row 64 s + l and every load is coalesced.  Padding
+// slots point at the row itself with value 0.  The diagonal is a separate
+// dense vector.  Both coordinates of a vector are interleaved (float2/double2)
+// so one matrix read serves x and y.
+//
+// Batched persistent PCG.  One cooperative launch covers all pieces.  Each
+// workgroup owns a contiguous range of slices of exactly one piece; the
+// workgroups of a piece meet at per-piece barriers (a monotonically increasing
+// arrival counter), exchange partial dot products through a small global
+// array and sum them in a fixed order, so every workgroup of a piece takes the
+// same alpha, beta and convergence decision and results are bitwise
+// deterministic.  Per iteration there are two barriers:
+//   A: beta; p_new = z + beta p_old (own rows, written to the other p buffer);
+//      q = A p_new computed by gathering z and p_old of neighbour rows (so
+//      p_new need not be visible yet); partial p.q
+//   B: alpha; e += alpha p; r -= alpha q; z = D^-1 r; partial r.z and r.r
+// q and p_new stay in registers between the phases.  Every wait is bounded:
+// a workgroup that spins too long raises a global abort flag and all
+// workgroups leave their loops.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include <hipcub/hipcub.hpp>
+
+#include "pgcp_internal.h"
+
+namespace pgcp {
+
+#define HIPCHK(x)                                                                   \
+    do {                                                                           \
+        hipError_t _e = (x);                                                       \
+        if (_e != hipSuccess)                                                      \
+            return Error{PGCP_E_HIP, std::string(#x) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+static constexpr int BLOCK = 256;
+static constexpr int WAVES = BLOCK / 64;
+static constexpr long long SPIN_MAX = 1ll << 24;
+
+// ----------------------------------------------------------------- buffers
+
+static Error dev_alloc(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return Error{PGCP_OK, ""};
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (bytes == 0) bytes = 16;
+    HIPCHK(hipMalloc(&b.p, bytes));
+    b.bytes = bytes;
+    return Error{PGCP_OK, ""};
+}
+
+static void dev_free(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+template <typename T>
+static Error upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    Error e = dev_alloc(b, v.size() * sizeof(T));
+    if (e.code != PGCP_OK) return e;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return Error{PGCP_OK, ""};
+}
+
+void free_part_device(pgcp_part* P) {
+    DevBuf* all[] = {&P->d_row_gv, &P->d_row_prev, &P->d_row_next, &P->d_row_kind, &P->d_slice_sub,
+                     &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_val64, &P->d_val32,
+                     &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
+                     &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
+                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1,
+                     &P->d_partial, &P->d_bar, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
+                     &P->d_flags, &P->wmap.d_wg_sub, &P->wmap.d_wg_s0, &P->wmap.d_wg_s1,
+                     &P->wmap.d_sub_wg0, &P->wmap.d_sub_nwg, &P->d_row0, &P->d_slicepart,
+                     &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
+                     &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp};
+    for (DevBuf* b : all) dev_free(*b);
+    if (P->ev0) (void)hipEventDestroy(P->ev0);
+    if (P->ev1) (void)hipEventDestroy(P->ev1);
+    P->ev0 = P->ev1 = nullptr;
+}
+
+Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
+    hipStream_t s = ctx->stream;
+    Error e{PGCP_OK, ""};
+#define UP(buf, vec)                      \
+    e = upload(buf, vec, s);              \
+    if (e.code != PGCP_OK) return e;
+    UP(P->d_row_gv, P->row_gv);
+    UP(P->d_row_prev, P->row_prev);
+    UP(P->d_row_next, P->row_next);
+    UP(P->d_row_kind, P->row_kind);
+    UP(P->d_slice_sub, P->slice_sub);
+    UP(P->d_sl_ptr, P->sl_ptr);
+    UP(P->d_sl_w, P->sl_w);
+    UP(P->d_sl_col, P->sl_col);
+    UP(P->d_sl_opp, P->sl_opp);
+    UP(P->d_pin_row, P->pin_row);
+    UP(P->d_pin_x1, P->pin_x1);
+    UP(P->d_loop_ptr, P->loop_ptr);
+    UP(P->d_loop_row, P->loop_row);
+    UP(P->d_loop_seam, P->loop_seam);
+    UP(P->d_seam_gv, P->seam_gv);
+    UP(P->d_row0, P->row0);
+    std::vector<uint8_t> md(P->N), mh(P->N);
+    for (int64_t r = 0; r < P->N; ++r) {
+        md[r] = P->row_kind[r] == 2 ? 1 : 0;
+        mh[r] = P->row_kind[r] != 0 ? 1 : 0;
+    }
+    for (int i = 0; i < P->K; ++i) {
+        md[P->pin_row[2 * i]] = 1;
+        md[P->pin_row[2 * i + 1]] = 1;
+    }
+    UP(P->d_mask_dncp, md);
+    UP(P->d_mask_harm, mh);
+#undef UP
+    const size_t N = (size_t)P->N, E = (size_t)P->sell_elems;
+    if ((e = dev_alloc(P->d_val64, E * 8)).code) return e;
+    if ((e = dev_alloc(P->d_val32, E * 4)).code) return e;
+    if ((e = dev_alloc(P->d_diag64, N * 8)).code) return e;
+    if ((e = dev_alloc(P->d_diag32, N * 4)).code) return e;
+    if ((e = dev_alloc(P->d_u64, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_r64, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_e, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_r, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_z, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_p0, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_p1, N * 16)).code) return e;
+    const size_t K = (size_t)P->K;
+    if ((e = dev_alloc(P->d_rnorm, K * 2 * 8)).code) return e;
+    if ((e = dev_alloc(P->d_scale, K * 2 * 8)).code) return e;
+    if ((e = dev_alloc(P->d_target, K * 2 * 8)).code) return e;
+    if ((e = dev_alloc(P->d_rrout, K * 2 * 8)).code) return e;
+    if ((e = dev_alloc(P->d_iters, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_status, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_active, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_bar, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_abort, 64)).code) return e;
+    if ((e = dev_alloc(P->d_flags, 64)).code) return e;
+    if ((e = dev_alloc(P->d_chart, K * 3 * 8)).code) return e;
+    if ((e = dev_alloc(P->d_slicepart, (size_t)P->nslices * 2 * 8)).code) return e;
+    return Error{PGCP_OK, ""};
+}
+
+// ----------------------------------------------------------------- small vector helpers
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+template <typename V, typename S>
+__device__ __forceinline__ V axpy2(V x, S ax, S ay, V y) {   // y + a*x per component
+    V o;
+    o.x = y.x + ax * x.x;
+    o.y = y.y + ay * x.y;
+    return o;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Fixed-order block sum of NV values per thread; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < WAVES; ++w) s += lds[w * NV + i];
+            v[i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------- assembly
+
+__device__ __forceinline__ double cot_at(const double* __restrict__ V, int a, int b, int k) {
+    // cot of the angle at k in triangle (a, b, k): (u.v) / |u x v|, u = v_a - v_k, v = v_b - v_k
+    double ux = V[3 * (int64_t)a] - V[3 * (int64_t)k], uy = V[3 * (int64_t)a + 1] - V[3 * (int64_t)k + 1],
+           uz = V[3 * (int64_t)a + 2] - V[3 * (int64_t)k + 2];
+    double vx = V[3 * (int64_t)b] - V[3 * (int64_t)k], vy = V[3 * (int64_t)b + 1] - V[3 * (int64_t)k + 1],
+           vz = V[3 * (int64_t)b + 2] - V[3 * (int64_t)k + 2];
+    double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    double dot = ux * vx + uy * vy + uz * vz;
+    return dot / sqrt(cx * cx + cy * cy + cz * cz);
+}
+
+// One thread per packed row: every off-diagonal slot of the row gets
+// -w_pq = -(cot at opp1 + cot at opp2)/2, the diagonal the sum of w_pq.
+// The cotangents of an edge are evaluated with the endpoints in ascending
+// global order so that both rows of a symmetric pair compute identical bits.
+__global__ void __launch_bounds__(BLOCK) k_assemble(
+    int64_t nslices, const int64_t* __restrict__ sl_ptr, const int32_t* __restrict__ sl_w,
+    const int32_t* __restrict__ sl_col, const int32_t* __restrict__ sl_opp,
+    const int32_t* __restrict__ row_gv, const double* __restrict__ V, double* __restrict__ val64,
+    float* __restrict__ val32, double* __restrict__ diag64, float* __restrict__ diag32,
+    int* __restrict__ bad) {
+    int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int64_t s = row >> 6;
+    if (s >= nslices) return;
+    int lane = (int)(row & 63);
+    int g = row_gv[row];
+    int64_t base = sl_ptr[s] + lane;
+    int w = sl_w[s];
+    double dsum = 0.0;
+    for (int k = 0; k < w; ++k) {
+        int64_t el = base + (int64_t)k * 64;
+        int o1 = sl_opp[2 * el], o2 = sl_opp[2 * el + 1];
+        double wv = 0.0;
+        if (o1 >= 0 && g >= 0) {
+            int h = row_gv[sl_col[el]];
+            int a = min(g, h), b = max(g, h);
+            double c1 = cot_at(V, a, b, o1);
+            double c2 = (o2 >= 0) ? cot_at(V, a, b, o2) : 0.0;
+            if (!isfinite(c1) || !isfinite(c2)) atomicExch(bad, 1);
+            wv = 0.5 * (c1 + c2);
+        }
+        val64[el] = -wv;
+        val32[el] = (float)(-wv);
+        dsum += wv;
+    }
+    diag64[row] = dsum;
+    diag32[row] = (float)dsum;
+}
+
+// ----------------------------------------------------------------- FP64 residual
+
+// r = -(A u) on free rows, 0 on Dirichlet rows; per-slice partial |r|^2 (x, y).
+__global__ void __launch_bounds__(BLOCK) k_residual64(
+    int64_t nslices, const int64_t* __restrict__ sl_ptr, const int32_t* __restrict__ sl_w,
+    const int32_t* __restrict__ sl_col, const double* __restrict__ val, const double* __restrict__ diag,
+    const int32_t* __restrict__ rprev, const int32_t* __restrict__ rnext, int coupled,
+    const uint8_t* __restrict__ mask, const double2* __restrict__ u, double2* __restrict__ r,
+    double* __restrict__ slice_part) {
+    int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    int64_t s = row >> 6;
+    if (s >= nslices) return;
+    int lane = (int)(row & 63);
+    double2 ur = u[row];
+    double ax = diag[row] * ur.x, ay = diag[row] * ur.y;
+    int64_t base = sl_ptr[s] + lane;
+    int w = sl_w[s];
+    for (int k = 0; k < w; ++k) {
+        int64_t el = base + (int64_t)k * 64;
+        double v = val[el];
+        double2 uc = u[sl_col[el]];
+        ax += v * uc.x;
+        ay += v * uc.y;
+    }
+    if (coupled) {
+        int pv = rprev[row], nx = rnext[row];
+        if (pv >= 0) {
+            double2 un = u[nx], up = u[pv];
+            ax -= 0.5 * (un.y - up.y);
+            ay += 0.5 * (un.x - up.x);
+        }
+    }
+    double2 out;
+    if (mask[row]) {
+        out.x = 0.0;
+        out.y = 0.0;
+    } else {
+        out.x = -ax;
+        out.y = -ay;
+    }
+    r[row] = out;
+    double px = wave_sum(out.x * out.x), py = wave_sum(out.y * out.y);
+    if (lane == 0) {
+        slice_part[2 * s] = px;
+        slice_part[2 * s + 1] = py;
+    }
+}
+
+// One block per piece: fixed-order sum of its slices' partials.
+__global__ void __launch_bounds__(BLOCK) k_piece_sum(const int32_t* __restrict__ row0,
+                                                      const double* __restrict__ slice_part,
+                                                      double* __restrict__ out) {
+    __shared__ double lds[WAVES * 2];
+    int i = blockIdx.x;
+    int64_t s0 = row0[i] / 64, s1 = row0[i + 1] / 64;
+    double v[2] = {0.0, 0.0};
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += BLOCK) {
+        v[0] += slice_part[2 * s];
+        v[1] += slice_part[2 * s + 1];
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        out[2 * i] = v[0];
+        out[2 * i + 1] = v[1];
+    }
+}
+
+// r_T = r64 / scale (per piece and coordinate), e = 0.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_prep_inner(int64_t N, const int32_t* __restrict__ slice_sub,
+                                                       const double2* __restrict__ r64,
+                                                       const double* __restrict__ scale,
+                                                       typename Vec2<T>::type* __restrict__ r,
+                                                       typename Vec2<T>::type* __restrict__ e) {
+    int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (row >= N) return;
+    int i = slice_sub[row >> 6];
+    double sx = scale[2 * i], sy = scale[2 * i + 1];
+    double2 v = r64[row];
+    typename Vec2<T>::type o, zero;
+    o.x = (T)(sx > 0.0 ? v.x / sx : 0.0);
+    o.y = (T)(sy > 0.0 ? v.y / sy : 0.0);
+    zero.x = (T)0;
+    zero.y = (T)0;
+    r[row] = o;
+    e[row] = zero;
+}
+
+// u += scale * e on active pieces.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_apply_inner(int64_t N, const int32_t* __restrict__ slice_sub,
+                                                        const int32_t* __restrict__ active,
+                                                        const double* __restrict__ scale,
+                                                        const typename Vec2<T>::type* __restrict__ e,
+                                                        double2* __restrict__ u) {
+    int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (row >= N) return;
+    int i = slice_sub[row >> 6];
+    if (!active[i]) return;
+    typename Vec2<T>::type d = e[row];
+    double2 x = u[row];
+    x.x += scale[2 * i] * (double)d.x;
+    x.y += scale[2 * i + 1] * (double)d.y;
+    u[row] = x;
+}
+
+// ----------------------------------------------------------------- persistent batched PCG
+
+template <typename T>
+struct CGArgs {
+    const int64_t* sl_ptr;
+    const int32_t* sl_w;
+    const int32_t* sl_col;
+    const T* val;
+    const T* diag;
+    const int32_t* rprev;
+    const int32_t* rnext;
+    const uint8_t* mask;
+    const int32_t* wg_sub;
+    const int32_t* wg_s0;
+    const int32_t* wg_s1;
+    const int32_t* sub_wg0;
+    const int32_t* sub_nwg;
+    const int32_t* active;         // [K]
+    const double* target_rel2;     // [K*2] squared relative tolerance per piece and coordinate
+    typename Vec2<T>::type* e;
+    typename Vec2<T>::type* r;
+    typename Vec2<T>::type* z;
+    typename Vec2<T>::type* pa;
+    typename Vec2<T>::type* pb;
+    double* partial;               // [G][8]
+    unsigned* bar;                 // [K]
+    int* abort_flag;
+    int32_t* iters;                // [K] out
+    double* rr_out;                // [K*2] out: final recursive |r|^2 / |r0|^2
+    int32_t* status;               // [K] out: 0 ok, 1 breakdown, 2 max_iter, 3 abort
+    int coupled;
+    int max_iter;
+};
+
+__device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned target, int* abort_flag,
+                                              int* lds_abort) {
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long long spins = 0;
+        int ab = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            ++spins;
+            if ((spins & 255) == 0) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ab = 1;
+                    break;
+                }
+                if (spins > SPIN_MAX) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *lds_abort = ab;
+    }
+    __syncthreads();
+    __threadfence();
+    return *lds_abort != 0;
+}
+
+// Sum the partials of the piece's workgroups in a fixed order (tree over
+// workgroup index); nv values at offset off of each workgroup's 8-slot record.
+template <int NV>
+__device__ __forceinline__ void piece_sum(const double* partial, int wg0, int nwg, int off,
+                                          double (&out)[NV], double* lds) {
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += BLOCK) {
+        const double* p = partial + 8 * (int64_t)(wg0 + w) + off;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[16 + i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = lds[16 + i];
+    __syncthreads();
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(BLOCK) k_pcg(CGArgs<T> a) {
+    using V2 = typename Vec2<T>::type;
+    __shared__ double lds[32];
+    __shared__ int lds_abort;
+    const int wg = blockIdx.x;
+    const int sub = a.wg_sub[wg];
+    if (!a.active[sub]) return;
+    const int s0 = a.wg_s0[wg], s1 = a.wg_s1[wg];
+    const int wg0 = a.sub_wg0[sub], nwg = a.sub_nwg[sub];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned* bar = a.bar + sub;
+    unsigned nbar = 0;
+    double* mypart = a.partial + 8 * (int64_t)wg;
+
+    int64_t rows[R];
+    bool valid[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        int s = s0 + wave + WAVES * j;
+        valid[j] = s < s1;
+        rows[j] = (int64_t)s * 64 + lane;
+    }
+
+    // ---- start: z = D^-1 r, p_old = 0, r.z and r.r
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    V2 zero;
+    zero.x = (T)0;
+    zero.y = (T)0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (!valid[j]) continue;
+        int64_t rw = rows[j];
+        V2 rr = a.r[rw];
+        V2 zz;
+        if (a.mask[rw]) {
+            zz = zero;
+            a.r[rw] = zero;
+            rr = zero;
+        } else {
+            T dinv = (T)1 / a.diag[rw];
+            zz.x = dinv * rr.x;
+            zz.y = dinv * rr.y;
+        }
+        a.z[rw] = zz;
+        a.pa[rw] = zero;
+        acc[0] += (double)rr.x * (double)zz.x;
+        acc[1] += (double)rr.y * (double)zz.y;
+        acc[2] += (double)rr.x * (double)rr.x;
+        acc[3] += (double)rr.y * (double)rr.y;
+    }
+    block_sum<4>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 4; ++i) mypart[2 + i] = acc[i];
+    }
+    nbar++;
+    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
+        if (threadIdx.x == 0 && wg == wg0) a.status[sub] = 3;
+        return;
+    }
+    double st[4];
+    piece_sum<4>(a.partial, wg0, nwg, 2, st, lds);
+    double rz[2] = {st[0], st[1]};
+    double rr0[2] = {st[2], st[3]};
+    if (a.coupled) {
+        rz[0] = rz[1] = st[0] + st[1];
+        rr0[0] = rr0[1] = st[2] + st[3];
+    }
+    const double tgt[2] = {a.target_rel2[2 * sub] * rr0[0], a.target_rel2[2 * sub + 1] * rr0[1]};
+    bool done[2] = {rr0[0] <= tgt[0] || !(rz[0] > 0.0), rr0[1] <= tgt[1] || !(rz[1] > 0.0)};
+    double rrc[2] = {rr0[0], rr0[1]};
+    double beta[2] = {0.0, 0.0};
+    int it = 0;
+    int stat = 0;
+    V2* pold = a.pa;
+    V2* pnew = a.pb;
+
+    while (!(done[0] && done[1])) {
+        if (it >= a.max_iter) {
+            stat = 2;
+            break;
+        }
+        // ---- phase A: p_new = z + beta p_old; q = A p_new; p.q
+        const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
+        V2 q[R], pn[R];
+        double pq[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (!valid[j]) continue;
+            int64_t rw = rows[j];
+            V2 zr = a.z[rw], po = pold[rw];
+            V2 p;
+            p.x = done[0] ? (T)0 : zr.x + bx * po.x;
+            p.y = done[1] ? (T)0 : zr.y + by * po.y;
+            pnew[rw] = p;
+            const int64_t s = rw >> 6;
+            const int64_t base = a.sl_ptr[s] + lane;
+            const int w = a.sl_w[s];
+            const T dg = a.diag[rw];
+            T qx = dg * p.x, qy = dg * p.y;
+            for (int k = 0; k < w; ++k) {
+                const int64_t el = base + (int64_t)k * 64;
+                const T v = a.val[el];
+                const int c = a.sl_col[el];
+                V2 zc = a.z[c], pc = pold[c];
+                qx += v * (zc.x + bx * pc.x);
+                qy += v * (zc.y + by * pc.y);
+            }
+            if (a.coupled) {
+                int pv = a.rprev[rw], nx = a.rnext[rw];
+                if (pv >= 0) {
+                    V2 zn = a.z[nx], pnx = pold[nx], zp = a.z[pv], ppv = pold[pv];
+                    T nxx = zn.x + bx * pnx.x, nxy = zn.y + by * pnx.y;
+                    T pvx = zp.x + bx * ppv.x, pvy = zp.y + by * ppv.y;
+                    qx -= (T)0.5 * (nxy - pvy);
+                    qy += (T)0.5 * (nxx - pvx);
+                }
+            }
+            if (a.mask[rw]) {
+                qx = (T)0;
+                qy = (T)0;
+            }
+            q[j].x = qx;
+            q[j].y = qy;
+            pn[j] = p;
+            pq[0] += (double)p.x * (double)qx;
+            pq[1] += (double)p.y * (double)qy;
+        }
+        block_sum<2>(pq, lds);
+        if (threadIdx.x == 0) {
+            mypart[0] = pq[0];
+            mypart[1] = pq[1];
+        }
+        nbar++;
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
+            stat = 3;
+            break;
+        }
+        double pqs[2];
+        piece_sum<2>(a.partial, wg0, nwg, 0, pqs, lds);
+        double alpha[2] = {0.0, 0.0};
+        if (a.coupled) {
+            double den = pqs[0] + pqs[1];
+            if (!(den > 0.0) || !isfinite(den)) {
+                stat = 1;
+                break;
+            }
+            alpha[0] = alpha[1] = rz[0] / den;
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                if (done[c]) continue;
+                if (!(pqs[c] > 0.0) || !isfinite(pqs[c])) {
+                    stat = 1;
+                    break;
+                }
+                alpha[c] = rz[c] / pqs[c];
+            }
+            if (stat) break;
+        }
+        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r
+        const T ax = (T)alpha[0], ay = (T)alpha[1];
+        double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (!valid[j]) continue;
+            int64_t rw = rows[j];
+            V2 ev = a.e[rw], rv = a.r[rw];
+            ev.x += ax * pn[j].x;
+            ev.y += ay * pn[j].y;
+            rv.x -= ax * q[j].x;
+            rv.y -= ay * q[j].y;
+            V2 zz;
+            if (a.mask[rw]) {
+                zz = zero;
+            } else {
+                T dinv = (T)1 / a.diag[rw];
+                zz.x = dinv * rv.x;
+                zz.y = dinv * rv.y;
+            }
+            a.e[rw] = ev;
+            a.r[rw] = rv;
+            a.z[rw] = zz;
+            acc2[0] += (double)rv.x * (double)zz.x;
+            acc2[1] += (double)rv.y * (double)zz.y;
+            acc2[2] += (double)rv.x * (double)rv.x;
+            acc2[3] += (double)rv.y * (double)rv.y;
+        }
+        block_sum<4>(acc2, lds);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < 4; ++i) mypart[2 + i] = acc2[i];
+        }
+        nbar++;
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
+            stat = 3;
+            break;
+        }
+        piece_sum<4>(a.partial, wg0, nwg, 2, st, lds);
+        double rzn[2] = {st[0], st[1]};
+        double rrn[2] = {st[2], st[3]};
+        if (a.coupled) {
+            rzn[0] = rzn[1] = st[0] + st[1];
+            rrn[0] = rrn[1] = st[2] + st[3];
+        }
+        for (int c = 0; c < 2; ++c) {
+            if (done[c]) continue;
+            rrc[c] = rrn[c];
+            beta[c] = rzn[c] / rz[c];
+            rz[c] = rzn[c];
+            if (rrn[c] <= tgt[c] || !(rzn[c] > 0.0)) done[c] = true;
+        }
+        if (a.coupled) done[1] = done[0];
+        V2* t = pold;
+        pold = pnew;
+        pnew = t;
+        ++it;
+    }
+    if (wg == wg0 && threadIdx.x == 0) {
+        a.iters[sub] = it;
+        a.status[sub] = stat;
+        a.rr_out[2 * sub] = rr0[0] > 0.0 ? rrc[0] / rr0[0] : 0.0;
+        a.rr_out[2 * sub + 1] = rr0[1] > 0.0 ? rrc[1] / rr0[1] : 0.0;
+    }
+}
+
+// ----------------------------------------------------------------- DNCP / harmonic set-up and gathers
+
+__global__ void k_init_dncp(int K, const int32_t* __restrict__ pin_row, const double* __restrict__ pin_x1,
+                            double2* __restrict__ u) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K) return;
+    u[pin_row[2 * i]] = make_double2(0.0, 0.0);
+    u[pin_row[2 * i + 1]] = make_double2(pin_x1[i], 0.0);
+}
+
+__device__ __forceinline__ double2 chart_fwd(double2 z, double2 c, int cinf) {
+    // w = (z - c) / (1 + conj(c) z); infinity -> 1/conj(c)
+    if (isinf(z.x) || isinf(z.y)) {
+        double d = c.x * c.x + c.y * c.y;
+        return make_double2(c.x / d, c.y / d);
+    }
+    if (cinf) {   // chart centred at infinity: w = -1/z
+        double d = z.x * z.x + z.y * z.y;
+        return make_double2(-z.x / d, z.y / d);
+    }
+    double nx = z.x - c.x, ny = z.y - c.y;
+    double dx = 1.0 + (c.x * z.x + c.y * z.y), dy = c.x * z.y - c.y * z.x;
+    double d = dx * dx + dy * dy;
+    return make_double2((nx * dx + ny * dy) / d, (ny * dx - nx * dy) / d);
+}
+
+__device__ __forceinline__ double2 chart_inv(double2 w, double2 c, int cinf, bool* isinfz) {
+    // z = (w + c) / (1 - conj(c) w)
+    *isinfz = false;
+    if (cinf) {
+        double d = w.x * w.x + w.y * w.y;
+        if (d == 0.0) {
+            *isinfz = true;
+            return w;
+        }
+        return make_double2(-w.x / d, w.y / d);
+    }
+    double nx = w.x + c.x, ny = w.y + c.y;
+    double dx = 1.0 - (c.x * w.x + c.y * w.y), dy = -(c.x * w.y - c.y * w.x);
+    double d = dx * dx + dy * dy;
+    if (d == 0.0) {
+        *isinfz = true;
+        return w;
+    }
+    return make_double2((nx * dx + ny * dy) / d, (ny * dx - nx * dy) / d);
+}
+
+__device__ __forceinline__ void inv_stereo(double2 z, bool zinf, double* out) {
+    if (zinf || isinf(z.x) || isinf(z.y)) {
+        out[0] = 0.0;
+        out[1] = 0.0;
+        out[2] = 1.0;
+        return;
+    }
+    double r2 = z.x * z.x + z.y * z.y, den = r2 + 1.0;
+    out[0] = 2.0 * z.x / den;
+    out[1] = -2.0 * z.y / den;
+    out[2] = (r2 - 1.0) / den;
+}
+
+// u = welded values (in the piece's chart for the sphere) on loop rows, 0 elsewhere.
+__global__ void __launch_bounds__(BLOCK) k_init_harm(int64_t nbdy, int K, const int32_t* __restrict__ loop_ptr,
+                                                      const int32_t* __restrict__ loop_row,
+                                                      const int32_t* __restrict__ loop_seam,
+                                                      const int32_t* __restrict__ slice_sub,
+                                                      const double2* __restrict__ welded,
+                                                      const double* __restrict__ chart, int sphere,
+                                                      double2* __restrict__ u) {
+    int64_t e = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (e >= nbdy) return;
+    int r = loop_row[e];
+    double2 v = welded[loop_seam[e]];
+    if (sphere) {
+        int i = slice_sub[r >> 6];
+        v = chart_fwd(v, make_double2(chart[3 * i], chart[3 * i + 1]), (int)chart[3 * i + 2]);
+    }
+    u[r] = v;
+}
+
+// One block per piece: translate so the loop mean is 0 and gather the loop.
+__global__ void __launch_bounds__(BLOCK) k_dncp_bdy(const int32_t* __restrict__ loop_ptr,
+                                                     const int32_t* __restrict__ loop_row,
+                                                     const double2* __restrict__ u, double* __restrict__ bdy) {
+    __shared__ double lds[32];
+    int i = blockIdx.x;
+    int e0 = loop_ptr[i], e1 = loop_ptr[i + 1];
+    double v[2] = {0.0, 0.0};
+    for (int e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        double2 x = u[loop_row[e]];
+        v[0] += x.x;
+        v[1] += x.y;
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        lds[20] = v[0] / (double)(e1 - e0);
+        lds[21] = v[1] / (double)(e1 - e0);
+    }
+    __syncthreads();
+    double mx = lds[20], my = lds[21];
+    for (int e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        double2 x = u[loop_row[e]];
+        bdy[2 * (int64_t)e] = x.x - mx;
+        bdy[2 * (int64_t)e + 1] = x.y - my;
+    }
+}
+
+// Interior rows write their own value; seam vertices come from the weld.
+__global__ void __launch_bounds__(BLOCK) k_harm_out(int64_t N, const uint8_t* __restrict__ row_kind,
+                                                     const int32_t* __restrict__ row_gv,
+                                                     const int32_t* __restrict__ slice_sub,
+                                                     const double2* __restrict__ u, const double* __restrict__ chart,
+                                                     int sphere, double* __restrict__ out) {
+    int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= N || row_kind[r] != 0) return;
+    int64_t g = row_gv[r];
+    double2 w = u[r];
+    if (sphere) {
+        int i = slice_sub[r >> 6];
+        bool zi;
+        double2 z = chart_inv(w, make_double2(chart[3 * i], chart[3 * i + 1]), (int)chart[3 * i + 2], &zi);
+        inv_stereo(z, zi, out + 3 * g);
+    } else {
+        out[2 * g] = w.x;
+        out[2 * g + 1] = w.y;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_seam_out(int64_t nseam, const int32_t* __restrict__ seam_gv,
+                                                     const double2* __restrict__ welded, int sphere,
+                                                     double* __restrict__ out) {
+    int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (s >= nseam) return;
+    int64_t g = seam_gv[s];
+    double2 w = welded[s];
+    if (sphere) {
+        inv_stereo(w, false, out + 3 * g);
+    } else {
+        out[2 * g] = w.x;
+        out[2 * g + 1] = w.y;
+    }
+}
+
+// ----------------------------------------------------------------- distortion
+
+__device__ __forceinline__ double angle3(double ux, double uy, double uz, double vx, double vy, double vz) {
+    double cx = uy * vz - uz * vy, cy = uz * vx - ux * vz, cz = ux * vy - uy * vx;
+    return atan2(sqrt(cx * cx + cy * cy + cz * cz), ux * vx + uy * vy + uz * vz);
+}
+
+struct DistPart {
+    double sum, sum2, maxd, maxmu;
+    double nflip, nmu1, pad0, pad1;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_distortion(int64_t nf, const double* __restrict__ V,
+                                                       const int32_t* __restrict__ F, const double* __restrict__ X,
+                                                       int dim, double* __restrict__ dout, double* __restrict__ muout,
+                                                       uint8_t* __restrict__ flipout, DistPart* __restrict__ part) {
+    __shared__ double lds[WAVES * 6 + 32];
+    int64_t f = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    double s = 0.0, s2 = 0.0, mx = 0.0, mmu = 0.0, nfl = 0.0, nmu = 0.0;
+    if (f < nf) {
+        int id[3] = {F[3 * f], F[3 * f + 1], F[3 * f + 2]};
+        double P[3][3], Q[3][3];
+        for (int c = 0; c < 3; ++c) {
+            for (int t = 0; t < 3; ++t) P[c][t] = V[3 * (int64_t)id[c] + t];
+            Q[c][0] = X[(int64_t)dim * id[c]];
+            Q[c][1] = X[(int64_t)dim * id[c] + 1];
+            Q[c][2] = dim == 3 ? X[(int64_t)dim * id[c] + 2] : 0.0;
+        }
+        const double rad2deg = 57.29577951308232;
+        for (int c = 0; c < 3; ++c) {
+            int i1 = (c + 1) % 3, i2 = (c + 2) % 3;
+            double as = angle3(P[i1][0] - P[c][0], P[i1][1] - P[c][1], P[i1][2] - P[c][2], P[i2][0] - P[c][0],
+                               P[i2][1] - P[c][1], P[i2][2] - P[c][2]);
+            double ap = angle3(Q[i1][0] - Q[c][0], Q[i1][1] - Q[c][1], Q[i1][2] - Q[c][2], Q[i2][0] - Q[c][0],
+                               Q[i2][1] - Q[c][1], Q[i2][2] - Q[c][2]);
+            double d = (ap - as) * rad2deg;
+            if (dout) dout[3 * f + c] = d;
+            double ad = fabs(d);
+            s += ad;
+            s2 += ad * ad;
+            mx = fmax(mx, ad);
+        }
+        // orientation
+        double ori;
+        if (dim == 2) {
+            ori = (Q[1][0] - Q[0][0]) * (Q[2][1] - Q[0][1]) - (Q[1][1] - Q[0][1]) * (Q[2][0] - Q[0][0]);
+        } else {
+            ori = Q[0][0] * (Q[1][1] * Q[2][2] - Q[1][2] * Q[2][1]) - Q[0][1] * (Q[1][0] * Q[2][2] - Q[1][2] * Q[2][0]) +
+                  Q[0][2] * (Q[1][0] * Q[2][1] - Q[1][1] * Q[2][0]);
+        }
+        bool flip = !(ori > 0.0);
+        // Beltrami coefficient between isometric frames: source (0, l1, x3 + i y3)
+        double e1[3], e2[3];
+        for (int t = 0; t < 3; ++t) {
+            e1[t] = P[1][t] - P[0][t];
+            e2[t] = P[2][t] - P[0][t];
+        }
+        double l1 = sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        double x3 = (e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2]) / l1;
+        double py[3];
+        for (int t = 0; t < 3; ++t) py[t] = e2[t] - x3 * e1[t] / l1;
+        double y3 = sqrt(py[0] * py[0] + py[1] * py[1] + py[2] * py[2]);
+        double w2x, w2y, w3x, w3y;
+        if (dim == 2) {
+            w2x = Q[1][0] - Q[0][0];
+            w2y = Q[1][1] - Q[0][1];
+            w3x = Q[2][0] - Q[0][0];
+            w3y = Q[2][1] - Q[0][1];
+        } else {
+            double f1[3], f2[3];
+            for (int t = 0; t < 3; ++t) {
+                f1[t] = Q[1][t] - Q[0][t];
+                f2[t] = Q[2][t] - Q[0][t];
+            }
+            double m1 = sqrt(f1[0] * f1[0] + f1[1] * f1[1] + f1[2] * f1[2]);
+            double xx = (f1[0] * f2[0] + f1[1] * f2[1] + f1[2] * f2[2]) / m1;
+            double qq[3];
+            for (int t = 0; t < 3; ++t) qq[t] = f2[t] - xx * f1[t] / m1;
+            double yy = sqrt(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2]);
+            w2x = m1;
+            w2y = 0.0;
+            w3x = xx;
+            w3y = ori > 0.0 ? yy : -yy;
+        }
+        // f(z) = a z + b conj(z); e1 = l1, e2 = x3 + i y3; d1 = w2, d2 = w3
+        // det = e1 conj(e2) - e2 conj(e1) = -2 i l1 y3
+        // a = (d1 conj(e2) - d2 conj(e1)) / det, b = (e1 d2 - e2 d1) / det
+        double anx = w2x * x3 + w2y * y3 - w3x * l1, any = w2y * x3 - w2x * y3 - w3y * l1;
+        double bnx = l1 * w3x - (x3 * w2x - y3 * w2y), bny = l1 * w3y - (x3 * w2y + y3 * w2x);
+        double mu = sqrt((bnx * bnx + bny * bny) / (anx * anx + any * any));
+        if (muout) muout[f] = mu;
+        if (flipout) flipout[f] = flip ? 1 : 0;
+        mmu = mu;
+        nfl = flip ? 1.0 : 0.0;
+        nmu = (mu >= 1.0 - 1e-8) ? 1.0 : 0.0;
+    }
+    // block reduction (fixed order)
+    double v[6] = {s, s2, mx, mmu, nfl, nmu};
+    for (int o = 32; o >= 1; o >>= 1) {
+        v[0] += __shfl_xor(v[0], o, 64);
+        v[1] += __shfl_xor(v[1], o, 64);
+        v[2] = fmax(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = fmax(v[3], __shfl_xor(v[3], o, 64));
+        v[4] += __shfl_xor(v[4], o, 64);
+        v[5] += __shfl_xor(v[5], o, 64);
+    }
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int i = 0; i < 6; ++i) lds[wave * 6 + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DistPart p{0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < WAVES; ++w) {
+            p.sum += lds[w * 6];
+            p.sum2 += lds[w * 6 + 1];
+            p.maxd = fmax(p.maxd, lds[w * 6 + 2]);
+            p.maxmu = fmax(p.maxmu, lds[w * 6 + 3]);
+            p.nflip += lds[w * 6 + 4];
+            p.nmu1 += lds[w * 6 + 5];
+        }
+        part[blockIdx.x] = p;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_dist_final(int64_t nblk, const DistPart* __restrict__ part,
+                                                       DistPart* __restrict__ out) {
+    __shared__ double lds[WAVES * 6 + 32];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nblk; b += BLOCK) {
+        DistPart p = part[b];
+        v[0] += p.sum;
+        v[1] += p.sum2;
+        v[2] = fmax(v[2], p.maxd);
+        v[3] = fmax(v[3], p.maxmu);
+        v[4] += p.nflip;
+        v[5] += p.nmu1;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        v[0] += __shfl_xor(v[0], o, 64);
+        v[1] += __shfl_xor(v[1], o, 64);
+        v[2] = fmax(v[2], __shfl_xor(v[2], o, 64));
+        v[3] = fmax(v[3], __shfl_xor(v[3], o, 64));
+        v[4] += __shfl_xor(v[4], o, 64);
+        v[5] += __shfl_xor(v[5], o, 64);
+    }
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int i = 0; i < 6; ++i) lds[wave * 6 + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        DistPart p{0, 0, 0, 0, 0, 0, 0, 0};
+        for (int w = 0; w < WAVES; ++w) {
+            p.sum += lds[w * 6];
+            p.sum2 += lds[w * 6 + 1];
+            p.maxd = fmax(p.maxd, lds[w * 6 + 2]);
+            p.maxmu = fmax(p.maxmu, lds[w * 6 + 3]);
+            p.nflip += lds[w * 6 + 4];
+            p.nmu1 += lds[w * 6 + 5];
+        }
+        *out = p;
+    }
+}
+
+__global__ void __launch_bounds__(BLOCK) k_absd(int64_t n, const double* __restrict__ d, double* __restrict__ o) {
+    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n) o[i] = fabs(d[i]);
+}
+
+__global__ void k_zero_u32(int64_t n, unsigned* p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_zero_d2(int64_t n, double2* p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_double2(0.0, 0.0);
+}
+
+// ----------------------------------------------------------------- host side: launches
+
+static inline unsigned grid_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
+
+Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemsetAsync(P->d_flags.p, 0, 4, s));
+    k_assemble<<<grid_for(P->N), BLOCK, 0, s>>>(P->nslices, (const int64_t*)P->d_sl_ptr.p,
+                                                 (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
+                                                 (const int32_t*)P->d_sl_opp.p, (const int32_t*)P->d_row_gv.p, V,
+                                                 (double*)P->d_val64.p, (float*)P->d_val32.p,
+                                                 (double*)P->d_diag64.p, (float*)P->d_diag32.p,
+                                                 (int*)P->d_flags.p);
+    HIPCHK(hipGetLastError());
+    P->assembled = true;
+    return Error{PGCP_OK, ""};
+}
+
+template <typename T, int R>
+static const void* pcg_kernel_ptr() {
+    return reinterpret_cast<const void*>(&k_pcg<T, R>);
+}
+
+template <typename T>
+static const void* pcg_kernel(int R) {
+    switch (R) {
+        case 1: return pcg_kernel_ptr<T, 1>();
+        case 2: return pcg_kernel_ptr<T, 2>();
+        case 4: return pcg_kernel_ptr<T, 4>();
+        case 8: return pcg_kernel_ptr<T, 8>();
+        default: return pcg_kernel_ptr<T, 16>();
+    }
+}
+
+// Build (or reuse) the workgroup map for precision prec (0 double, 1 float):
+// the smallest rows-per-thread R whose grid fits the co-resident capacity.
+static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec) {
+    if (P->wmap_prec == prec) return Error{PGCP_OK, ""};
+    int dev = ctx->device;
+    int n_cu = 0;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    int coop = 0;
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return Error{PGCP_E_HIP, "device does not support cooperative launches"};
+    WorkMap& W = P->wmap;
+    for (int R : {1, 2, 4, 8, 16}) {
+        int per_cu = 0;
+        const void* kern = prec == 0 ? pcg_kernel<double>(R) : pcg_kernel<float>(R);
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
+        int64_t cap = (int64_t)per_cu * n_cu;
+        int64_t slices_per_wg = (int64_t)WAVES * R;
+        int64_t G = 0;
+        for (int i = 0; i < P->K; ++i) {
+            int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            G += std::max<int64_t>(1, (ns + slices_per_wg - 1) / slices_per_wg);
+        }
+        if (G > cap && R < 16) continue;
+        if (G > cap) return Error{PGCP_E_INVALID, "problem too large for one cooperative launch"};
+        W.rows_per_thread = R;
+        W.n_wg = (int)G;
+        W.wg_sub.clear();
+        W.wg_s0.clear();
+        W.wg_s1.clear();
+        W.sub_wg0.assign(P->K, 0);
+        W.sub_nwg.assign(P->K, 0);
+        for (int i = 0; i < P->K; ++i) {
+            int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            int64_t nw = std::max<int64_t>(1, (ns + slices_per_wg - 1) / slices_per_wg);
+            W.sub_wg0[i] = (int32_t)W.wg_sub.size();
+            W.sub_nwg[i] = (int32_t)nw;
+            for (int64_t t = 0; t < nw; ++t) {
+                W.wg_sub.push_back(i);
+                W.wg_s0.push_back((int32_t)(sb + ns * t / nw));
+                W.wg_s1.push_back((int32_t)(sb + ns * (t + 1) / nw));
+            }
+        }
+        Error e{PGCP_OK, ""};
+        if ((e = upload(W.d_wg_sub, W.wg_sub, ctx->stream)).code) return e;
+        if ((e = upload(W.d_wg_s0, W.wg_s0, ctx->stream)).code) return e;
+        if ((e = upload(W.d_wg_s1, W.wg_s1, ctx->stream)).code) return e;
+        if ((e = upload(W.d_sub_wg0, W.sub_wg0, ctx->stream)).code) return e;
+        if ((e = upload(W.d_sub_nwg, W.sub_nwg, ctx->stream)).code) return e;
+        size_t need = (size_t)G * 8 * 8;
+        if (P->d_partial.bytes < need)
+            if ((e = dev_alloc(P->d_partial, need)).code) return e;
+        P->wmap_prec = prec;
+        return Error{PGCP_OK, ""};
+    }
+    return Error{PGCP_E_INVALID, "no work map"};
+}
+
+// Iterative refinement driver.  u64 holds the Dirichlet values on masked rows
+// and the current iterate elsewhere; solves A u = 0 on the free rows of every
+// piece to ||r||_2 <= tol ||b||_2 (per coordinate unless coupled), where
+// b = -A_FD u_D is the first residual (u_F = 0 on entry).  Each pass evaluates
+// the FP64 residual, then runs one batched PCG (FP64, or FP32 on the scaled
+// residual) on the pieces that have not converged, and adds its correction.
+static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_t* mask,
+                          const pgcp_solve_opts* o, pgcp_solve_stats* st) {
+    hipStream_t s = ctx->stream;
+    const int K = P->K;
+    const int prec = (o && o->precision == PGCP_FP32_REFINE) ? 1 : 0;
+    const double tol = (o && o->tol > 0) ? o->tol : 1e-10;
+    const double inner_tol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
+    const int max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
+    const int max_refine = (o && o->max_refine > 0) ? o->max_refine : 30;
+    Error e = build_workmap(ctx, P, prec);
+    if (e.code) return e;
+    const WorkMap& W = P->wmap;
+    const int R = W.rows_per_thread;
+
+    std::vector<double> bnorm(2 * K, 0.0), rnorm(2 * K, 0.0), scale(2 * K, 0.0), target(2 * K, 0.0);
+    std::vector<int32_t> active(K, 0), iters(K, 0), status(K, 0), it_total(K, 0), fail(K, 0);
+    std::vector<double> relres(2 * K, 0.0);
+    int steps = 0;
+    int64_t total = 0;
+    bool all_conv = false;
+    double cg_ms = 0.0, cg_bytes = 0.0;
+    int cg_launches = 0;
+    if (!P->ev0) {
+        HIPCHK(hipEventCreate(&P->ev0));
+        HIPCHK(hipEventCreate(&P->ev1));
+    }
+    // algorithmic bytes of one CG iteration of piece i: matrix values + column
+    // indices once, and per row z, p_old read, p_new written (phase A), e and r
+    // read+written, z written (phase B), the diagonal twice and the mask twice.
+    const double tsz = prec ? 4.0 : 8.0;
+    auto iter_bytes = [&](int i) {
+        return (double)P->sub_nnz[i] * (tsz + 4.0) + (double)P->sub_nv[i] * (8.0 * 2.0 * tsz + 2.0 * tsz + 2.0);
+    };
+    for (int outer = 0; outer < max_refine; ++outer) {
+        k_residual64<<<grid_for(P->N), BLOCK, 0, s>>>(
+            P->nslices, (const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
+            (const double*)P->d_val64.p, (const double*)P->d_diag64.p, (const int32_t*)P->d_row_prev.p,
+            (const int32_t*)P->d_row_next.p, coupled, mask, (const double2*)P->d_u64.p, (double2*)P->d_r64.p,
+            (double*)P->d_slicepart.p);
+        HIPCHK(hipGetLastError());
+        k_piece_sum<<<K, BLOCK, 0, s>>>((const int32_t*)P->d_row0.p, (const double*)P->d_slicepart.p,
+                                        (double*)P->d_rnorm.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(rnorm.data(), P->d_rnorm.p, 2 * K * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        steps++;
+        if (outer == 0) bnorm = rnorm;
+        int n_active = 0;
+        for (int i = 0; i < K; ++i) {
+            double rel[2];
+            if (coupled) {
+                double b = bnorm[2 * i] + bnorm[2 * i + 1], r = rnorm[2 * i] + rnorm[2 * i + 1];
+                rel[0] = rel[1] = b > 0 ? std::sqrt(r / b) : (r > 0 ? INFINITY : 0.0);
+            } else {
+                for (int c = 0; c < 2; ++c) {
+                    double b = bnorm[2 * i + c], r = rnorm[2 * i + c];
+                    rel[c] = b > 0 ? std::sqrt(r / b) : (r > 0 ? INFINITY : 0.0);
+                }
+            }
+            relres[2 * i] = rel[0];
+            relres[2 * i + 1] = rel[1];
+            bool conv = rel[0] <= tol && rel[1] <= tol;
+            active[i] = (!conv && !fail[i]) ? 1 : 0;
+            n_active += active[i];
+            for (int c = 0; c < 2; ++c) {
+                double r = coupled ? rnorm[2 * i] + rnorm[2 * i + 1] : rnorm[2 * i + c];
+                scale[2 * i + c] = prec ? std::sqrt(r) : 1.0;
+                // inner target: reach tol with margin; FP32 stops at inner_tol
+                double need = rel[c] > 0 ? 0.25 * (tol / rel[c]) * (tol / rel[c]) : 1.0;
+                if (coupled && c == 1) need = target[2 * i];
+                if (prec) need = std::max(need, inner_tol * inner_tol);
+                target[2 * i + c] = std::min(need, 1.0);
+            }
+        }
+        if (n_active == 0) {
+            all_conv = true;
+            break;
+        }
+        if (outer == max_refine - 1) break;
+        HIPCHK(hipMemcpyAsync(P->d_active.p, active.data(), K * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P->d_scale.p, scale.data(), 2 * K * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(P->d_target.p, target.data(), 2 * K * 8, hipMemcpyHostToDevice, s));
+        k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_bar.p);
+        k_zero_u32<<<1, 64, 0, s>>>(16, (unsigned*)P->d_abort.p);
+        HIPCHK(hipGetLastError());
+        if (prec) {
+            k_prep_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                                  (const double2*)P->d_r64.p,
+                                                                  (const double*)P->d_scale.p, (float2*)P->d_r.p,
+                                                                  (float2*)P->d_e.p);
+        } else {
+            k_prep_inner<double><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                                   (const double2*)P->d_r64.p,
+                                                                   (const double*)P->d_scale.p, (double2*)P->d_r.p,
+                                                                   (double2*)P->d_e.p);
+        }
+        HIPCHK(hipGetLastError());
+        dim3 grid(W.n_wg), block(BLOCK);
+        if (prec) {
+            CGArgs<float> a{(const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
+                            (const float*)P->d_val32.p, (const float*)P->d_diag32.p,
+                            (const int32_t*)P->d_row_prev.p, (const int32_t*)P->d_row_next.p, mask,
+                            (const int32_t*)W.d_wg_sub.p, (const int32_t*)W.d_wg_s0.p, (const int32_t*)W.d_wg_s1.p,
+                            (const int32_t*)W.d_sub_wg0.p, (const int32_t*)W.d_sub_nwg.p,
+                            (const int32_t*)P->d_active.p, (const double*)P->d_target.p, (float2*)P->d_e.p,
+                            (float2*)P->d_r.p, (float2*)P->d_z.p, (float2*)P->d_p0.p, (float2*)P->d_p1.p,
+                            (double*)P->d_partial.p, (unsigned*)P->d_bar.p, (int*)P->d_abort.p,
+                            (int32_t*)P->d_iters.p, (double*)P->d_rrout.p, (int32_t*)P->d_status.p, coupled,
+                            max_iter};
+            void* args[] = {&a};
+            HIPCHK(hipEventRecord(P->ev0, s));
+            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(R), grid, block, args, 0, s));
+            HIPCHK(hipEventRecord(P->ev1, s));
+        } else {
+            CGArgs<double> a{(const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
+                             (const double*)P->d_val64.p, (const double*)P->d_diag64.p,
+                             (const int32_t*)P->d_row_prev.p, (const int32_t*)P->d_row_next.p, mask,
+                             (const int32_t*)W.d_wg_sub.p, (const int32_t*)W.d_wg_s0.p, (const int32_t*)W.d_wg_s1.p,
+                             (const int32_t*)W.d_sub_wg0.p, (const int32_t*)W.d_sub_nwg.p,
+                             (const int32_t*)P->d_active.p, (const double*)P->d_target.p, (double2*)P->d_e.p,
+                             (double2*)P->d_r.p, (double2*)P->d_z.p, (double2*)P->d_p0.p, (double2*)P->d_p1.p,
+                             (double*)P->d_partial.p, (unsigned*)P->d_bar.p, (int*)P->d_abort.p,
+                             (int32_t*)P->d_iters.p, (double*)P->d_rrout.p, (int32_t*)P->d_status.p, coupled,
+                             max_iter};
+            void* args[] = {&a};
+            HIPCHK(hipEventRecord(P->ev0, s));
+            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(R), grid, block, args, 0, s));
+            HIPCHK(hipEventRecord(P->ev1, s));
+        }
+        if (prec) {
+            k_apply_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                                   (const int32_t*)P->d_active.p,
+                                                                   (const double*)P->d_scale.p,
+                                                                   (const float2*)P->d_e.p, (double2*)P->d_u64.p);
+        } else {
+            k_apply_inner<double><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                                    (const int32_t*)P->d_active.p,
+                                                                    (const double*)P->d_scale.p,
+                                                                    (const double2*)P->d_e.p, (double2*)P->d_u64.p);
+        }
+        HIPCHK(hipGetLastError());
+        int abort_flag = 0;
+        HIPCHK(hipMemcpyAsync(&abort_flag, P->d_abort.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(iters.data(), P->d_iters.p, K * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(status.data(), P->d_status.p, K * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (abort_flag) return Error{PGCP_E_HIP, "batched CG barrier timed out"};
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P->ev0, P->ev1));
+        cg_ms += ms;
+        cg_launches++;
+        for (int i = 0; i < K; ++i) {
+            if (!active[i]) continue;
+            it_total[i] += iters[i];
+            total += iters[i];
+            cg_bytes += iters[i] * iter_bytes(i);
+            if (status[i] == 1 && iters[i] == 0) fail[i] = 1;   // breakdown before any progress
+        }
+    }
+    bool noconv = false;
+    for (int i = 0; i < K; ++i) {
+        bool conv = relres[2 * i] <= tol && relres[2 * i + 1] <= tol;
+        if (!conv) noconv = true;
+        if (st) {
+            if (st->iters) st->iters[i] = it_total[i];
+            if (st->relres) {
+                st->relres[2 * i] = relres[2 * i];
+                st->relres[2 * i + 1] = relres[2 * i + 1];
+            }
+            if (st->status) st->status[i] = conv ? 0 : (fail[i] ? PGCP_E_BREAKDOWN : PGCP_E_NOCONV);
+        }
+    }
+    (void)all_conv;
+    if (st) {
+        st->n_sub = K;
+        st->refine_steps = steps;
+        st->total_iters = total;
+        st->cg_kernel_ms = cg_ms;
+        st->cg_bytes = cg_bytes;
+        st->cg_launches = cg_launches;
+        st->rows_per_thread = R;
+        st->cg_workgroups = W.n_wg;
+    }
+    if (noconv) return Error{PGCP_E_NOCONV, "some piece missed the residual tolerance"};
+    return Error{PGCP_OK, ""};
+}
+
+Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, double* bdy,
+                      pgcp_solve_stats* st) {
+    if (!P->assembled) return Error{PGCP_E_INVALID, "pgcp_assemble_cotan has not run"};
+    hipStream_t s = ctx->stream;
+    k_zero_d2<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (double2*)P->d_u64.p);
+    k_init_dncp<<<grid_for(P->K), BLOCK, 0, s>>>(P->K, (const int32_t*)P->d_pin_row.p,
+                                                  (const double*)P->d_pin_x1.p, (double2*)P->d_u64.p);
+    HIPCHK(hipGetLastError());
+    Error e = refine_solve(ctx, P, 1, (const uint8_t*)P->d_mask_dncp.p, o, st);
+    if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
+    k_dncp_bdy<<<P->K, BLOCK, 0, s>>>((const int32_t*)P->d_loop_ptr.p, (const int32_t*)P->d_loop_row.p,
+                                       (const double2*)P->d_u64.p, bdy);
+    HIPCHK(hipGetLastError());
+    return e;
+}
+
+Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp_solve_opts* o, double* out,
+                   pgcp_solve_stats* st) {
+    if (!P->assembled) return Error{PGCP_E_INVALID, "pgcp_assemble_cotan has not run"};
+    if (P->mode == PGCP_SPHERE && !P->welded) return Error{PGCP_E_INVALID, "sphere mode needs pgcp_weld first"};
+    hipStream_t s = ctx->stream;
+    const int sphere = P->mode == PGCP_SPHERE;
+    if (sphere) {
+        std::vector<double> ch(3 * P->K);
+        for (int i = 0; i < P->K; ++i) {
+            ch[3 * i] = P->chart[i].real();
+            ch[3 * i + 1] = P->chart[i].imag();
+            ch[3 * i + 2] = P->chart_inf[i];
+        }
+        Error e = upload(P->d_chart, ch, s);
+        if (e.code) return e;
+    }
+    k_zero_d2<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (double2*)P->d_u64.p);
+    k_init_harm<<<grid_for(P->n_bdy), BLOCK, 0, s>>>(P->n_bdy, P->K, (const int32_t*)P->d_loop_ptr.p,
+                                                      (const int32_t*)P->d_loop_row.p,
+                                                      (const int32_t*)P->d_loop_seam.p,
+                                                      (const int32_t*)P->d_slice_sub.p, (const double2*)welded,
+                                                      (const double*)P->d_chart.p, sphere, (double2*)P->d_u64.p);
+    HIPCHK(hipGetLastError());
+    Error e = refine_solve(ctx, P, 0, (const uint8_t*)P->d_mask_harm.p, o, st);
+    if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
+    k_harm_out<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p, (const int32_t*)P->d_row_gv.p,
+                                                 (const int32_t*)P->d_slice_sub.p, (const double2*)P->d_u64.p,
+                                                 (const double*)P->d_chart.p, sphere, out);
+    k_seam_out<<<grid_for(P->n_seam), BLOCK, 0, s>>>(P->n_seam, (const int32_t*)P->d_seam_gv.p,
+                                                      (const double2*)welded, sphere, out);
+    HIPCHK(hipGetLastError());
+    return e;
+}
+
+// Distortion check.  Scratch buffers live in the context-independent statics
+// of this call (allocated per call size).
+Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, const double* X,
+                     int dim, double* d, double* mu, uint8_t* flip, int want_q, pgcp_dist_stats* st) {
+    (void)nv;
+    hipStream_t s = ctx->stream;
+    const int64_t nblk = (nf + BLOCK - 1) / BLOCK;
+    DevBuf part, fin, dtmp, abs_d, sorted, cubtmp;
+    Error e{PGCP_OK, ""};
+    if ((e = dev_alloc(part, nblk * sizeof(DistPart))).code) return e;
+    if ((e = dev_alloc(fin, sizeof(DistPart))).code) return e;
+    double* dd = d;
+    if (want_q && !dd) {
+        if ((e = dev_alloc(dtmp, nf * 3 * 8)).code) return e;
+        dd = (double*)dtmp.p;
+    }
+    k_distortion<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, V, F, X, dim, dd, mu, flip, (DistPart*)part.p);
+    HIPCHK(hipGetLastError());
+    k_dist_final<<<1, BLOCK, 0, s>>>(nblk, (const DistPart*)part.p, (DistPart*)fin.p);
+    HIPCHK(hipGetLastError());
+    double med = NAN, iqr = NAN;
+    if (want_q) {
+        const int64_t n = 3 * nf;
+        if ((e = dev_alloc(abs_d, n * 8)).code) return e;
+        if ((e = dev_alloc(sorted, n * 8)).code) return e;
+        k_absd<<<grid_for(n), BLOCK, 0, s>>>(n, dd, (double*)abs_d.p);
+        size_t tmp_bytes = 0;
+        HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, (const double*)abs_d.p, (double*)sorted.p,
+                                                 (int)n, 0, 64, s));
+        if ((e = dev_alloc(cubtmp, tmp_bytes)).code) return e;
+        HIPCHK(hipcub::DeviceRadixSort::SortKeys(cubtmp.p, tmp_bytes, (const double*)abs_d.p, (double*)sorted.p,
+                                                 (int)n, 0, 64, s));
+        // midpoint-rule percentiles: position q*n + 1/2 (1-based), linear between neighbours
+        auto pct = [&](double q, double* out) -> Error {
+            double pos = q * (double)n + 0.5;
+            int64_t lo = (int64_t)std::floor(pos);
+            double t = pos - (double)lo;
+            double v[2];
+            int64_t i0 = std::min<int64_t>(std::max<int64_t>(lo, 1), n) - 1;
+            int64_t i1 = std::min<int64_t>(std::max<int64_t>(lo + 1, 1), n) - 1;
+            HIPCHK(hipMemcpyAsync(&v[0], (double*)sorted.p + i0, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&v[1], (double*)sorted.p + i1, 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (pos <= 1.0) *out = v[0];
+            else if (pos >= (double)n) *out = v[1];
+            else *out = v[0] + t * (v[1] - v[0]);
+            return Error{PGCP_OK, ""};
+        };
+        double p25, p50, p75;
+        if ((e = pct(0.25, &p25)).code) return e;
+        if ((e = pct(0.50, &p50)).code) return e;
+        if ((e = pct(0.75, &p75)).code) return e;
+        med = p50;
+        iqr = p75 - p25;
+    }
+    if (st) {
+        DistPart h;
+        HIPCHK(hipMemcpyAsync(&h, fin.p, sizeof(DistPart), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double n = 3.0 * (double)nf;
+        st->mean_abs_d = h.sum / n;
+        st->sd_abs_d = n > 1 ? std::sqrt(std::max(0.0, (h.sum2 - h.sum * h.sum / n) / (n - 1.0))) : 0.0;
+        st->max_abs_d = h.maxd;
+        st->median_abs_d = med;
+        st->iqr_abs_d = iqr;
+        st->max_mu = h.maxmu;
+        st->n_flipped = (int64_t)llround(h.nflip);
+        st->n_mu_ge1 = (int64_t)llround(h.nmu1);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    dev_free(part);
+    dev_free(fin);
+    dev_free(dtmp);
+    dev_free(abs_d);
+    dev_free(sorted);
+    dev_free(cubtmp);
+    return Error{PGCP_OK, ""};
+}
+
+Error assembled_ok(pgcp_ctx* ctx, pgcp_part* P) {
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, P->d_flags.p, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (bad) return Error{PGCP_E_DEGENERATE, "zero-area triangle in assembly"};
+    return Error{PGCP_OK, ""};
+}
+
+}  // namespace pgcp
+
+namespace pgcp {
+
+// Copy one piece's FP64 matrix back to host CSR (local indices, diagonal included).
+Error export_laplacian(pgcp_ctx* ctx, const pgcp_part* P, int piece, int32_t* rowptr, int32_t* col, double* val) {
+    const int32_t r0 = P->row0[piece];
+    const int32_t n = P->sub_nv[piece];
+    const int64_t s0 = r0 / 64, s1 = (r0 + (int64_t)n + 63) / 64;
+    const int64_t e0 = P->sl_ptr[s0], e1 = P->sl_ptr[s1];
+    std::vector<double> v(e1 - e0), dg(n);
+    HIPCHK(hipMemcpyAsync(v.data(), (const double*)P->d_val64.p + e0, (e1 - e0) * 8, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(dg.data(), (const double*)P->d_diag64.p + r0, (size_t)n * 8, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    rowptr[0] = 0;
+    for (int32_t l = 0; l < n; ++l) {
+        const int64_t r = r0 + l, s = r / 64;
+        const int lane = (int)(r & 63);
+        std::vector<std::pair<int32_t, double>> ent;
+        ent.emplace_back(l, dg[l]);
+        for (int k = 0; k < P->sl_w[s]; ++k) {
+            const int64_t el = P->sl_ptr[s] + (int64_t)k * 64 + lane;
+            const int32_t c = P->sl_col[el];
+            if (c == r) continue;   // padding slot
+            ent.emplace_back(c - r0, v[el - e0]);
+        }
+        std::sort(ent.begin(), ent.end());
+        rowptr[l + 1] = rowptr[l] + (int32_t)ent.size();
+        if (col && val) {
+            for (size_t t = 0; t < ent.size(); ++t) {
+                col[rowptr[l] + t] = ent[t].first;
+                val[rowptr[l] + t] = ent[t].second;
+            }
+        }
+    }
+    return Error{PGCP_OK, ""};
+}
+
+}  // namespace pgcp

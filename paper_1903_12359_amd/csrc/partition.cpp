@@ -1,0 +1,394 @@
+// Host plan builder: surface partition (Section 4.1) and everything the
+// batched device solves need (piece vertex lists, SELL-64 structure of the
+// cotangent Laplacian with the opposite vertices of every entry, boundary
+// loops, DNCP pins, seam list) plus the weld merge tree.
+//
+// Pieces are the connected components of the face graph whose edges are the
+// interior edges with equal labels on both sides (an edge between different
+// labels is a cut edge).  They are numbered by their smallest face index and
+// each must be a topological disk.
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "pgcp_internal.h"
+
+namespace pgcp {
+namespace {
+
+struct UnionFind {
+    std::vector<int32_t> parent;
+    explicit UnionFind(int64_t n) : parent(n) { std::iota(parent.begin(), parent.end(), 0); }
+    int32_t find(int32_t x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    }
+    void unite(int32_t a, int32_t b) {
+        a = find(a);
+        b = find(b);
+        if (a == b) return;
+        if (a < b) std::swap(a, b);
+        parent[a] = b;   // root = smaller index
+    }
+};
+
+Error topo(const std::string& m) { return Error{PGCP_E_TOPOLOGY, m}; }
+
+}  // namespace
+
+Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                 const int32_t* label, int mode) {
+    if (nv <= 0 || nf <= 0 || nv > INT32_MAX / 2 || nf > INT32_MAX / 4)
+        return Error{PGCP_E_INVALID, "mesh size out of range"};
+    if (mode < 0 || mode > 2) return Error{PGCP_E_INVALID, "bad mode"};
+    P->nv = nv;
+    P->nf = nf;
+    P->mode = mode;
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+        if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+            return Error{PGCP_E_INVALID, "face index out of range"};
+        if (a == b || b == c || a == c) return topo("face with a repeated vertex");
+    }
+
+    // ---- half-edge twins by counting sort on the smaller endpoint
+    const int64_t nh = 3 * nf;
+    std::vector<int64_t> cnt(nv + 1, 0);
+    for (int64_t h = 0; h < nh; ++h) {
+        int32_t a = F[h], b = F[(h / 3) * 3 + (h % 3 + 1) % 3];
+        cnt[std::min(a, b) + 1]++;
+    }
+    for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
+    std::vector<int32_t> bucket(nh);
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t h = 0; h < nh; ++h) {
+            int32_t a = F[h], b = F[(h / 3) * 3 + (h % 3 + 1) % 3];
+            bucket[fill[std::min(a, b)]++] = (int32_t)h;
+        }
+    }
+    auto he_a = [&](int64_t h) { return F[h]; };
+    auto he_b = [&](int64_t h) { return F[(h / 3) * 3 + (h % 3 + 1) % 3]; };
+    std::vector<int32_t> twin(nh, -1);
+    for (int64_t v = 0; v < nv; ++v) {
+        int64_t s = cnt[v], e = cnt[v + 1];
+        // group by the larger endpoint (buckets are tiny: the vertex degree)
+        for (int64_t i = s; i < e; ++i) {
+            int32_t hi = std::max(he_a(bucket[i]), he_b(bucket[i]));
+            int found = 0;
+            int32_t other = -1;
+            for (int64_t j = s; j < e; ++j) {
+                if (j == i) continue;
+                if (std::max(he_a(bucket[j]), he_b(bucket[j])) == hi) {
+                    found++;
+                    other = bucket[j];
+                }
+            }
+            if (found > 1) return topo("non-manifold edge (more than two faces)");
+            if (found == 1) {
+                if (he_a(other) == he_a(bucket[i])) return topo("inconsistently oriented faces");
+                twin[bucket[i]] = other;
+            }
+        }
+    }
+
+    // ---- pieces: components of the face graph over uncut interior edges
+    UnionFind uf(nf);
+    for (int64_t h = 0; h < nh; ++h) {
+        int32_t t = twin[h];
+        if (t < 0 || t < h) continue;
+        int32_t f0 = (int32_t)(h / 3), f1 = t / 3;
+        if (label[f0] == label[f1]) uf.unite(f0, f1);
+    }
+    P->face_sub.assign(nf, -1);
+    std::vector<int32_t> root_id(nf, -1);
+    int K = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        int32_t r = uf.find((int32_t)f);
+        if (root_id[r] < 0) root_id[r] = K++;
+        P->face_sub[f] = root_id[r];
+    }
+    P->K = K;
+
+    // faces of each piece, ascending
+    std::vector<int64_t> fptr(K + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) fptr[P->face_sub[f] + 1]++;
+    for (int i = 0; i < K; ++i) fptr[i + 1] += fptr[i];
+    std::vector<int32_t> faces(nf);
+    {
+        std::vector<int64_t> fill(fptr.begin(), fptr.end() - 1);
+        for (int64_t f = 0; f < nf; ++f) faces[fill[P->face_sub[f]]++] = (int32_t)f;
+    }
+    P->sub_nf.resize(K);
+    for (int i = 0; i < K; ++i) P->sub_nf[i] = (int32_t)(fptr[i + 1] - fptr[i]);
+
+    // vertices of each piece (sorted), packed rows padded to 64
+    std::vector<std::vector<int32_t>> verts(K);
+    Error err{PGCP_OK, ""};
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < K; ++i) {
+        auto& vv = verts[i];
+        vv.reserve(3 * (fptr[i + 1] - fptr[i]));
+        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t)
+            for (int c = 0; c < 3; ++c) vv.push_back(F[3 * (int64_t)faces[t] + c]);
+        std::sort(vv.begin(), vv.end());
+        vv.erase(std::unique(vv.begin(), vv.end()), vv.end());
+    }
+    P->sub_nv.resize(K);
+    P->row0.assign(K + 1, 0);
+    for (int i = 0; i < K; ++i) {
+        P->sub_nv[i] = (int32_t)verts[i].size();
+        int64_t padded = (verts[i].size() + 63) / 64 * 64;
+        if ((int64_t)P->row0[i] + padded > INT32_MAX) return Error{PGCP_E_INVALID, "too many rows"};
+        P->row0[i + 1] = P->row0[i] + (int32_t)padded;
+    }
+    const int64_t N = P->row0[K];
+    P->N = N;
+    P->nslices = N / 64;
+    P->row_gv.assign(N, -1);
+    P->row_prev.assign(N, -1);
+    P->row_next.assign(N, -1);
+    P->row_kind.assign(N, 2);
+    P->slice_sub.resize(P->nslices);
+    for (int i = 0; i < K; ++i) {
+        for (size_t l = 0; l < verts[i].size(); ++l) {
+            P->row_gv[P->row0[i] + l] = verts[i][l];
+            P->row_kind[P->row0[i] + l] = 0;
+        }
+        for (int64_t s = P->row0[i] / 64; s < P->row0[i + 1] / 64; ++s) P->slice_sub[s] = i;
+    }
+
+    // corner -> packed row
+    std::vector<int32_t> corner_row(nh);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < K; ++i) {
+        const auto& vv = verts[i];
+        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
+            int64_t f = faces[t];
+            for (int c = 0; c < 3; ++c) {
+                int32_t g = F[3 * f + c];
+                auto it = std::lower_bound(vv.begin(), vv.end(), g);
+                corner_row[3 * f + c] = P->row0[i] + (int32_t)(it - vv.begin());
+            }
+        }
+    }
+
+    // ---- boundary loops, Euler characteristic, pins
+    std::vector<std::vector<int32_t>> loops(K);   // packed rows, CCW
+    std::vector<std::string> emsg(K);
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < K; ++i) {
+        int32_t r0 = P->row0[i];
+        int32_t n = (int32_t)verts[i].size();
+        std::vector<int32_t> nxt(n, -1);
+        int64_t nb = 0;
+        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
+            int64_t f = faces[t];
+            for (int c = 0; c < 3; ++c) {
+                int64_t h = 3 * f + c;
+                int32_t tw = twin[h];
+                if (tw >= 0 && P->face_sub[tw / 3] == i) continue;
+                int32_t a = corner_row[h] - r0, b = corner_row[3 * f + (c + 1) % 3] - r0;
+                if (nxt[a] >= 0) {
+                    emsg[i] = "piece " + std::to_string(i) + ": pinched boundary vertex";
+                    break;
+                }
+                nxt[a] = b;
+                nb++;
+            }
+            if (!emsg[i].empty()) break;
+        }
+        if (!emsg[i].empty()) continue;
+        if (nb == 0) {
+            emsg[i] = "piece " + std::to_string(i) + " has no boundary";
+            continue;
+        }
+        int32_t start = 0;
+        while (nxt[start] < 0) start++;   // smallest local index = smallest global index
+        std::vector<int32_t>& L = loops[i];
+        int32_t v = start;
+        do {
+            L.push_back(v + r0);
+            v = nxt[v];
+        } while (v != start && (int64_t)L.size() <= nb);
+        if ((int64_t)L.size() != nb) {
+            emsg[i] = "piece " + std::to_string(i) + ": more than one boundary loop";
+            continue;
+        }
+        int64_t nfi = fptr[i + 1] - fptr[i];
+        if ((3 * nfi + nb) % 2 != 0 || (int64_t)n - (3 * nfi + nb) / 2 + nfi != 1) {
+            emsg[i] = "piece " + std::to_string(i) + ": Euler characteristic is not 1";
+            continue;
+        }
+    }
+    for (int i = 0; i < K; ++i)
+        if (!emsg[i].empty()) return topo(emsg[i]);
+
+    P->loop_ptr.assign(K + 1, 0);
+    for (int i = 0; i < K; ++i) P->loop_ptr[i + 1] = P->loop_ptr[i] + (int32_t)loops[i].size();
+    P->n_bdy = P->loop_ptr[K];
+    P->loop_row.resize(P->n_bdy);
+    P->loop_gv.resize(P->n_bdy);
+    P->pin_row.resize(2 * K);
+    P->pin_x1.resize(K);
+    for (int i = 0; i < K; ++i) {
+        const auto& L = loops[i];
+        int32_t nb = (int32_t)L.size();
+        for (int32_t e = 0; e < nb; ++e) {
+            int32_t r = L[e];
+            P->loop_row[P->loop_ptr[i] + e] = r;
+            P->loop_gv[P->loop_ptr[i] + e] = P->row_gv[r];
+            P->row_kind[r] = 1;
+            P->row_next[r] = L[(e + 1) % nb];
+            P->row_prev[r] = L[(e + nb - 1) % nb];
+        }
+        // pins: p0 = smallest global index (loop start), p1 = farthest from p0 in R^3
+        const double* x0 = V + 3 * (int64_t)P->row_gv[L[0]];
+        double best = -1.0;
+        int32_t p1 = L[0];
+        for (int32_t e = 0; e < nb; ++e) {
+            const double* x = V + 3 * (int64_t)P->row_gv[L[e]];
+            double dx = x[0] - x0[0], dy = x[1] - x0[1], dz = x[2] - x0[2];
+            double d = std::sqrt(dx * dx + dy * dy + dz * dz);
+            if (d > best) {
+                best = d;
+                p1 = L[e];
+            }
+        }
+        if (!(best > 0.0)) return Error{PGCP_E_DEGENERATE, "piece with coincident boundary vertices"};
+        P->pin_row[2 * i] = L[0];
+        P->pin_row[2 * i + 1] = p1;
+        P->pin_x1[i] = best;
+    }
+
+    // seam vertices (ascending) and the seam index of each loop entry
+    P->seam_gv = P->loop_gv;
+    std::sort(P->seam_gv.begin(), P->seam_gv.end());
+    P->seam_gv.erase(std::unique(P->seam_gv.begin(), P->seam_gv.end()), P->seam_gv.end());
+    P->n_seam = (int64_t)P->seam_gv.size();
+    P->loop_seam.resize(P->n_bdy);
+    for (int64_t e = 0; e < P->n_bdy; ++e)
+        P->loop_seam[e] = (int32_t)(std::lower_bound(P->seam_gv.begin(), P->seam_gv.end(),
+                                                     P->loop_gv[e]) - P->seam_gv.begin());
+
+    // ---- off-diagonal structure with opposite vertices, per row
+    // each corner (k of face (i,j,k)) contributes entries i->j and j->i with
+    // opposite vertex k.
+    std::vector<int32_t> deg_raw(N, 0);
+    for (int64_t h = 0; h < nh; ++h) {
+        deg_raw[corner_row[h]] += 2;
+    }
+    std::vector<int64_t> rptr(N + 1, 0);
+    for (int64_t r = 0; r < N; ++r) rptr[r + 1] = rptr[r] + deg_raw[r];
+    std::vector<int32_t> ent_col(rptr[N]), ent_opp(rptr[N]);
+    {
+        std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
+        for (int64_t f = 0; f < nf; ++f) {
+            for (int c = 0; c < 3; ++c) {
+                int32_t ri = corner_row[3 * f + (c + 1) % 3];
+                int32_t rj = corner_row[3 * f + (c + 2) % 3];
+                int32_t gk = F[3 * f + c];
+                ent_col[fill[ri]] = rj;
+                ent_opp[fill[ri]++] = gk;
+                ent_col[fill[rj]] = ri;
+                ent_opp[fill[rj]++] = gk;
+            }
+        }
+    }
+    // merge duplicates: unique columns ascending, up to two opposite vertices
+    std::vector<int32_t> deg(N, 0);
+    std::vector<int32_t> u_col(rptr[N]), u_o1(rptr[N]), u_o2(rptr[N]);
+    std::vector<std::string> derr(1);
+    bool bad_edge = false;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < N; ++r) {
+        int64_t s = rptr[r], e = rptr[r + 1];
+        // insertion sort by (col, opp): rows are short
+        for (int64_t a = s + 1; a < e; ++a) {
+            int32_t c = ent_col[a], o = ent_opp[a];
+            int64_t b = a - 1;
+            while (b >= s && (ent_col[b] > c || (ent_col[b] == c && ent_opp[b] > o))) {
+                ent_col[b + 1] = ent_col[b];
+                ent_opp[b + 1] = ent_opp[b];
+                b--;
+            }
+            ent_col[b + 1] = c;
+            ent_opp[b + 1] = o;
+        }
+        int32_t d = 0;
+        for (int64_t a = s; a < e;) {
+            int64_t b = a;
+            while (b < e && ent_col[b] == ent_col[a]) b++;
+            if (b - a > 2) bad_edge = true;
+            u_col[s + d] = ent_col[a];
+            u_o1[s + d] = ent_opp[a];
+            u_o2[s + d] = (b - a == 2) ? ent_opp[a + 1] : -1;
+            d++;
+            a = b;
+        }
+        deg[r] = d;
+    }
+    if (bad_edge) return topo("edge with more than two faces inside a piece");
+
+    // ---- SELL-64 layout
+    P->sl_ptr.assign(P->nslices + 1, 0);
+    P->sl_w.assign(P->nslices, 0);
+    int64_t nnz = 0;
+    for (int64_t s = 0; s < P->nslices; ++s) {
+        int32_t w = 0;
+        for (int l = 0; l < 64; ++l) w = std::max(w, deg[s * 64 + l]);
+        P->sl_w[s] = w;
+        P->sl_ptr[s + 1] = P->sl_ptr[s] + (int64_t)w * 64;
+        for (int l = 0; l < 64; ++l) nnz += deg[s * 64 + l];
+    }
+    P->nnz_off = nnz;
+    P->sub_nnz.assign(K, 0);
+    for (int i = 0; i < K; ++i)
+        for (int64_t r = P->row0[i]; r < P->row0[i + 1]; ++r) P->sub_nnz[i] += deg[r];
+    P->sell_elems = P->sl_ptr[P->nslices];
+    P->sl_col.resize(P->sell_elems);
+    P->sl_opp.resize(2 * P->sell_elems);
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < P->nslices; ++s) {
+        int64_t base = P->sl_ptr[s];
+        for (int l = 0; l < 64; ++l) {
+            int64_t r = s * 64 + l;
+            for (int32_t k = 0; k < P->sl_w[s]; ++k) {
+                int64_t el = base + (int64_t)k * 64 + l;
+                if (k < deg[r]) {
+                    P->sl_col[el] = u_col[rptr[r] + k];
+                    P->sl_opp[2 * el] = u_o1[rptr[r] + k];
+                    P->sl_opp[2 * el + 1] = u_o2[rptr[r] + k];
+                } else {
+                    P->sl_col[el] = (int32_t)r;
+                    P->sl_opp[2 * el] = -1;
+                    P->sl_opp[2 * el + 1] = -1;
+                }
+            }
+        }
+    }
+
+    // ---- weld merge tree (depends on the loops only)
+    std::vector<std::vector<int>> gl(K);
+    std::vector<int64_t> sizes(K);
+    for (int i = 0; i < K; ++i) {
+        gl[i].assign(P->loop_gv.begin() + P->loop_ptr[i], P->loop_gv.begin() + P->loop_ptr[i + 1]);
+        sizes[i] = P->sub_nf[i];
+    }
+    P->weld_rounds.clear();
+    if (K > 1) {
+        Error e = merge_plan(gl, sizes, mode, &P->weld_rounds);
+        if (e.code != PGCP_OK) return e;
+    } else if (mode == PGCP_SPHERE) {
+        return Error{PGCP_E_WELD, "sphere mode needs at least two pieces"};
+    }
+    P->chart.assign(K, cplx(0.0, 0.0));
+    P->chart_inf.assign(K, 0);
+    return Error{PGCP_OK, ""};
+}
+
+}  // namespace pgcp

@@ -1,0 +1,129 @@
+// Internal declarations shared by the host (C++) and device (HIP) parts of libpgcp.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/pgcp.h"
+
+namespace pgcp {
+
+using cplx = std::complex<double>;
+
+// Error carried from internal code to the C ABI.
+struct Error {
+    pgcp_status code;
+    std::string msg;
+};
+
+// Device buffer owned by a plan or context.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+// A device-side work assignment for the persistent batched CG: each workgroup
+// owns a contiguous range of 64-row slices of exactly one piece.
+struct WorkMap {
+    int rows_per_thread = 0;     // R
+    int n_wg = 0;                // grid size
+    std::vector<int32_t> wg_sub, wg_s0, wg_s1;   // per workgroup
+    std::vector<int32_t> sub_wg0, sub_nwg;       // per piece
+    DevBuf d_wg_sub, d_wg_s0, d_wg_s1, d_sub_wg0, d_sub_nwg;
+};
+
+}  // namespace pgcp
+
+// Opaque handles of the C ABI.
+struct pgcp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int n_cu = 0;
+    std::string last_error;
+};
+
+struct pgcp_part {
+    int64_t nv = 0, nf = 0;
+    int K = 0;
+    int mode = 0;
+    int64_t N = 0;          // packed rows (pieces padded to multiples of 64)
+    int64_t nslices = 0;    // N / 64
+    int64_t n_bdy = 0, n_seam = 0, nnz_off = 0, sell_elems = 0;
+
+    // ---------------- host plan
+    std::vector<int32_t> face_sub;            // [nf]
+    std::vector<int32_t> sub_nv, sub_nf;      // [K]
+    std::vector<int64_t> sub_nnz;             // [K] off-diagonal entries of each piece
+    std::vector<int32_t> row0;                // [K+1]
+    std::vector<int32_t> row_gv;              // [N]  -1 = padding row
+    std::vector<int32_t> row_prev, row_next;  // [N]  CCW loop neighbours (packed rows), -1 inside
+    std::vector<uint8_t> row_kind;            // [N]  0 interior, 1 boundary loop, 2 padding
+    std::vector<int32_t> slice_sub;           // [nslices]
+    std::vector<int64_t> sl_ptr;              // [nslices+1] first element of each slice
+    std::vector<int32_t> sl_w;                // [nslices] slice width (max off-diagonals per row)
+    std::vector<int32_t> sl_col;              // [sell_elems] packed column; padding = own row
+    std::vector<int32_t> sl_opp;              // [2*sell_elems] opposite vertices (global ids) or -1
+    std::vector<int32_t> pin_row;             // [2K] DNCP pins p0, p1 (packed rows)
+    std::vector<double> pin_x1;               // [K] x coordinate of p1 (|v_p1 - v_p0|)
+    std::vector<int32_t> loop_ptr;            // [K+1]
+    std::vector<int32_t> loop_gv, loop_row, loop_seam;   // [n_bdy]
+    std::vector<int32_t> seam_gv;             // [n_seam]
+    std::vector<std::vector<std::pair<int, int>>> weld_rounds;
+    std::vector<pgcp::cplx> chart;            // [K] sphere chart centres (after the weld)
+    std::vector<int32_t> chart_inf;           // [K] chart centre is the point at infinity
+
+    // ---------------- device mirrors
+    pgcp::DevBuf d_row_gv, d_row_prev, d_row_next, d_row_kind, d_slice_sub;
+    pgcp::DevBuf d_sl_ptr, d_sl_w, d_sl_col, d_sl_opp;
+    pgcp::DevBuf d_val64, d_val32, d_diag64, d_diag32;
+    pgcp::DevBuf d_pin_row, d_pin_x1, d_loop_ptr, d_loop_row, d_loop_seam, d_seam_gv;
+    pgcp::DevBuf d_mask_dncp, d_mask_harm;    // [N] uint8: 1 = Dirichlet row
+    pgcp::DevBuf d_chart;                     // [2K] doubles
+
+    // ---------------- solver work space
+    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1;
+    pgcp::DevBuf d_partial, d_bar, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
+    pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
+    pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
+    pgcp::WorkMap wmap;
+    int wmap_prec = -1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    bool assembled = false;
+    bool welded = false;
+    bool host_only = false;
+};
+
+namespace pgcp {
+
+// host plan (partition.cpp)
+Error build_plan(pgcp_part* part, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                 const int32_t* label, int mode);
+
+// weld (weld.cpp)
+int shared_arc(const std::vector<int>& la, const std::vector<int>& lb, int* start);
+Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<int64_t>& sizes,
+                 int mode, std::vector<std::vector<std::pair<int, int>>>* rounds);
+Error weld_all(pgcp_part* part, const double* bdy_uv, double* welded_uv);
+
+// device side (device.hip)
+Error upload_plan(pgcp_ctx* ctx, pgcp_part* part);
+void free_part_device(pgcp_part* part);
+Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V);
+Error assembled_ok(pgcp_ctx* ctx, pgcp_part* P);
+Error export_laplacian(pgcp_ctx* ctx, const pgcp_part* P, int piece, int32_t* rowptr, int32_t* col,
+                       double* val);
+Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, double* bdy,
+                      pgcp_solve_stats* st);
+Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp_solve_opts* o,
+                   double* out, pgcp_solve_stats* st);
+Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                     const double* X, int dim, double* d, double* mu, uint8_t* flip, int want_q,
+                     pgcp_dist_stats* st);
+
+}  // namespace pgcp

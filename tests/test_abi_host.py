@@ -1,0 +1,118 @@
+"""C-ABI library on the CPU: exported symbols, and the host stages (partition,
+weld) against the oracle.  No device calls are made here.
+
+Partition work is integer work and must match bit-exactly; the weld is the
+same sequence of analytic maps evaluated in a different order (arc points
+first, then the recorded chain per point), so it must agree to rounding.
+"""
+import re
+
+import numpy as np
+import pytest
+
+from oracle.pipeline import local_params, prepare
+from oracle.weld import weld as oracle_weld
+from synth import case_c1, case_c2, small_grid_case
+
+pg = pytest.importorskip("paper_1903_12359_amd")
+HEADER = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "include", "pgcp.h")
+
+
+def _lib():
+    try:
+        return pg.load_library()
+    except ImportError as e:   # the build step has not run in this checkout
+        pytest.skip(str(e))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(pgcp_[a-z_]+)\s*\(", text))
+    assert declared == set(pg.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+CASES = [
+    lambda: small_grid_case(17, 2, 2, seed=0),
+    lambda: small_grid_case(25, 3, 3, seed=2, jitter=0.3),
+    lambda: small_grid_case(21, 4, 1, seed=5),
+    lambda: small_grid_case(9, 1, 1, seed=1),
+    lambda: small_grid_case(23, 3, 2, seed=4, mode="disk"),
+    case_c1,
+    lambda: case_c2(n=96),
+]
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_partition_bit_exact(make):
+    _lib()
+    case = make()
+    plan = pg.Plan(None, case.V, case.F, case.label, case.mode)
+    ex = plan.export()
+    part, subs = prepare(case.V, case.F, case.label)
+    assert plan.K == part.K
+    assert np.array_equal(ex["face_sub"], part.face_sub)
+    for i, s in enumerate(part.subs):
+        assert ex["sub_nv"][i] == s.verts.size
+        assert np.array_equal(ex["loop_gv"][ex["loop_ptr"][i]:ex["loop_ptr"][i + 1]], s.loop)
+    seam = np.unique(np.concatenate([s.loop for s in part.subs]))
+    assert np.array_equal(ex["seam_gv"], seam)
+
+
+@pytest.mark.parametrize("make", CASES)
+def test_weld_matches_oracle(make):
+    _lib()
+    case = make()
+    plan = pg.Plan(None, case.V, case.F, case.label, case.mode)
+    ex = plan.export()
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    wo = oracle_weld([s["loop"] for s in subs], bdy, case.mode, sizes=[len(s["T"]) for s in subs])
+    bh = np.concatenate([np.column_stack([b.real, b.imag]) for b in bdy])
+    wc = pg.weld(None, plan, bh)
+    zo = np.array([wo[g] for g in ex["seam_gv"]])
+    zc = wc[:, 0] + 1j * wc[:, 1]
+    assert np.abs(zo - zc).max() <= 1e-10 * np.abs(zo).max()
+    if case.mode == "disk":
+        assert np.abs(np.abs(zc).max() - 1.0) < 1e-12
+
+
+def test_partition_errors_are_topology():
+    _lib()
+    from synth import block_labels, grid_mesh
+    from synth.meshes import grid_cell_index
+    n = 7
+    xy, F = grid_mesh(n)
+    V = np.column_stack([xy, np.zeros(n * n)])
+    ring = np.where(block_labels(n, 3, 3) == 4, 1, 0).astype(np.int32)
+    ic, jc = grid_cell_index(n)
+    block = (ic < 3) & (jc < 3)
+    hole = ((ic == 1) & (jc == 1)) | ((ic == 2) & (jc == 2))
+    pinch = (block & ~hole).astype(np.int32)
+    F2 = np.vstack([F, [[F[0, 0], F[0, 1], 5 * n]]]).astype(np.int32)
+    for VV, FF, lab in [(V, F, ring), (V, F, pinch), (V, F2, np.zeros(F2.shape[0], np.int32))]:
+        with pytest.raises(pg.PGCPError) as ei:
+            pg.Plan(None, VV, FF, lab, "free")
+        assert ei.value.status == "TOPOLOGY"
+    bad = F.copy()
+    bad[0, 0] = n * n + 5
+    with pytest.raises(pg.PGCPError) as ei:
+        pg.Plan(None, V, bad, np.zeros(F.shape[0], np.int32), "free")
+    assert ei.value.status == "INVALID"
+
+
+def test_single_piece_weld_is_identity_and_disk_circle():
+    _lib()
+    case = small_grid_case(13, 1, 1, seed=3)
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    bh = np.column_stack([bdy[0].real, bdy[0].imag])
+    plan = pg.Plan(None, case.V, case.F, case.label, "free")
+    w = pg.weld(None, plan, bh)
+    order = np.argsort(subs[0]["loop"])
+    np.testing.assert_array_equal(w, bh[order])
+    plan = pg.Plan(None, case.V, case.F, case.label, "disk")
+    w = pg.weld(None, plan, bh)
+    assert np.abs(np.hypot(w[:, 0], w[:, 1]) - 1).max() < 1e-12

@@ -1,0 +1,196 @@
+"""GPU path (libpgcp through its C ABI) against the FP64 oracle, stage by stage.
+
+Each stage is fed the oracle's own input for that stage, so the comparison
+measures that stage alone: assembly (relative 1e-13), DNCP boundary
+coordinates (FP64 path 1e-9, FP32+refinement 1e-6 relative to the largest
+coordinate), harmonic map with the oracle's welded boundary (same bounds),
+distortion arrays (angles to 1e-9 degrees, flips bit-exact).  End-to-end runs
+must be flip-free and close to the oracle's output.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.cotan import cotan_laplacian
+from oracle.distortion import distortion as oracle_distortion
+from oracle.pipeline import harmonic_all, local_params, pgcp, prepare
+from oracle.weld import weld as oracle_weld
+from synth import case_c1, case_c2, small_grid_case
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1903_12359_amd as pg
+    pg.load_library()          # fails loudly when the library is missing
+    assert torch.cuda.is_available()
+    return pg.Context(0)
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+CASES = {
+    "g17_2x2": lambda: small_grid_case(17, 2, 2, seed=0),
+    "g33_3x3_jit": lambda: small_grid_case(33, 3, 3, seed=2, jitter=0.3),
+    "g40_4x2": lambda: small_grid_case(40, 4, 2, seed=6),
+    "g12_1x1": lambda: small_grid_case(12, 1, 1, seed=1),
+    "C1": case_c1,
+    "C2_n128": lambda: case_c2(n=128),
+}
+
+
+def _oracle_stages(case):
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    welded = oracle_weld([s["loop"] for s in subs], bdy, case.mode, sizes=[len(s["T"]) for s in subs])
+    return part, subs, bdy, welded
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assembly_matches_oracle(ctx, name):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("assembly", name, case.nv)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    part, subs = prepare(case.V, case.F, case.label)
+    for i, s in enumerate(subs):
+        L = plan.laplacian(i).toarray()
+        Lo = cotan_laplacian(s["P"], s["T"]).toarray()
+        assert np.abs(L - Lo).max() <= 1e-13 * np.abs(Lo).max(), (name, i)
+        assert np.array_equal(L, L.T)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
+def test_dncp_matches_oracle(ctx, name, prec, tol, bound):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("dncp", name, prec)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    bdy, rep = pg.local_param(ctx, plan, precision=prec, tol=tol)
+    assert (rep.status == 0).all(), rep.relres
+    assert rep.relres.max() <= tol
+    part, subs = prepare(case.V, case.F, case.label)
+    ob = np.concatenate(local_params(subs))
+    g = bdy.cpu().numpy()
+    gz = g[:, 0] + 1j * g[:, 1]
+    err = np.abs(gz - ob).max() / np.abs(ob).max()
+    say("  max rel err", err, "iters", rep.total_iters)
+    assert err <= bound
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
+def test_harmonic_matches_oracle(ctx, name, prec, tol, bound):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("harmonic", name, prec)
+    part, subs, bdy, welded = _oracle_stages(case)
+    vals, _ = harmonic_all(subs, welded, case.mode)
+    from oracle.pipeline import assemble
+    phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    seam = plan.export()["seam_gv"]
+    w = np.array([welded[int(v)] for v in seam])
+    wd = _dev(np.column_stack([w.real, w.imag]))
+    phi, rep = pg.harmonic_solve(ctx, plan, wd, precision=prec, tol=tol)
+    assert (rep.status == 0).all(), rep.relres
+    g = phi.cpu().numpy()
+    err = np.abs(g - phi_o).max() / np.abs(phi_o).max()
+    say("  max rel err", err, "iters", rep.total_iters)
+    assert err <= bound
+
+
+@pytest.mark.parametrize("name", ["g33_3x3_jit", "C1", "C2_n128"])
+def test_distortion_matches_oracle(ctx, name):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("distortion", name)
+    r = pgcp(case.V, case.F, case.label, case.mode)
+    phi = r["phi"]
+    st, d, mu, flip = pg.distortion(ctx, _dev(case.V), _dev(case.F.astype(np.int32)), _dev(phi),
+                                    want_arrays=True, quantiles=True)
+    o = r["dist"]
+    assert np.abs(d.cpu().numpy() - o["d"]).max() <= 1e-9
+    assert np.abs(mu.cpu().numpy() - o["mu"]).max() <= 1e-9 * max(1.0, o["mu"].max())
+    assert np.array_equal(flip.cpu().numpy().astype(bool), o["flip"])
+    os_ = o["stats"]
+    for k in ("mean_abs_d", "sd_abs_d", "max_abs_d", "median_abs_d", "iqr_abs_d"):
+        assert abs(st[k] - os_[k]) <= 1e-9 * max(1.0, abs(os_[k])), k
+    assert st["n_flipped"] == os_["n_flipped"]
+
+
+def test_distortion_flips_and_affine(ctx):
+    import paper_1903_12359_amd as pg
+    case = small_grid_case(20, 1, 1, seed=4, flat=True, jitter=0.3)
+    V, F = _dev(case.V), _dev(case.F.astype(np.int32))
+    st, _, mu, _ = pg.distortion(ctx, V, F, _dev(case.V[:, :2] * np.array([2.0, 1.0])), want_arrays=True)
+    assert np.abs(mu.cpu().numpy() - 1 / 3).max() < 1e-12 and st["n_flipped"] == 0
+    st, _, _, flip = pg.distortion(ctx, V, F, _dev(case.V[:, :2] * np.array([-1.0, 1.0])), want_arrays=True)
+    assert st["n_flipped"] == case.nf and flip.cpu().numpy().all()
+
+
+@pytest.mark.parametrize("name", ["g17_2x2", "C1", "C2_n128"])
+def test_end_to_end(ctx, name):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("end-to-end", name)
+    phi, st, info = pg.run(ctx, case.V, case.F, case.label, case.mode, precision="fp64", tol=1e-13)
+    r = pgcp(case.V, case.F, case.label, case.mode)
+    g = phi.cpu().numpy()
+    err = np.abs(g - r["phi"]).max() / np.abs(r["phi"]).max()
+    say("  end-to-end rel err", err, st)
+    assert st["n_flipped"] == 0
+    assert err <= 1e-7
+    assert abs(st["mean_abs_d"] - r["dist"]["stats"]["mean_abs_d"]) <= 1e-6
+
+
+def test_run_twice_bitwise(ctx):
+    import paper_1903_12359_amd as pg
+    case = small_grid_case(33, 3, 3, seed=2, jitter=0.3)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    V = _dev(case.V)
+    outs = []
+    for prec in ("fp32", "fp32", "fp64", "fp64"):
+        pg.assemble_cotan(ctx, plan, V)
+        b, _ = pg.local_param(ctx, plan, precision=prec, tol=1e-10)
+        outs.append(b.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[2], outs[3])
+
+
+def test_noconv_reports_per_piece(ctx):
+    import paper_1903_12359_amd as pg
+    case = small_grid_case(33, 2, 2, seed=1)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    with pytest.raises(pg.PGCPError) as ei:
+        pg.local_param(ctx, plan, precision="fp64", tol=1e-12, max_iter=2, max_refine=2)
+    assert ei.value.status == "NOCONV"
+    _, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-12, max_iter=2, max_refine=2,
+                            allow_noconv=True)
+    assert (rep.status == -4).all() and (rep.iters > 0).all()
+
+
+def test_call_order_errors(ctx):
+    import paper_1903_12359_amd as pg
+    case = small_grid_case(9, 1, 1, seed=1)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    with pytest.raises(pg.PGCPError) as ei:
+        pg.local_param(ctx, plan)
+    assert ei.value.status == "INVALID"
