@@ -61,12 +61,16 @@ typedef struct pgcp_part pgcp_part;
  * the FP64 matrix, per piece (per coordinate for the harmonic solve).
  * inner_tol: relative residual reduction of each FP32 inner solve (FP32_REFINE).
  * max_iter: cap on CG iterations per inner solve; max_refine: cap on FP64
- * residual evaluations.  Zero fields take the defaults (1e-10, 1e-4, 20000, 30). */
+ * residual evaluations; stall_iters: an inner solve stops early after this
+ * many iterations without a 10% reduction of its residual (restarted from the
+ * FP64 residual by the next refinement pass).  Zero fields take the defaults
+ * (1e-10, 1e-4, 20000, 30, 4000).  PGCP_VERBOSE=1 in the environment prints
+ * one line per refinement pass to stderr. */
 typedef struct {
     int32_t precision;        /* pgcp_precision */
     int32_t max_iter;
     int32_t max_refine;
-    int32_t reserved;
+    int32_t stall_iters;
     double tol;
     double inner_tol;
 } pgcp_solve_opts;
@@ -83,8 +87,9 @@ typedef struct {
     double cg_kernel_ms;      /* out: summed duration of the batched-CG launches (HIP events) */
     double cg_bytes;          /* out: algorithmic bytes those launches move (see DESIGN)      */
     int32_t cg_launches;      /* out: number of batched-CG launches                    */
-    int32_t rows_per_thread;  /* out: rows per thread of the batched-CG launch shape   */
+    int32_t rows_per_thread;  /* out: 64-row slices per wave of the batched-CG launch  */
     int32_t cg_workgroups;    /* out: workgroups of the batched-CG launch              */
+    int32_t cg_block;         /* out: threads per workgroup of the batched-CG launch   */
     int32_t reserved2;
 } pgcp_solve_stats;
 

@@ -33,7 +33,7 @@ class PGCPError(RuntimeError):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
+                ("stall_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
 
 
 class SolveStats(ctypes.Structure):
@@ -41,7 +41,8 @@ class SolveStats(ctypes.Structure):
                 ("iters", ctypes.POINTER(ctypes.c_int32)), ("relres", ctypes.POINTER(ctypes.c_double)),
                 ("status", ctypes.POINTER(ctypes.c_int32)), ("seconds", ctypes.c_double),
                 ("cg_kernel_ms", ctypes.c_double), ("cg_bytes", ctypes.c_double), ("cg_launches", ctypes.c_int32),
-                ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("cg_block", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class DistStats(ctypes.Structure):
@@ -105,8 +106,9 @@ def _ptr(a):
     return a.data_ptr()
 
 
-def _opts(precision="fp64", tol=1e-10, inner_tol=0.0, max_iter=0, max_refine=0):
+def _opts(precision="fp64", tol=1e-10, inner_tol=0.0, max_iter=0, max_refine=0, stall_iters=0):
     o = SolveOpts()
+    o.stall_iters = stall_iters
     o.precision = PGCP_FP32_REFINE if precision in ("fp32", "fp32_refine", PGCP_FP32_REFINE) else PGCP_FP64
     o.tol = tol
     o.inner_tol = inner_tol
@@ -129,6 +131,7 @@ class SolveReport:
     cg_launches: int = 0
     rows_per_thread: int = 0
     cg_workgroups: int = 0
+    cg_block: int = 0
 
 
 class Context:
@@ -249,7 +252,7 @@ def _report(st, keep):
     it, rr, ss = keep
     return SolveReport(st.n_sub, st.refine_steps, st.total_iters, it.copy(), rr.reshape(-1, 2).copy(),
                        ss.copy(), st.seconds, st.cg_kernel_ms, st.cg_bytes, st.cg_launches, st.rows_per_thread,
-                       st.cg_workgroups)
+                       st.cg_workgroups, st.cg_block)
 
 
 def assemble_cotan(ctx: Context, plan: Plan, V_dev):
@@ -322,11 +325,14 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
 
 
 def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,
-        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None):
+        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64"):
     """Algorithm 3 end to end; returns (phi_dev, dist_stats, reports).
 
     V, F, label are host arrays (the partition runs on the host); V_dev/F_dev
-    are their device copies (made here if not given).
+    are their device copies (made here if not given).  `precision` is the
+    inner-solve precision of the harmonic solve; the DNCP solve uses
+    `dncp_precision` (FP64 by default: its free-boundary system has a
+    near-null space that FP32 CG cannot resolve, see the design notes).
     """
     import torch
     dev = f"cuda:{ctx.device}"
@@ -344,7 +350,7 @@ def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inn
     times["partition"] = time.perf_counter() - t
     t = time.perf_counter()
     assemble_cotan(ctx, plan, V_dev)
-    bdy, rep1 = local_param(ctx, plan, precision=precision, tol=tol, inner_tol=inner_tol)
+    bdy, rep1 = local_param(ctx, plan, precision=dncp_precision, tol=tol, inner_tol=inner_tol)
     bdy_h = bdy.cpu().numpy()
     times["assemble+dncp"] = time.perf_counter() - t
     t = time.perf_counter()

@@ -124,6 +124,7 @@ pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts*
     if (!ctx || !P || !bdy_uv_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     double t0 = now();
+    if (!P->assembled) return bad(ctx, "pgcp_assemble_cotan has not run");
     Error e = pgcp::assembled_ok(ctx, P);
     if (e.code == PGCP_OK) e = pgcp::run_local_param(ctx, P, opts, bdy_uv_dev, stats);
     if (stats) {

@@ -87,8 +87,11 @@ void free_part_device(pgcp_part* P) {
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
                      &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1,
                      &P->d_partial, &P->d_bar, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
-                     &P->d_flags, &P->wmap.d_wg_sub, &P->wmap.d_wg_s0, &P->wmap.d_wg_s1,
-                     &P->wmap.d_sub_wg0, &P->wmap.d_sub_nwg, &P->d_row0, &P->d_slicepart,
+                     &P->d_flags, &P->wmap32.d_wg_sub, &P->wmap32.d_wg_s0, &P->wmap32.d_wg_s1,
+                     &P->wmap32.d_sub_pbase, &P->wmap32.d_sub_nwg, &P->wmap32.d_wg_rank,
+                     &P->wmap64.d_wg_sub, &P->wmap64.d_wg_s0, &P->wmap64.d_wg_s1, &P->wmap64.d_wg_rank,
+                     &P->wmap64.d_sub_pbase, &P->wmap64.d_sub_nwg, 
+                     &P->d_row0, &P->d_slicepart,
                      &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
                      &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp};
     for (DevBuf* b : all) dev_free(*b);
@@ -156,6 +159,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_flags, 64)).code) return e;
     if ((e = dev_alloc(P->d_chart, K * 3 * 8)).code) return e;
     if ((e = dev_alloc(P->d_slicepart, (size_t)P->nslices * 2 * 8)).code) return e;
+    HIPCHK(hipMemsetAsync(P->d_flags.p, 0, 64, s));
     return Error{PGCP_OK, ""};
 }
 
@@ -370,11 +374,12 @@ struct CGArgs {
     const int32_t* rprev;
     const int32_t* rnext;
     const uint8_t* mask;
-    const int32_t* wg_sub;
-    const int32_t* wg_s0;
-    const int32_t* wg_s1;
-    const int32_t* sub_wg0;
-    const int32_t* sub_nwg;
+    const int32_t* wg_sub;         // [G] piece of each workgroup, -1 = idle
+    const int32_t* wg_rank;        // [G] rank of the workgroup inside its piece
+    const int32_t* wg_s0;          // [G] first slice
+    const int32_t* wg_s1;          // [G] end slice
+    const int32_t* sub_pbase;      // [K] first partial record of the piece
+    const int32_t* sub_nwg;        // [K] workgroups of the piece
     const int32_t* active;         // [K]
     const double* target_rel2;     // [K*2] squared relative tolerance per piece and coordinate
     typename Vec2<T>::type* e;
@@ -382,25 +387,97 @@ struct CGArgs {
     typename Vec2<T>::type* z;
     typename Vec2<T>::type* pa;
     typename Vec2<T>::type* pb;
-    double* partial;               // [G][8]
+    double* partial;               // [sum nwg][8]
     unsigned* bar;                 // [K]
     int* abort_flag;
     int32_t* iters;                // [K] out
     double* rr_out;                // [K*2] out: final recursive |r|^2 / |r0|^2
-    int32_t* status;               // [K] out: 0 ok, 1 breakdown, 2 max_iter, 3 abort
+    int32_t* status;               // [K] out: 0 ok, 1 breakdown, 2 max_iter, 3 abort, 4 stagnation
     int coupled;
     int max_iter;
+    int n_xcd;                     // workgroup g runs on XCD g % n_xcd (round-robin dispatch)
+    int stall;                     // stop after this many iterations without a 10% residual gain
 };
 
-__device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned target, int* abort_flag,
-                                              int* lds_abort) {
-    __threadfence();
+// Fixed-order block sum of NV values per thread; result returned to every thread.
+template <int BLK, int NV>
+__device__ __forceinline__ void bsum(double (&v)[NV], double* lds) {
+    constexpr int NW = BLK / 64;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += lds[w * NV + i];
+            lds[NW * NV + i] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = lds[NW * NV + i];
+    __syncthreads();
+}
+
+// Cross-workgroup data (the z and p vectors that neighbours gather, and the
+// partial dot products) is published and read with relaxed agent-scope atomic
+// stores and loads, which are coherent across the whole device; everything a
+// workgroup only reads itself (matrix, diagonal, e, r) uses plain accesses.
+__device__ __forceinline__ float2 ld_c(const float2* p) {
+    uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float2 r;
+    __builtin_memcpy(&r, &u, 8);
+    return r;
+}
+__device__ __forceinline__ double2 ld_c(const double2* p) {
+    const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+    uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double2 r;
+    __builtin_memcpy(&r.x, &a, 8);
+    __builtin_memcpy(&r.y, &b, 8);
+    return r;
+}
+__device__ __forceinline__ void st_c(float2* p, float2 v) {
+    uint64_t u;
+    __builtin_memcpy(&u, &v, 8);
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_c(double2* p, double2 v) {
+    uint64_t a, b;
+    __builtin_memcpy(&a, &v.x, 8);
+    __builtin_memcpy(&b, &v.y, 8);
+    uint64_t* q = reinterpret_cast<uint64_t*>(p);
+    __hip_atomic_store(q, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_c(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_c(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier of the workgroups of one piece: every wave waits until its stores
+// (the atomics above included) have completed, then one wave bumps the
+// piece's arrival counter and polls it.  A workgroup that sees the counter
+// reach its target can therefore read everything published before it.
+// Polling is bounded; a workgroup that waits too long raises the abort flag,
+// and every waiting workgroup leaves when it sees the flag.
+__device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned target, int* abort_flag, int* lds_flag) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         long long spins = 0;
         int ab = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             ++spins;
             if ((spins & 255) == 0) {
                 if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -415,99 +492,122 @@ __device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned target, in
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        *lds_abort = ab;
+        *lds_flag = ab;
     }
     __syncthreads();
-    __threadfence();
-    return *lds_abort != 0;
+    return *lds_flag != 0;
 }
 
-// Sum the partials of the piece's workgroups in a fixed order (tree over
-// workgroup index); nv values at offset off of each workgroup's 8-slot record.
-template <int NV>
-__device__ __forceinline__ void piece_sum(const double* partial, int wg0, int nwg, int off,
-                                          double (&out)[NV], double* lds) {
-    double v[NV];
+// Fixed-order sum of the piece's partial records (slots off .. off+NV-1).
+template <int BLK, int NV>
+__device__ __forceinline__ void piece_sum(const double* partial, int pbase, int nwg, int off, double (&out)[NV],
+                                          double* lds) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = 0.0;
-    for (int w = threadIdx.x; w < nwg; w += BLOCK) {
-        const double* p = partial + 8 * (int64_t)(wg0 + w) + off;
+    for (int i = 0; i < NV; ++i) out[i] = 0.0;
+    for (int w = threadIdx.x; w < nwg; w += BLK) {
+        const double* p = partial + 8 * (int64_t)(pbase + w) + off;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int i = 0; i < NV; ++i) out[i] += ld_c(p + i);
     }
-    block_sum<NV>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) lds[16 + i] = v[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = lds[16 + i];
-    __syncthreads();
+    bsum<BLK, NV>(out, lds);
 }
 
-template <typename T, int R>
-__global__ void __launch_bounds__(BLOCK) k_pcg(CGArgs<T> a) {
+// Register-resident batched PCG.  Thread t of a workgroup owns the rows
+// (s0 + wave + NW j) * 64 + lane, j < R, for the whole solve: e, r, z, p of its
+// rows live in registers.  Each iteration the workgroup stages p_new of its
+// own rows in LDS for the SpMV; columns owned by other workgroups of the piece
+// ("halo") are rebuilt as z + beta p_old from the values those workgroups
+// published through the coherent path.  Only rows with a neighbour in another
+// workgroup publish z and p.
+template <typename T, int BLK, int R>
+__global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     using V2 = typename Vec2<T>::type;
-    __shared__ double lds[32];
-    __shared__ int lds_abort;
+    constexpr int NW = BLK / 64;
+    extern __shared__ unsigned char smem_raw[];
+    V2* lds_p = reinterpret_cast<V2*>(smem_raw);
+    __shared__ double lds[NW * 8 + 16];
+    __shared__ int lds_flag;
     const int wg = blockIdx.x;
     const int sub = a.wg_sub[wg];
-    if (!a.active[sub]) return;
+    if (sub < 0 || !a.active[sub]) return;
     const int s0 = a.wg_s0[wg], s1 = a.wg_s1[wg];
-    const int wg0 = a.sub_wg0[sub], nwg = a.sub_nwg[sub];
+    const int rank = a.wg_rank[wg];
+    const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
+    const bool leader = rank == 0 && threadIdx.x == 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t lo = (int64_t)s0 * 64, hi = (int64_t)s1 * 64;
     unsigned* bar = a.bar + sub;
     unsigned nbar = 0;
-    double* mypart = a.partial + 8 * (int64_t)wg;
+    double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
 
     int64_t rows[R];
-    bool valid[R];
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-        int s = s0 + wave + WAVES * j;
-        valid[j] = s < s1;
-        rows[j] = (int64_t)s * 64 + lane;
-    }
-
-    // ---- start: z = D^-1 r, p_old = 0, r.z and r.r
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    bool valid[R], msk[R], expo[R];
+    V2 e[R], r[R], z[R], po[R];
+    T dg[R], dinv[R];
     V2 zero;
     zero.x = (T)0;
     zero.y = (T)0;
+
+    // ---- start: registers, export flags, z = D^-1 r, p_old = 0
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < R; ++j) {
+        const int s = s0 + wave + NW * j;
+        valid[j] = s < s1;
+        rows[j] = (int64_t)s * 64 + lane;
+        e[j] = zero;
+        po[j] = zero;
+        r[j] = zero;
+        z[j] = zero;
+        dg[j] = (T)0;
+        dinv[j] = (T)0;
+        msk[j] = true;
+        expo[j] = false;
         if (!valid[j]) continue;
-        int64_t rw = rows[j];
-        V2 rr = a.r[rw];
-        V2 zz;
-        if (a.mask[rw]) {
-            zz = zero;
-            a.r[rw] = zero;
-            rr = zero;
-        } else {
-            T dinv = (T)1 / a.diag[rw];
-            zz.x = dinv * rr.x;
-            zz.y = dinv * rr.y;
+        const int64_t rw = rows[j];
+        msk[j] = a.mask[rw] != 0;
+        dg[j] = a.diag[rw];
+        if (!msk[j]) {
+            dinv[j] = (T)1 / dg[j];
+            r[j] = a.r[rw];
+            z[j].x = dinv[j] * r[j].x;
+            z[j].y = dinv[j] * r[j].y;
         }
-        a.z[rw] = zz;
-        a.pa[rw] = zero;
-        acc[0] += (double)rr.x * (double)zz.x;
-        acc[1] += (double)rr.y * (double)zz.y;
-        acc[2] += (double)rr.x * (double)rr.x;
-        acc[3] += (double)rr.y * (double)rr.y;
+        const int64_t base = a.sl_ptr[s] + lane;
+        const int w = a.sl_w[s];
+        bool ex = false;
+        for (int k = 0; k < w; ++k) {
+            const int c = a.sl_col[base + (int64_t)k * 64];
+            ex |= (c < lo || c >= hi);
+        }
+        if (a.coupled) {
+            const int pv = a.rprev[rw];
+            if (pv >= 0) {
+                const int nx = a.rnext[rw];
+                ex |= (pv < lo || pv >= hi || nx < lo || nx >= hi);
+            }
+        }
+        expo[j] = ex;
+        if (ex) {
+            st_c(a.z + rw, z[j]);
+            st_c(a.pa + rw, zero);
+        }
+        acc[0] += (double)r[j].x * (double)z[j].x;
+        acc[1] += (double)r[j].y * (double)z[j].y;
+        acc[2] += (double)r[j].x * (double)r[j].x;
+        acc[3] += (double)r[j].y * (double)r[j].y;
     }
-    block_sum<4>(acc, lds);
+    bsum<BLK, 4>(acc, lds);
     if (threadIdx.x == 0) {
-        for (int i = 0; i < 4; ++i) mypart[2 + i] = acc[i];
+        for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
     }
     nbar++;
-    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
-        if (threadIdx.x == 0 && wg == wg0) a.status[sub] = 3;
+    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        if (leader) a.status[sub] = 3;
         return;
     }
     double st[4];
-    piece_sum<4>(a.partial, wg0, nwg, 2, st, lds);
+    piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
     double rz[2] = {st[0], st[1]};
     double rr0[2] = {st[2], st[3]};
     if (a.coupled) {
@@ -518,6 +618,8 @@ __global__ void __launch_bounds__(BLOCK) k_pcg(CGArgs<T> a) {
     bool done[2] = {rr0[0] <= tgt[0] || !(rz[0] > 0.0), rr0[1] <= tgt[1] || !(rz[1] > 0.0)};
     double rrc[2] = {rr0[0], rr0[1]};
     double beta[2] = {0.0, 0.0};
+    double best = (done[0] ? 0.0 : 1.0) + (done[1] ? 0.0 : 1.0);
+    int it_best = 0;
     int it = 0;
     int stat = 0;
     V2* pold = a.pa;
@@ -528,64 +630,86 @@ __global__ void __launch_bounds__(BLOCK) k_pcg(CGArgs<T> a) {
             stat = 2;
             break;
         }
-        // ---- phase A: p_new = z + beta p_old; q = A p_new; p.q
+        // ---- phase A: p_new = z + beta p_old (registers, LDS, halo publish); q = A p_new; p.q
         const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
-        V2 q[R], pn[R];
+        V2 pn[R], q[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            V2 p;
+            p.x = done[0] ? (T)0 : z[j].x + bx * po[j].x;
+            p.y = done[1] ? (T)0 : z[j].y + by * po[j].y;
+            pn[j] = p;
+            if (valid[j]) {
+                lds_p[rows[j] - lo] = p;
+                if (expo[j]) st_c(pnew + rows[j], p);
+            }
+        }
+        __syncthreads();
         double pq[2] = {0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            if (!valid[j]) continue;
-            int64_t rw = rows[j];
-            V2 zr = a.z[rw], po = pold[rw];
-            V2 p;
-            p.x = done[0] ? (T)0 : zr.x + bx * po.x;
-            p.y = done[1] ? (T)0 : zr.y + by * po.y;
-            pnew[rw] = p;
+            q[j] = zero;
+            if (!valid[j] || msk[j]) continue;
+            const int64_t rw = rows[j];
             const int64_t s = rw >> 6;
             const int64_t base = a.sl_ptr[s] + lane;
             const int w = a.sl_w[s];
-            const T dg = a.diag[rw];
-            T qx = dg * p.x, qy = dg * p.y;
+            T qx = dg[j] * pn[j].x, qy = dg[j] * pn[j].y;
             for (int k = 0; k < w; ++k) {
                 const int64_t el = base + (int64_t)k * 64;
                 const T v = a.val[el];
                 const int c = a.sl_col[el];
-                V2 zc = a.z[c], pc = pold[c];
-                qx += v * (zc.x + bx * pc.x);
-                qy += v * (zc.y + by * pc.y);
+                V2 pc;
+                if (c >= lo && c < hi) {
+                    pc = lds_p[c - lo];
+                } else {
+                    V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
+                    pc.x = zc.x + bx * oc.x;
+                    pc.y = zc.y + by * oc.y;
+                }
+                qx += v * pc.x;
+                qy += v * pc.y;
             }
             if (a.coupled) {
-                int pv = a.rprev[rw], nx = a.rnext[rw];
+                const int pv = a.rprev[rw];
                 if (pv >= 0) {
-                    V2 zn = a.z[nx], pnx = pold[nx], zp = a.z[pv], ppv = pold[pv];
-                    T nxx = zn.x + bx * pnx.x, nxy = zn.y + by * pnx.y;
-                    T pvx = zp.x + bx * ppv.x, pvy = zp.y + by * ppv.y;
-                    qx -= (T)0.5 * (nxy - pvy);
-                    qy += (T)0.5 * (nxx - pvx);
+                    const int nx = a.rnext[rw];
+                    V2 pN, pP;
+                    if (nx >= lo && nx < hi) {
+                        pN = lds_p[nx - lo];
+                    } else {
+                        V2 zc = ld_c(a.z + nx), oc = ld_c(pold + nx);
+                        pN.x = zc.x + bx * oc.x;
+                        pN.y = zc.y + by * oc.y;
+                    }
+                    if (pv >= lo && pv < hi) {
+                        pP = lds_p[pv - lo];
+                    } else {
+                        V2 zc = ld_c(a.z + pv), oc = ld_c(pold + pv);
+                        pP.x = zc.x + bx * oc.x;
+                        pP.y = zc.y + by * oc.y;
+                    }
+                    qx -= (T)0.5 * (pN.y - pP.y);
+                    qy += (T)0.5 * (pN.x - pP.x);
                 }
-            }
-            if (a.mask[rw]) {
-                qx = (T)0;
-                qy = (T)0;
             }
             q[j].x = qx;
             q[j].y = qy;
-            pn[j] = p;
-            pq[0] += (double)p.x * (double)qx;
-            pq[1] += (double)p.y * (double)qy;
+            pq[0] += (double)pn[j].x * (double)qx;
+            pq[1] += (double)pn[j].y * (double)qy;
         }
-        block_sum<2>(pq, lds);
+        bsum<BLK, 2>(pq, lds);
         if (threadIdx.x == 0) {
-            mypart[0] = pq[0];
-            mypart[1] = pq[1];
+            st_c(mypart + 0, pq[0]);
+            st_c(mypart + 1, pq[1]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
             stat = 3;
             break;
         }
         double pqs[2];
-        piece_sum<2>(a.partial, wg0, nwg, 0, pqs, lds);
+        piece_sum<BLK, 2>(a.partial, pbase, nwg, 0, pqs, lds);
         double alpha[2] = {0.0, 0.0};
         if (a.coupled) {
             double den = pqs[0] + pqs[1];
@@ -610,59 +734,64 @@ __global__ void __launch_bounds__(BLOCK) k_pcg(CGArgs<T> a) {
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            if (!valid[j]) continue;
-            int64_t rw = rows[j];
-            V2 ev = a.e[rw], rv = a.r[rw];
-            ev.x += ax * pn[j].x;
-            ev.y += ay * pn[j].y;
-            rv.x -= ax * q[j].x;
-            rv.y -= ay * q[j].y;
-            V2 zz;
-            if (a.mask[rw]) {
-                zz = zero;
-            } else {
-                T dinv = (T)1 / a.diag[rw];
-                zz.x = dinv * rv.x;
-                zz.y = dinv * rv.y;
-            }
-            a.e[rw] = ev;
-            a.r[rw] = rv;
-            a.z[rw] = zz;
-            acc2[0] += (double)rv.x * (double)zz.x;
-            acc2[1] += (double)rv.y * (double)zz.y;
-            acc2[2] += (double)rv.x * (double)rv.x;
-            acc2[3] += (double)rv.y * (double)rv.y;
+            po[j] = pn[j];
+            if (!valid[j] || msk[j]) continue;
+            e[j].x += ax * pn[j].x;
+            e[j].y += ay * pn[j].y;
+            r[j].x -= ax * q[j].x;
+            r[j].y -= ay * q[j].y;
+            z[j].x = dinv[j] * r[j].x;
+            z[j].y = dinv[j] * r[j].y;
+            if (expo[j]) st_c(a.z + rows[j], z[j]);
+            acc2[0] += (double)r[j].x * (double)z[j].x;
+            acc2[1] += (double)r[j].y * (double)z[j].y;
+            acc2[2] += (double)r[j].x * (double)r[j].x;
+            acc2[3] += (double)r[j].y * (double)r[j].y;
         }
-        block_sum<4>(acc2, lds);
+        bsum<BLK, 4>(acc2, lds);
         if (threadIdx.x == 0) {
-            for (int i = 0; i < 4; ++i) mypart[2 + i] = acc2[i];
+            for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_abort)) {
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
             stat = 3;
             break;
         }
-        piece_sum<4>(a.partial, wg0, nwg, 2, st, lds);
+        piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
         double rzn[2] = {st[0], st[1]};
         double rrn[2] = {st[2], st[3]};
         if (a.coupled) {
             rzn[0] = rzn[1] = st[0] + st[1];
             rrn[0] = rrn[1] = st[2] + st[3];
         }
+        double prog = 0.0;
         for (int c = 0; c < 2; ++c) {
             if (done[c]) continue;
             rrc[c] = rrn[c];
             beta[c] = rzn[c] / rz[c];
             rz[c] = rzn[c];
             if (rrn[c] <= tgt[c] || !(rzn[c] > 0.0)) done[c] = true;
+            else prog += rrn[c] / rr0[c];
         }
         if (a.coupled) done[1] = done[0];
+        ++it;
+        // stagnation: no 10% gain of the relative residual in `stall` iterations
+        if (prog < 0.9 * best) {
+            best = prog;
+            it_best = it;
+        } else if (!(done[0] && done[1]) && it - it_best > a.stall) {
+            stat = 4;
+            break;
+        }
         V2* t = pold;
         pold = pnew;
         pnew = t;
-        ++it;
     }
-    if (wg == wg0 && threadIdx.x == 0) {
+    // the correction leaves through plain stores (read by the next kernel)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (valid[j]) a.e[rows[j]] = e[j];
+    if (leader) {
         a.iters[sub] = it;
         a.status[sub] = stat;
         a.rr_out[2 * sub] = rr0[0] > 0.0 ? rrc[0] / rr0[0] : 0.0;
@@ -1008,77 +1137,244 @@ Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
     return Error{PGCP_OK, ""};
 }
 
-template <typename T, int R>
-static const void* pcg_kernel_ptr() {
-    return reinterpret_cast<const void*>(&k_pcg<T, R>);
+// Launch shapes of the batched PCG: (threads per workgroup, 64-row slices per wave).
+struct PcgCfg {
+    int blk, R;
+};
+static const PcgCfg kPcgCfgs[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {512, 1},
+                                  {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+
+template <typename T>
+static const void* pcg_kernel(int blk, int R) {
+    if (blk == 256) {
+        switch (R) {
+            case 1: return reinterpret_cast<const void*>(&k_pcg<T, 256, 1>);
+            case 2: return reinterpret_cast<const void*>(&k_pcg<T, 256, 2>);
+            case 4: return reinterpret_cast<const void*>(&k_pcg<T, 256, 4>);
+            default: return reinterpret_cast<const void*>(&k_pcg<T, 256, 8>);
+        }
+    }
+    if (blk == 512) {
+        switch (R) {
+            case 1: return reinterpret_cast<const void*>(&k_pcg<T, 512, 1>);
+            case 2: return reinterpret_cast<const void*>(&k_pcg<T, 512, 2>);
+            default: return reinterpret_cast<const void*>(&k_pcg<T, 512, 4>);
+        }
+    }
+    if (R == 1) return reinterpret_cast<const void*>(&k_pcg<T, 1024, 1>);
+    return reinterpret_cast<const void*>(&k_pcg<T, 1024, 2>);
+}
+
+// Workgroup map for one launch shape.  Pieces are placed on XCDs by
+// longest-processing-time first (workgroups g with g % n_xcd == x run on XCD x
+// under the hardware's round-robin dispatch), every piece on exactly one XCD,
+// so that its per-piece barrier only involves workgroups sharing one L2.
+static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, WorkMap* W, bool* fits) {
+    *fits = false;
+    int n_cu = 0, coop = 0;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx->device));
+    if (!coop) return Error{PGCP_E_HIP, "device does not support cooperative launches"};
+    const int n_xcd = (n_cu >= 64 && n_cu % 32 == 0) ? n_cu / 32 : 1;
+    int per_cu = 0;
+    const void* kern = prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R);
+    const size_t lds_bytes = (size_t)cfg.blk * cfg.R * (prec == 0 ? 16 : 8);
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
+    const int64_t cap = (int64_t)per_cu * n_cu;
+    const int64_t spw = (int64_t)(cfg.blk / 64) * cfg.R;   // slices per workgroup
+    const int K = P->K;
+    std::vector<int64_t> nw(K);
+    for (int i = 0; i < K; ++i) {
+        int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+        nw[i] = std::max<int64_t>(1, (ns + spw - 1) / spw);
+    }
+    std::vector<int> order(K);
+    for (int i = 0; i < K; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nw[a] > nw[b]; });
+    std::vector<int64_t> load(n_xcd, 0);
+    std::vector<std::vector<int>> on(n_xcd);
+    for (int i : order) {
+        int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        on[x].push_back(i);
+        load[x] += nw[i];
+    }
+    const int64_t slots = *std::max_element(load.begin(), load.end());
+    const int64_t G = slots * n_xcd;
+    if (G > cap) return Error{PGCP_OK, ""};
+    W->blk = cfg.blk;
+    W->rows_per_thread = cfg.R;
+    W->n_xcd = n_xcd;
+    W->n_wg = (int)G;
+    W->wg_sub.assign(G, -1);
+    W->wg_rank.assign(G, 0);
+    W->wg_s0.assign(G, 0);
+    W->wg_s1.assign(G, 0);
+    W->sub_pbase.assign(K, 0);
+    W->sub_nwg.assign(K, 0);
+    int32_t pb = 0;
+    for (int i = 0; i < K; ++i) {
+        W->sub_pbase[i] = pb;
+        W->sub_nwg[i] = (int32_t)nw[i];
+        pb += (int32_t)nw[i];
+    }
+    W->n_partials = pb;
+    for (int x = 0; x < n_xcd; ++x) {
+        int64_t slot = 0;
+        for (int i : on[x]) {
+            int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            for (int64_t t = 0; t < nw[i]; ++t, ++slot) {
+                int64_t g = slot * n_xcd + x;
+                W->wg_sub[g] = i;
+                W->wg_rank[g] = (int32_t)t;
+                W->wg_s0[g] = (int32_t)(sb + ns * t / nw[i]);
+                W->wg_s1[g] = (int32_t)(sb + ns * (t + 1) / nw[i]);
+            }
+        }
+    }
+    Error e{PGCP_OK, ""};
+    if ((e = upload(W->d_wg_sub, W->wg_sub, ctx->stream)).code) return e;
+    if ((e = upload(W->d_wg_rank, W->wg_rank, ctx->stream)).code) return e;
+    if ((e = upload(W->d_wg_s0, W->wg_s0, ctx->stream)).code) return e;
+    if ((e = upload(W->d_wg_s1, W->wg_s1, ctx->stream)).code) return e;
+    if ((e = upload(W->d_sub_pbase, W->sub_pbase, ctx->stream)).code) return e;
+    if ((e = upload(W->d_sub_nwg, W->sub_nwg, ctx->stream)).code) return e;
+    if ((e = dev_alloc(P->d_partial, (size_t)pb * 8 * 8)).code) return e;
+    *fits = true;
+    return Error{PGCP_OK, ""};
 }
 
 template <typename T>
-static const void* pcg_kernel(int R) {
-    switch (R) {
-        case 1: return pcg_kernel_ptr<T, 1>();
-        case 2: return pcg_kernel_ptr<T, 2>();
-        case 4: return pcg_kernel_ptr<T, 4>();
-        case 8: return pcg_kernel_ptr<T, 8>();
-        default: return pcg_kernel_ptr<T, 16>();
-    }
+static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, int coupled, int max_iter,
+                         const T* val, const T* diag) {
+    using V2 = typename Vec2<T>::type;
+    CGArgs<T> a;
+    a.sl_ptr = (const int64_t*)P->d_sl_ptr.p;
+    a.sl_w = (const int32_t*)P->d_sl_w.p;
+    a.sl_col = (const int32_t*)P->d_sl_col.p;
+    a.val = val;
+    a.diag = diag;
+    a.rprev = (const int32_t*)P->d_row_prev.p;
+    a.rnext = (const int32_t*)P->d_row_next.p;
+    a.mask = mask;
+    a.wg_sub = (const int32_t*)W.d_wg_sub.p;
+    a.wg_rank = (const int32_t*)W.d_wg_rank.p;
+    a.wg_s0 = (const int32_t*)W.d_wg_s0.p;
+    a.wg_s1 = (const int32_t*)W.d_wg_s1.p;
+    a.sub_pbase = (const int32_t*)W.d_sub_pbase.p;
+    a.sub_nwg = (const int32_t*)W.d_sub_nwg.p;
+    a.active = (const int32_t*)P->d_active.p;
+    a.target_rel2 = (const double*)P->d_target.p;
+    a.e = (V2*)P->d_e.p;
+    a.r = (V2*)P->d_r.p;
+    a.z = (V2*)P->d_z.p;
+    a.pa = (V2*)P->d_p0.p;
+    a.pb = (V2*)P->d_p1.p;
+    a.partial = (double*)P->d_partial.p;
+    a.bar = (unsigned*)P->d_bar.p;
+    a.abort_flag = (int*)P->d_abort.p;
+    a.iters = (int32_t*)P->d_iters.p;
+    a.rr_out = (double*)P->d_rrout.p;
+    a.status = (int32_t*)P->d_status.p;
+    a.coupled = coupled;
+    a.max_iter = max_iter;
+    a.n_xcd = W.n_xcd;
+    a.stall = 600;
+    return a;
 }
 
-// Build (or reuse) the workgroup map for precision prec (0 double, 1 float):
-// the smallest rows-per-thread R whose grid fits the co-resident capacity.
-static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec) {
-    if (P->wmap_prec == prec) return Error{PGCP_OK, ""};
-    int dev = ctx->device;
-    int n_cu = 0;
-    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    int coop = 0;
-    HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-    if (!coop) return Error{PGCP_E_HIP, "device does not support cooperative launches"};
-    WorkMap& W = P->wmap;
-    for (int R : {1, 2, 4, 8, 16}) {
-        int per_cu = 0;
-        const void* kern = prec == 0 ? pcg_kernel<double>(R) : pcg_kernel<float>(R);
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, 0));
-        int64_t cap = (int64_t)per_cu * n_cu;
-        int64_t slices_per_wg = (int64_t)WAVES * R;
-        int64_t G = 0;
-        for (int i = 0; i < P->K; ++i) {
-            int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
-            G += std::max<int64_t>(1, (ns + slices_per_wg - 1) / slices_per_wg);
-        }
-        if (G > cap && R < 16) continue;
-        if (G > cap) return Error{PGCP_E_INVALID, "problem too large for one cooperative launch"};
-        W.rows_per_thread = R;
-        W.n_wg = (int)G;
-        W.wg_sub.clear();
-        W.wg_s0.clear();
-        W.wg_s1.clear();
-        W.sub_wg0.assign(P->K, 0);
-        W.sub_nwg.assign(P->K, 0);
-        for (int i = 0; i < P->K; ++i) {
-            int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
-            int64_t nw = std::max<int64_t>(1, (ns + slices_per_wg - 1) / slices_per_wg);
-            W.sub_wg0[i] = (int32_t)W.wg_sub.size();
-            W.sub_nwg[i] = (int32_t)nw;
-            for (int64_t t = 0; t < nw; ++t) {
-                W.wg_sub.push_back(i);
-                W.wg_s0.push_back((int32_t)(sb + ns * t / nw));
-                W.wg_s1.push_back((int32_t)(sb + ns * (t + 1) / nw));
-            }
-        }
-        Error e{PGCP_OK, ""};
-        if ((e = upload(W.d_wg_sub, W.wg_sub, ctx->stream)).code) return e;
-        if ((e = upload(W.d_wg_s0, W.wg_s0, ctx->stream)).code) return e;
-        if ((e = upload(W.d_wg_s1, W.wg_s1, ctx->stream)).code) return e;
-        if ((e = upload(W.d_sub_wg0, W.sub_wg0, ctx->stream)).code) return e;
-        if ((e = upload(W.d_sub_nwg, W.sub_nwg, ctx->stream)).code) return e;
-        size_t need = (size_t)G * 8 * 8;
-        if (P->d_partial.bytes < need)
-            if ((e = dev_alloc(P->d_partial, need)).code) return e;
-        P->wmap_prec = prec;
-        return Error{PGCP_OK, ""};
+static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
+    if (prec) {
+        k_prep_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                              (const double2*)P->d_r64.p,
+                                                              (const double*)P->d_scale.p, (float2*)P->d_r.p,
+                                                              (float2*)P->d_e.p);
+    } else {
+        k_prep_inner<double><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
+                                                               (const double2*)P->d_r64.p,
+                                                               (const double*)P->d_scale.p, (double2*)P->d_r.p,
+                                                               (double2*)P->d_e.p);
     }
-    return Error{PGCP_E_INVALID, "no work map"};
+    k_zero_u32<<<grid_for(P->K), BLOCK, 0, s>>>(P->K, (unsigned*)P->d_bar.p);
+    k_zero_u32<<<1, 64, 0, s>>>(16, (unsigned*)P->d_abort.p);
+    HIPCHK(hipGetLastError());
+    return Error{PGCP_OK, ""};
+}
+
+static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t* mask, int coupled, int max_iter,
+                        int stall, hipStream_t s) {
+    dim3 grid(W.n_wg), block(W.blk);
+    if (prec) {
+        CGArgs<float> a = cg_args<float>(P, W, mask, coupled, max_iter, (const float*)P->d_val32.p,
+                                         (const float*)P->d_diag32.p);
+        a.stall = stall;
+        void* args[] = {&a};
+        HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
+                                          (size_t)W.blk * W.rows_per_thread * 8, s));
+    } else {
+        CGArgs<double> a = cg_args<double>(P, W, mask, coupled, max_iter, (const double*)P->d_val64.p,
+                                           (const double*)P->d_diag64.p);
+        a.stall = stall;
+        void* args[] = {&a};
+        HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
+                                          (size_t)W.blk * W.rows_per_thread * 16, s));
+    }
+    return Error{PGCP_OK, ""};
+}
+
+// Choose the launch shape: PGCP_PCG_CFG="blk,R" forces one; otherwise every
+// shape that fits is timed for a few iterations on the real batch (the first
+// time a plan solves in a precision) and the fastest per iteration is kept.
+static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t* mask, int coupled) {
+    WorkMap& W = prec ? P->wmap32 : P->wmap64;
+    if (W.n_wg > 0) return Error{PGCP_OK, ""};
+    hipStream_t s = ctx->stream;
+    const char* force = getenv("PGCP_PCG_CFG");
+    if (force) {
+        PcgCfg c{256, 1};
+        if (sscanf(force, "%d,%d", &c.blk, &c.R) == 2) {
+            bool fits;
+            Error e = build_workmap(ctx, P, prec, c, &W, &fits);
+            if (e.code) return e;
+            if (fits) return Error{PGCP_OK, ""};
+        }
+    }
+    const char* tune = getenv("PGCP_TUNE");
+    const bool do_tune = !(tune && tune[0] == '0');
+    float best_ms = 1e30f;
+    PcgCfg best{0, 0};
+    const int probe_iters = 40;
+    for (const PcgCfg& c : kPcgCfgs) {
+        WorkMap T;
+        bool fits;
+        Error e = build_workmap(ctx, P, prec, c, &T, &fits);
+        if (e.code) return e;
+        if (!fits) continue;
+        if (!do_tune) {
+            best = c;
+            break;
+        }
+        if ((e = prep_inner(P, prec, s)).code) return e;
+        HIPCHK(hipEventRecord(P->ev0, s));
+        if ((e = launch_pcg(P, T, prec, mask, coupled, probe_iters, 1 << 30, s)).code) return e;
+        HIPCHK(hipEventRecord(P->ev1, s));
+        HIPCHK(hipEventSynchronize(P->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, P->ev0, P->ev1));
+        int ab = 0;
+        HIPCHK(hipMemcpy(&ab, P->d_abort.p, 4, hipMemcpyDeviceToHost));
+        if (ab) return Error{PGCP_E_HIP, "batched CG barrier timed out while tuning"};
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
+            dev_free(*b);
+    }
+    if (best.blk == 0) return Error{PGCP_E_INVALID, "problem too large for one cooperative launch"};
+    bool fits;
+    Error e = build_workmap(ctx, P, prec, best, &W, &fits);
+    if (e.code) return e;
+    return Error{PGCP_OK, ""};
 }
 
 // Iterative refinement driver.  u64 holds the Dirichlet values on masked rows
@@ -1096,10 +1392,15 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     const double inner_tol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
     const int max_iter = (o && o->max_iter > 0) ? o->max_iter : 20000;
     const int max_refine = (o && o->max_refine > 0) ? o->max_refine : 30;
-    Error e = build_workmap(ctx, P, prec);
-    if (e.code) return e;
-    const WorkMap& W = P->wmap;
-    const int R = W.rows_per_thread;
+    const int stall = (o && o->stall_iters > 0) ? o->stall_iters : 4000;
+    const char* vb = getenv("PGCP_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
+    if (!P->ev0) {
+        HIPCHK(hipEventCreate(&P->ev0));
+        HIPCHK(hipEventCreate(&P->ev1));
+    }
+    Error e{PGCP_OK, ""};
+    const WorkMap& W = prec ? P->wmap32 : P->wmap64;
 
     std::vector<double> bnorm(2 * K, 0.0), rnorm(2 * K, 0.0), scale(2 * K, 0.0), target(2 * K, 0.0);
     std::vector<int32_t> active(K, 0), iters(K, 0), status(K, 0), it_total(K, 0), fail(K, 0);
@@ -1109,10 +1410,6 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     bool all_conv = false;
     double cg_ms = 0.0, cg_bytes = 0.0;
     int cg_launches = 0;
-    if (!P->ev0) {
-        HIPCHK(hipEventCreate(&P->ev0));
-        HIPCHK(hipEventCreate(&P->ev1));
-    }
     // algorithmic bytes of one CG iteration of piece i: matrix values + column
     // indices once, and per row z, p_old read, p_new written (phase A), e and r
     // read+written, z written (phase B), the diagonal twice and the mask twice.
@@ -1161,6 +1458,12 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
                 target[2 * i + c] = std::min(need, 1.0);
             }
         }
+        if (verbose) {
+            double worst = 0.0;
+            for (int i = 0; i < K; ++i) worst = std::max(worst, std::max(relres[2 * i], relres[2 * i + 1]));
+            fprintf(stderr, "[pgcp] %s %s pass %d: active %d/%d worst relres %.3e\n", coupled ? "dncp" : "harmonic",
+                    prec ? "fp32" : "fp64", outer, n_active, K, worst);
+        }
         if (n_active == 0) {
             all_conv = true;
             break;
@@ -1169,53 +1472,12 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         HIPCHK(hipMemcpyAsync(P->d_active.p, active.data(), K * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(P->d_scale.p, scale.data(), 2 * K * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(P->d_target.p, target.data(), 2 * K * 8, hipMemcpyHostToDevice, s));
-        k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_bar.p);
-        k_zero_u32<<<1, 64, 0, s>>>(16, (unsigned*)P->d_abort.p);
-        HIPCHK(hipGetLastError());
-        if (prec) {
-            k_prep_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
-                                                                  (const double2*)P->d_r64.p,
-                                                                  (const double*)P->d_scale.p, (float2*)P->d_r.p,
-                                                                  (float2*)P->d_e.p);
-        } else {
-            k_prep_inner<double><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
-                                                                   (const double2*)P->d_r64.p,
-                                                                   (const double*)P->d_scale.p, (double2*)P->d_r.p,
-                                                                   (double2*)P->d_e.p);
-        }
-        HIPCHK(hipGetLastError());
-        dim3 grid(W.n_wg), block(BLOCK);
-        if (prec) {
-            CGArgs<float> a{(const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
-                            (const float*)P->d_val32.p, (const float*)P->d_diag32.p,
-                            (const int32_t*)P->d_row_prev.p, (const int32_t*)P->d_row_next.p, mask,
-                            (const int32_t*)W.d_wg_sub.p, (const int32_t*)W.d_wg_s0.p, (const int32_t*)W.d_wg_s1.p,
-                            (const int32_t*)W.d_sub_wg0.p, (const int32_t*)W.d_sub_nwg.p,
-                            (const int32_t*)P->d_active.p, (const double*)P->d_target.p, (float2*)P->d_e.p,
-                            (float2*)P->d_r.p, (float2*)P->d_z.p, (float2*)P->d_p0.p, (float2*)P->d_p1.p,
-                            (double*)P->d_partial.p, (unsigned*)P->d_bar.p, (int*)P->d_abort.p,
-                            (int32_t*)P->d_iters.p, (double*)P->d_rrout.p, (int32_t*)P->d_status.p, coupled,
-                            max_iter};
-            void* args[] = {&a};
-            HIPCHK(hipEventRecord(P->ev0, s));
-            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(R), grid, block, args, 0, s));
-            HIPCHK(hipEventRecord(P->ev1, s));
-        } else {
-            CGArgs<double> a{(const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
-                             (const double*)P->d_val64.p, (const double*)P->d_diag64.p,
-                             (const int32_t*)P->d_row_prev.p, (const int32_t*)P->d_row_next.p, mask,
-                             (const int32_t*)W.d_wg_sub.p, (const int32_t*)W.d_wg_s0.p, (const int32_t*)W.d_wg_s1.p,
-                             (const int32_t*)W.d_sub_wg0.p, (const int32_t*)W.d_sub_nwg.p,
-                             (const int32_t*)P->d_active.p, (const double*)P->d_target.p, (double2*)P->d_e.p,
-                             (double2*)P->d_r.p, (double2*)P->d_z.p, (double2*)P->d_p0.p, (double2*)P->d_p1.p,
-                             (double*)P->d_partial.p, (unsigned*)P->d_bar.p, (int*)P->d_abort.p,
-                             (int32_t*)P->d_iters.p, (double*)P->d_rrout.p, (int32_t*)P->d_status.p, coupled,
-                             max_iter};
-            void* args[] = {&a};
-            HIPCHK(hipEventRecord(P->ev0, s));
-            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(R), grid, block, args, 0, s));
-            HIPCHK(hipEventRecord(P->ev1, s));
-        }
+        // launch shape: chosen once per plan and precision, on this residual
+        if ((e = choose_workmap(ctx, P, prec, mask, coupled)).code) return e;
+        if ((e = prep_inner(P, prec, s)).code) return e;
+        HIPCHK(hipEventRecord(P->ev0, s));
+        if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s)).code) return e;
+        HIPCHK(hipEventRecord(P->ev1, s));
         if (prec) {
             k_apply_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
                                                                    (const int32_t*)P->d_active.p,
@@ -1238,6 +1500,16 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         HIPCHK(hipEventElapsedTime(&ms, P->ev0, P->ev1));
         cg_ms += ms;
         cg_launches++;
+        if (verbose) {
+            int mx = 0, nst[5] = {0, 0, 0, 0, 0};
+            for (int i = 0; i < K; ++i)
+                if (active[i]) {
+                    mx = std::max(mx, iters[i]);
+                    nst[std::min(std::max(status[i], 0), 4)]++;
+                }
+            fprintf(stderr, "[pgcp]   cg launch %.2f ms, max iters %d, status ok/brk/maxit/abort/stall %d/%d/%d/%d/%d\n",
+                    ms, mx, nst[0], nst[1], nst[2], nst[3], nst[4]);
+        }
         for (int i = 0; i < K; ++i) {
             if (!active[i]) continue;
             it_total[i] += iters[i];
@@ -1267,8 +1539,9 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         st->cg_kernel_ms = cg_ms;
         st->cg_bytes = cg_bytes;
         st->cg_launches = cg_launches;
-        st->rows_per_thread = R;
+        st->rows_per_thread = W.rows_per_thread;
         st->cg_workgroups = W.n_wg;
+        st->cg_block = W.blk;
     }
     if (noconv) return Error{PGCP_E_NOCONV, "some piece missed the residual tolerance"};
     return Error{PGCP_OK, ""};

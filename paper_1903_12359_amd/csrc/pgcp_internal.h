@@ -30,11 +30,14 @@ struct DevBuf {
 // A device-side work assignment for the persistent batched CG: each workgroup
 // owns a contiguous range of 64-row slices of exactly one piece.
 struct WorkMap {
-    int rows_per_thread = 0;     // R
-    int n_wg = 0;                // grid size
-    std::vector<int32_t> wg_sub, wg_s0, wg_s1;   // per workgroup
-    std::vector<int32_t> sub_wg0, sub_nwg;       // per piece
-    DevBuf d_wg_sub, d_wg_s0, d_wg_s1, d_sub_wg0, d_sub_nwg;
+    int blk = 0;                 // threads per workgroup
+    int rows_per_thread = 0;     // 64-row slices per wave
+    int n_xcd = 1;
+    int n_wg = 0;                // grid size (0 = not built)
+    int n_partials = 0;
+    std::vector<int32_t> wg_sub, wg_rank, wg_s0, wg_s1;   // per workgroup
+    std::vector<int32_t> sub_pbase, sub_nwg;              // per piece
+    DevBuf d_wg_sub, d_wg_rank, d_wg_s0, d_wg_s1, d_sub_pbase, d_sub_nwg;
 };
 
 }  // namespace pgcp
@@ -90,8 +93,7 @@ struct pgcp_part {
     pgcp::DevBuf d_partial, d_bar, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
-    pgcp::WorkMap wmap;
-    int wmap_prec = -1;
+    pgcp::WorkMap wmap32, wmap64;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     bool assembled = false;

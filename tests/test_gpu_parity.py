@@ -194,3 +194,53 @@ def test_call_order_errors(ctx):
     with pytest.raises(pg.PGCPError) as ei:
         pg.local_param(ctx, plan)
     assert ei.value.status == "INVALID"
+
+
+@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8"])
+def test_forced_launch_shapes(ctx, cfg, monkeypatch):
+    """Every launch shape, with pieces spread over several workgroups, gives the oracle's answer."""
+    import paper_1903_12359_amd as pg
+    monkeypatch.setenv("PGCP_PCG_CFG", cfg)
+    case = case_c2(n=160)
+    say("forced shape", cfg)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    bdy, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13)
+    assert f"{rep.cg_block},{rep.rows_per_thread}" == cfg
+    part, subs = prepare(case.V, case.F, case.label)
+    ob = np.concatenate(local_params(subs))
+    g = bdy.cpu().numpy()
+    err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+    say("  workgroups", rep.cg_workgroups, "err", err)
+    assert err <= 1e-9
+    b2, _ = pg.local_param(ctx, plan, precision="fp64", tol=1e-13)
+    assert np.array_equal(b2.cpu().numpy(), g)
+
+
+def test_c2_full_size_stagewise(ctx):
+    """C2 at full size (512^2 vertices, 16 pieces): DNCP and harmonic against the oracle."""
+    import paper_1903_12359_amd as pg
+    case = case_c2()
+    say("C2 full: oracle")
+    part, subs, bdy, welded = _oracle_stages(case)
+    vals, _ = harmonic_all(subs, welded, case.mode)
+    from oracle.pipeline import assemble
+    phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+    ob = np.concatenate(bdy)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    # full-size pieces (16.6k vertices) are too ill-conditioned for CG to reach
+    # 1e-13 in FP64; 1e-12 is the parity setting here
+    for prec, tol, bound in (("fp64", 1e-12, 1e-9), ("fp32", 1e-11, 1e-6)):
+        say("C2 full:", prec)
+        b, rep = pg.local_param(ctx, plan, precision=prec, tol=tol)
+        g = b.cpu().numpy()
+        err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+        say("  dncp err", err, "iters", rep.total_iters)
+        assert err <= bound
+        seam = plan.export()["seam_gv"]
+        w = np.array([welded[int(v)] for v in seam])
+        phi, rep = pg.harmonic_solve(ctx, plan, _dev(np.column_stack([w.real, w.imag])), precision=prec, tol=tol)
+        err = np.abs(phi.cpu().numpy() - phi_o).max() / np.abs(phi_o).max()
+        say("  harmonic err", err, "iters", rep.total_iters)
+        assert err <= bound
