@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the pieces of one mesh are solved in one batched launch on a "
@@ -84,7 +86,12 @@ def main():
     V_dev = torch.from_numpy(case.V).to(dev)
     F_dev = torch.from_numpy(case.F.astype(np.int32)).to(dev)
     ctx = pg.Context(0)
-    stream = torch.cuda.current_stream()
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         times = {}

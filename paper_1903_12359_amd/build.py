@@ -3,7 +3,9 @@
     python -m paper_1903_12359_amd.build
 
 Device code is compiled with packed FP32 instructions disabled.  Host C++
-(partition, weld, C ABI) uses OpenMP.
+(partition, weld, C ABI) uses OpenMP.  The weld uses plain complex multiply
+and divide (-fcx-limited-range): every point at infinity is carried as an
+explicit flag, so no operation there meets an infinite or NaN operand.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-fopenmp", "-Wno-unused-result"]
 DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics"]
 HOST_SOURCES = ["partition.cpp", "weld.cpp", "api.cpp"]
+HOST_EXTRA = {"weld.cpp": ["-fcx-limited-range"]}
 DEVICE_SOURCES = ["device.hip"]
 
 
@@ -47,7 +50,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
-        _run([hipcc, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([hipcc, *COMMON, *HOST_EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fopenmp", f"--offload-arch={ARCH}", "-o", tmp, *objs])

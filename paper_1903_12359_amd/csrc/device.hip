@@ -1338,6 +1338,15 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             if (fits) return Error{PGCP_OK, ""};
         }
     }
+    std::string key = std::to_string(prec) + ":" + std::to_string(coupled) + ":" + std::to_string(P->K);
+    for (int i = 0; i < P->K; ++i) key += "," + std::to_string((P->row0[i + 1] - P->row0[i]) / 64);
+    auto hit = ctx->tuned.find(key);
+    if (hit != ctx->tuned.end()) {
+        bool fits;
+        Error e = build_workmap(ctx, P, prec, PcgCfg{hit->second.first, hit->second.second}, &W, &fits);
+        if (e.code) return e;
+        if (fits) return Error{PGCP_OK, ""};
+    }
     const char* tune = getenv("PGCP_TUNE");
     const bool do_tune = !(tune && tune[0] == '0');
     float best_ms = 1e30f;
@@ -1374,6 +1383,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     bool fits;
     Error e = build_workmap(ctx, P, prec, best, &W, &fits);
     if (e.code) return e;
+    ctx->tuned[key] = {best.blk, best.R};
     return Error{PGCP_OK, ""};
 }
 

@@ -9,7 +9,10 @@
 // each must be a topological disk.
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "pgcp_internal.h"
@@ -42,6 +45,16 @@ Error topo(const std::string& m) { return Error{PGCP_E_TOPOLOGY, m}; }
 
 Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, int64_t nf,
                  const int32_t* label, int mode) {
+    const char* vb = getenv("PGCP_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
+    auto t_last = std::chrono::steady_clock::now();
+    auto lap = [&](const char* what) {
+        if (!verbose) return;
+        auto t = std::chrono::steady_clock::now();
+        fprintf(stderr, "[pgcp] partition %-12s %8.2f ms\n", what,
+                std::chrono::duration<double, std::milli>(t - t_last).count());
+        t_last = t;
+    };
     if (nv <= 0 || nf <= 0 || nv > INT32_MAX / 2 || nf > INT32_MAX / 4)
         return Error{PGCP_E_INVALID, "mesh size out of range"};
     if (mode < 0 || mode > 2) return Error{PGCP_E_INVALID, "bad mode"};
@@ -55,47 +68,40 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         if (a == b || b == c || a == c) return topo("face with a repeated vertex");
     }
 
-    // ---- half-edge twins by counting sort on the smaller endpoint
+    // ---- half-edge twins: outgoing half-edges of every vertex (CSR by source),
+    // then the twin of a->b is the b->a entry in b's list.
     const int64_t nh = 3 * nf;
+    auto he_b = [&](int64_t h) { return F[(h / 3) * 3 + (h % 3 + 1) % 3]; };
     std::vector<int64_t> cnt(nv + 1, 0);
-    for (int64_t h = 0; h < nh; ++h) {
-        int32_t a = F[h], b = F[(h / 3) * 3 + (h % 3 + 1) % 3];
-        cnt[std::min(a, b) + 1]++;
-    }
+    for (int64_t h = 0; h < nh; ++h) cnt[F[h] + 1]++;
     for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
-    std::vector<int32_t> bucket(nh);
+    std::vector<int32_t> out_h(nh);
     {
         std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        for (int64_t h = 0; h < nh; ++h) {
-            int32_t a = F[h], b = F[(h / 3) * 3 + (h % 3 + 1) % 3];
-            bucket[fill[std::min(a, b)]++] = (int32_t)h;
-        }
+        for (int64_t h = 0; h < nh; ++h) out_h[fill[F[h]]++] = (int32_t)h;
     }
-    auto he_a = [&](int64_t h) { return F[h]; };
-    auto he_b = [&](int64_t h) { return F[(h / 3) * 3 + (h % 3 + 1) % 3]; };
     std::vector<int32_t> twin(nh, -1);
-    for (int64_t v = 0; v < nv; ++v) {
-        int64_t s = cnt[v], e = cnt[v + 1];
-        // group by the larger endpoint (buckets are tiny: the vertex degree)
-        for (int64_t i = s; i < e; ++i) {
-            int32_t hi = std::max(he_a(bucket[i]), he_b(bucket[i]));
-            int found = 0;
-            int32_t other = -1;
-            for (int64_t j = s; j < e; ++j) {
-                if (j == i) continue;
-                if (std::max(he_a(bucket[j]), he_b(bucket[j])) == hi) {
-                    found++;
-                    other = bucket[j];
-                }
+    int bad_nm = 0, bad_or = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad_nm, bad_or)
+    for (int64_t h = 0; h < nh; ++h) {
+        const int32_t a = F[h], b = he_b(h);
+        int found = 0;
+        int32_t t = -1;
+        for (int64_t q = cnt[b]; q < cnt[b + 1]; ++q)
+            if (he_b(out_h[q]) == a) {
+                found++;
+                t = out_h[q];
             }
-            if (found > 1) return topo("non-manifold edge (more than two faces)");
-            if (found == 1) {
-                if (he_a(other) == he_a(bucket[i])) return topo("inconsistently oriented faces");
-                twin[bucket[i]] = other;
-            }
-        }
+        int same = 0;
+        for (int64_t q = cnt[a]; q < cnt[a + 1]; ++q)
+            if (he_b(out_h[q]) == b) same++;
+        if (same > 1) bad_or++;              // two half-edges a->b: faces disagree on orientation
+        if (found > 1 || found + same > 2) bad_nm++;
+        if (found == 1) twin[h] = t;
     }
-
+    if (bad_or) return topo("inconsistently oriented faces");
+    if (bad_nm) return topo("non-manifold edge (more than two faces)");
+    lap("twins");
     // ---- pieces: components of the face graph over uncut interior edges
     UnionFind uf(nf);
     for (int64_t h = 0; h < nh; ++h) {
@@ -162,6 +168,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         for (int64_t s = P->row0[i] / 64; s < P->row0[i + 1] / 64; ++s) P->slice_sub[s] = i;
     }
 
+    lap("pieces");
     // corner -> packed row
     std::vector<int32_t> corner_row(nh);
 #pragma omp parallel for schedule(dynamic)
@@ -177,6 +184,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         }
     }
 
+    lap("rows");
     // ---- boundary loops, Euler characteristic, pins
     std::vector<std::vector<int32_t>> loops(K);   // packed rows, CCW
     std::vector<std::string> emsg(K);
@@ -275,27 +283,34 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         P->loop_seam[e] = (int32_t)(std::lower_bound(P->seam_gv.begin(), P->seam_gv.end(),
                                                      P->loop_gv[e]) - P->seam_gv.begin());
 
+    lap("loops");
     // ---- off-diagonal structure with opposite vertices, per row
     // each corner (k of face (i,j,k)) contributes entries i->j and j->i with
     // opposite vertex k.
     std::vector<int32_t> deg_raw(N, 0);
-    for (int64_t h = 0; h < nh; ++h) {
-        deg_raw[corner_row[h]] += 2;
-    }
+#pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < K; ++i)
+        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t)
+            for (int c = 0; c < 3; ++c) deg_raw[corner_row[3 * (int64_t)faces[t] + c]] += 2;
     std::vector<int64_t> rptr(N + 1, 0);
     for (int64_t r = 0; r < N; ++r) rptr[r + 1] = rptr[r] + deg_raw[r];
     std::vector<int32_t> ent_col(rptr[N]), ent_opp(rptr[N]);
     {
         std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
-        for (int64_t f = 0; f < nf; ++f) {
-            for (int c = 0; c < 3; ++c) {
-                int32_t ri = corner_row[3 * f + (c + 1) % 3];
-                int32_t rj = corner_row[3 * f + (c + 2) % 3];
-                int32_t gk = F[3 * f + c];
-                ent_col[fill[ri]] = rj;
-                ent_opp[fill[ri]++] = gk;
-                ent_col[fill[rj]] = ri;
-                ent_opp[fill[rj]++] = gk;
+        // rows of different pieces are disjoint: fill piece by piece in parallel
+#pragma omp parallel for schedule(dynamic)
+        for (int i = 0; i < K; ++i) {
+            for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
+                const int64_t f = faces[t];
+                for (int c = 0; c < 3; ++c) {
+                    int32_t ri = corner_row[3 * f + (c + 1) % 3];
+                    int32_t rj = corner_row[3 * f + (c + 2) % 3];
+                    int32_t gk = F[3 * f + c];
+                    ent_col[fill[ri]] = rj;
+                    ent_opp[fill[ri]++] = gk;
+                    ent_col[fill[rj]] = ri;
+                    ent_opp[fill[rj]++] = gk;
+                }
             }
         }
     }
@@ -334,6 +349,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     }
     if (bad_edge) return topo("edge with more than two faces inside a piece");
 
+    lap("entries");
     // ---- SELL-64 layout
     P->sl_ptr.assign(P->nslices + 1, 0);
     P->sl_w.assign(P->nslices, 0);
@@ -372,6 +388,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         }
     }
 
+    lap("sell");
     // ---- weld merge tree (depends on the loops only)
     std::vector<std::vector<int>> gl(K);
     std::vector<int64_t> sizes(K);
@@ -386,6 +403,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     } else if (mode == PGCP_SPHERE) {
         return Error{PGCP_E_WELD, "sphere mode needs at least two pieces"};
     }
+    lap("merge plan");
     P->chart.assign(K, cplx(0.0, 0.0));
     P->chart_inf.assign(K, 0);
     return Error{PGCP_OK, ""};

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <map>
 #include <cstdint>
 #include <string>
 #include <utility>
@@ -48,6 +49,9 @@ struct pgcp_ctx {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     std::string last_error;
+    // autotuned batched-CG launch shapes, keyed by precision, system kind and
+    // the per-piece slice counts of the plan: (threads per workgroup, slices per wave)
+    std::map<std::string, std::pair<int, int>> tuned;
 };
 
 struct pgcp_part {

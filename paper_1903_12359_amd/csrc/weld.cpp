@@ -38,7 +38,20 @@ struct EP {
     bool inf;
 };
 
-inline cplx csqrt_principal(cplx w) { return std::sqrt(w); }
+// Principal square root (Re >= 0; on the negative real axis the sign of the
+// imaginary zero picks the half, as for the C library's csqrt).  Plain
+// formula: the weld's values stay far from overflow.
+inline cplx csqrt_principal(cplx w) {
+    const double x = w.real(), y = w.imag();
+    const double r = std::sqrt(x * x + y * y);
+    if (r == 0.0) return cplx(0.0, y);
+    if (x >= 0.0) {
+        const double t = std::sqrt(0.5 * (r + x));
+        return cplx(t, y / (2.0 * t));
+    }
+    const double t = std::sqrt(0.5 * (r - x));
+    return cplx(std::fabs(y) / (2.0 * t), std::copysign(t, y));
+}
 
 struct Component {
     std::vector<int> outer;       // CCW loop, global ids
@@ -87,6 +100,7 @@ ZipRecord zip_arc(std::vector<EP>& arc, int k, int branch, bool squared) {
         double c = xi.real() / r2, d = xi.imag() / r2;
         R.c[j - 2] = c;
         R.d[j - 2] = d;
+#pragma omp parallel for schedule(static) if (k >= 384)
         for (int l = 0; l <= k; ++l) {
             if (l == j - 1) {
                 arc[l] = EP{cplx(0.0, (double)branch), false};
@@ -96,26 +110,38 @@ ZipRecord zip_arc(std::vector<EP>& arc, int k, int branch, bool squared) {
                 arc[l] = EP{0.0, false};
                 continue;
             }
-            // L_xi(z) = c z / (1 + i d z)
-            cplx L;
-            bool Linf = false;
-            if (arc[l].inf) {
-                if (d != 0.0) L = cplx(0.0, -c / d);
-                else Linf = true;
-            } else {
-                cplx den = 1.0 + cplx(0.0, d) * arc[l].z;
-                if (den == cplx(0.0, 0.0)) Linf = true;
-                else L = c * arc[l].z / den;
-            }
-            if (Linf) {
-                arc[l] = EP{0.0, true};
-            } else if (l < j - 1) {
-                double s = L.imag();
-                double sg = (s > 0.0) ? 1.0 : (s < 0.0 ? -1.0 : 0.0);
+            if (l < j - 1) {
+                // zipped: z = i t on the imaginary axis, L = i c t / (1 - d t)
+                if (arc[l].inf) {
+                    if (d == 0.0) continue;   // L(inf) = inf stays inf
+                    const double s = -c / d;
+                    arc[l] = EP{cplx(0.0, (s > 0 ? 1.0 : -1.0) * std::sqrt(s * s + 1.0)), false};
+                    continue;
+                }
+                const double t = arc[l].z.imag(), den = 1.0 - d * t;
+                if (den == 0.0) {
+                    arc[l] = EP{0.0, true};
+                    continue;
+                }
+                const double s = c * t / den;
+                const double sg = (s > 0.0) ? 1.0 : (s < 0.0 ? -1.0 : 0.0);
                 arc[l] = EP{cplx(0.0, sg * std::sqrt(s * s + 1.0)), false};
-            } else {
-                arc[l] = EP{csqrt_principal(L * L - 1.0), false};
+                continue;
             }
+            // not yet zipped: L_xi(z) = c z / (1 + i d z), principal sqrt(L^2 - 1)
+            if (arc[l].inf) {
+                if (d == 0.0) continue;
+                const cplx L = cplx(0.0, -c / d);
+                arc[l] = EP{csqrt_principal(L * L - 1.0), false};
+                continue;
+            }
+            const cplx den = 1.0 + cplx(0.0, d) * arc[l].z;
+            if (den == cplx(0.0, 0.0)) {
+                arc[l] = EP{0.0, true};
+                continue;
+            }
+            const cplx L = c * arc[l].z / den;
+            arc[l] = EP{csqrt_principal(L * L - 1.0), false};
         }
     }
     // final map z / (1 - z / zeta)
@@ -221,27 +247,43 @@ CloseRecord close_arcs(std::vector<EP>& A, std::vector<EP>& B, int k) {
         if (!(c0 > 0.0)) throw Error{PGCP_E_WELD, "glued pair out of cyclic order"};
         R.c0.push_back(c0);
         R.c1.push_back(c1);
-        for (auto* S : {&A, &B}) {
-            auto& X = *S;
-            for (int l = 0; l <= k; ++l) {
-                if (l == j) {
-                    X[l] = EP{0.0, false};
+#pragma omp parallel for schedule(static) if (k >= 384)
+        for (int m = 0; m < 2 * (k + 1); ++m) {
+            auto& X = m <= k ? A : B;
+            const int l = m <= k ? m : m - (k + 1);
+            if (l == j) {
+                X[l] = EP{0.0, false};
+                continue;
+            }
+            if (l < j && !X[l].inf) {
+                // unglued arc point on the imaginary axis: T(i u) = i u / (c0 + c1 u)
+                const double u = X[l].z.imag(), den = c0 + c1 * u;
+                if (den == 0.0) {
+                    X[l] = EP{0.0, true};
                     continue;
                 }
-                EP t = T_apply(c0, c1, X[l]);
-                if (t.inf) {
-                    X[l] = t;
-                } else if (l < j) {
-                    double s = t.z.imag();
-                    if (std::fabs(s) <= 1.0) {
-                        X[l] = EP{cplx(std::sqrt(1.0 - s * s), 0.0), false};
-                    } else {
-                        double sg = s > 0.0 ? 1.0 : -1.0;
-                        X[l] = EP{cplx(0.0, sg * std::sqrt(s * s - 1.0)), false};
-                    }
+                const double s = u / den;
+                if (std::fabs(s) <= 1.0) {
+                    X[l] = EP{cplx(std::sqrt(1.0 - s * s), 0.0), false};
                 } else {
-                    X[l] = EP{csqrt_principal(t.z * t.z + 1.0), false};
+                    const double sg = s > 0.0 ? 1.0 : -1.0;
+                    X[l] = EP{cplx(0.0, sg * std::sqrt(s * s - 1.0)), false};
                 }
+                continue;
+            }
+            EP t = T_apply(c0, c1, X[l]);
+            if (t.inf) {
+                X[l] = t;
+            } else if (l < j) {
+                const double s = t.z.imag();
+                if (std::fabs(s) <= 1.0) {
+                    X[l] = EP{cplx(std::sqrt(1.0 - s * s), 0.0), false};
+                } else {
+                    const double sg = s > 0.0 ? 1.0 : -1.0;
+                    X[l] = EP{cplx(0.0, sg * std::sqrt(s * s - 1.0)), false};
+                }
+            } else {
+                X[l] = EP{csqrt_principal(t.z * t.z + 1.0), false};
             }
         }
     }
