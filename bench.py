@@ -1,6 +1,6 @@
 """PGCP hot-path benchmark on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--workload c2|c1|c5]
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--workload c2|c1|c3|c5]
 
 One step is Algorithm 3 end to end on one synthetic mesh already resident in
 device memory (V, F; labels and the host copy of the connectivity for the
@@ -31,8 +31,16 @@ HBM_PEAK_GBS = 8000.0
 
 
 def make_case(name):
-    from synth import case_c1, case_c2, case_c5
-    return {"c1": case_c1, "c2": case_c2, "c5": case_c5}[name]()
+    from synth import case_c1, case_c2, case_c3, case_c5
+    return {"c1": case_c1, "c2": case_c2, "c3": case_c3, "c5": case_c5}[name]()
+
+
+def describe(case, n_sub):
+    if case.mode == "sphere":
+        return (f"{case.name}: level-{case.meta['level']} icosphere ({case.nv} vertices), radius perturbed by "
+                f"spherical harmonics l<=8, {n_sub} k-means pieces, sphere output")
+    n = case.meta.get("n", int(round(case.nv ** 0.5)))
+    return f"{case.name}: {n}^2-vertex bump height field, {n_sub} pieces, {case.mode} boundary"
 
 
 def cpu_baseline(workload: str, timeout: float = 600.0):
@@ -61,7 +69,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -138,8 +146,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64 (DNCP) + f32 CG with f64 refinement (harmonic)" if args.precision == "fp32" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{case.name}: {case.meta.get('n', '')}^2-vertex bump height field, "
-                               f"{info['dncp'].n_sub} pieces, {case.mode} boundary",
+        "config": {"workload": describe(case, info["dncp"].n_sub),
                    "nv": case.nv, "nf": case.nf, "pieces": info["dncp"].n_sub, "precision": args.precision,
                    "tol": args.tol, "preconditioner": "jacobi"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

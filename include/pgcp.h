@@ -85,12 +85,15 @@ typedef struct {
     int32_t* status;          /* in/out [n_sub] 0 = converged                         */
     double seconds;           /* out: wall time of the call                          */
     double cg_kernel_ms;      /* out: summed duration of the batched-CG launches (HIP events) */
-    double cg_bytes;          /* out: algorithmic bytes those launches move (see DESIGN)      */
+    double cg_bytes;          /* out: algorithmic bytes those launches move: per CG iteration and
+                                 row, its matrix entries (value + column index), its diagonal
+                                 entry and ten passes over the interleaved (x, y) vectors       */
     int32_t cg_launches;      /* out: number of batched-CG launches                    */
     int32_t rows_per_thread;  /* out: 64-row slices per wave of the batched-CG launch  */
     int32_t cg_workgroups;    /* out: workgroups of the batched-CG launch              */
     int32_t cg_block;         /* out: threads per workgroup of the batched-CG launch   */
-    int32_t reserved2;
+    int32_t cg_stream;        /* out: 1 if the launch streamed its vectors through memory
+                                 (rows beyond what registers of one cooperative grid hold) */
 } pgcp_solve_stats;
 
 /* Distortion statistics over all 3|F| angles (Table 5 of the paper). */
@@ -178,10 +181,13 @@ pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* part, const double* bdy_uv_host,
 /* Section 4.5.  Harmonic map of every piece with the welded boundary as
  * Dirichlet data (same L, boundary rows eliminated), batched CG; then the
  * global gather: interior vertices from their piece, seam vertices from the
- * weld.  Sphere mode solves each piece in its rotated chart and finishes with
- * the stereographic projection (2Re w, -2Im w, |w|^2-1)/(|w|^2+1).
- * welded_uv_dev [n_seam][2]; out_dev [nv][2] (free/disk) or [nv][3] (sphere).
- * Requires pgcp_assemble_cotan and pgcp_weld. */
+ * weld.  Sphere mode solves each piece in its own rotation chart
+ * w = (z - c)/(1 + conj(c) z), c = stereographic image of the normalised mean of
+ * the piece's welded boundary points on the sphere (computed on the device from
+ * welded_uv_dev), and finishes with the stereographic projection
+ * (2Re w, -2Im w, |w|^2-1)/(|w|^2+1).  welded_uv_dev [n_seam][2] (a point at
+ * infinity as an infinite coordinate); out_dev [nv][2] (free/disk) or [nv][3]
+ * (sphere).  Requires pgcp_assemble_cotan. */
 pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* part, const double* welded_uv_dev,
                                 const pgcp_solve_opts* opts, double* out_dev,
                                 pgcp_solve_stats* stats);

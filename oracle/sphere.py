@@ -41,23 +41,37 @@ def stereo(p: np.ndarray) -> np.ndarray:
 
 
 def chart_centre(wb: np.ndarray) -> complex:
+    """sigma of the normalised mean of sigma^{-1}(wb); infinity when that is the north pole."""
     P = inv_stereo(wb)
     m = P.mean(axis=0)
     m /= np.linalg.norm(m)
+    if not 1.0 - m[2] > 0.0:
+        return complex("inf")
     return complex(stereo(m[None, :])[0])
 
 
 def chart(z: np.ndarray, c: complex) -> np.ndarray:
+    """Rotation chart (z - c)/(1 + conj(c) z); for c = infinity the rotation -1/z."""
     z = np.asarray(z, dtype=np.complex128)
     out = np.empty_like(z)
     inf = ~np.isfinite(z)
+    if not np.isfinite(c):
+        out[~inf] = -1.0 / z[~inf]
+        out[inf] = 0.0
+        return out
     out[~inf] = (z[~inf] - c) / (1.0 + np.conj(c) * z[~inf])
     out[inf] = 1.0 / np.conj(c) if c != 0 else complex("inf")
     return out
 
 
 def chart_inv(w: np.ndarray, c: complex) -> np.ndarray:
+    """Inverse of `chart`: (w + c)/(1 - conj(c) w), or -1/w for c = infinity."""
     w = np.asarray(w, dtype=np.complex128)
+    if not np.isfinite(c):
+        out = np.full_like(w, complex("inf"))
+        nz = w != 0
+        out[nz] = -1.0 / w[nz]
+        return out
     den = 1.0 - np.conj(c) * w
     out = np.empty_like(w)
     z0 = den == 0

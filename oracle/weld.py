@@ -36,12 +36,15 @@ Points known to lie on the imaginary axis (by their index) are kept exactly on
 it; points known to be 0 or infinity are set exactly.
 
 Weld order (the paper only shows a three-piece example, and for the sphere
-welds "until two large components are left"): a balanced merge tree.  In each
-round disjoint pairs of components that share one contiguous boundary arc of
-at least 3 vertices are welded, smallest combined size first.  Welding a small
-piece onto a much larger union makes the normalisation below ill-conditioned
-(the two centres sit close together relative to the union) and the zipper
-crowds; pairs of similar size avoid that.  Sequences: A = the lower-id
+merges down to two big components before closing): a balanced merge tree.  In
+each round disjoint pairs of components that share one contiguous boundary arc
+of at least 3 vertices are welded.  Pairs sharing a long arc relative to their
+loops come first: a union glued along a short arc has a narrow neck, the zipper
+crowds points there, and a later weld through it breaks down in floating
+point.  Among equally fat pairs the smaller combined size goes first: welding
+a small piece onto a much larger union makes the normalisation below
+ill-conditioned (the two centres sit close together relative to the union).
+Sequences: A = the lower-id
 component's CCW outer loop starting at the arc's first vertex a_0, then its
 other tracked points, then the auxiliary points 0 and inf; B = the other
 component's loop traversed clockwise from a_0, then its other tracked points,
@@ -56,6 +59,8 @@ closed weld: Algorithm 2 with the arc equal to the whole loop (starting at its
 smallest global index), so every loop point is glued.
 """
 from __future__ import annotations
+
+from fractions import Fraction
 
 import numpy as np
 
@@ -325,9 +330,12 @@ def merge_plan(loops, sizes, mode):
     """Balanced weld order as rounds of disjoint pairs.
 
     Components start as the subdomains.  In each round every weldable pair
-    (one contiguous shared arc of >= 3 vertices) is a candidate; candidates are
-    taken greedily by smallest combined size (face count), then smallest ids,
-    with each component used at most once per round.  A merged component is
+    (one contiguous shared arc of >= 3 vertices) is a candidate.  Candidates
+    are taken greedily, each component at most once per round, in order of
+    decreasing fatness k / min(|loop_i|, |loop_j|) (k = shared arc length):
+    two pieces glued along a short arc form a union with a narrow neck, where
+    the zipper crowds points until the next weld fails in floating point.
+    Ties go to the smaller combined size (face count), then the smaller ids.  A merged component is
     named by the smaller id.  In sphere mode merging stops at two components,
     which are then closed-welded.  Returns (rounds, outer loop of each final
     component by id).
@@ -347,10 +355,11 @@ def merge_plan(loops, sizes, mode):
                 res = shared_arc(comps[i], comps[j])
                 if res is None or res[0] != "partial":
                     continue
-                cands.append((size[i] + size[j], i, j, res))
+                fat = Fraction(res[2], min(len(comps[i]), len(comps[j])))
+                cands.append(((-fat, size[i] + size[j], i, j), i, j, res))
         if not cands:
             raise WeldError("no pair of components can be welded")
-        cands.sort(key=lambda c: (c[0], c[1], c[2]))
+        cands.sort(key=lambda c: c[0])
         used = set()
         rnd = []
         for _, i, j, res in cands:

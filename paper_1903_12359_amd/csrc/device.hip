@@ -85,7 +85,7 @@ void free_part_device(pgcp_part* P) {
                      &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_val64, &P->d_val32,
                      &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
-                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1,
+                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q,
                      &P->d_partial, &P->d_bar, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
                      &P->d_flags, &P->wmap32.d_wg_sub, &P->wmap32.d_wg_s0, &P->wmap32.d_wg_s1,
                      &P->wmap32.d_sub_pbase, &P->wmap32.d_sub_nwg, &P->wmap32.d_wg_rank,
@@ -146,6 +146,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_z, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_p0, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_p1, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_q, N * 16)).code) return e;
     const size_t K = (size_t)P->K;
     if ((e = dev_alloc(P->d_rnorm, K * 2 * 8)).code) return e;
     if ((e = dev_alloc(P->d_scale, K * 2 * 8)).code) return e;
@@ -387,6 +388,7 @@ struct CGArgs {
     typename Vec2<T>::type* z;
     typename Vec2<T>::type* pa;
     typename Vec2<T>::type* pb;
+    typename Vec2<T>::type* q;     // streaming kernel only: A p of the own rows
     double* partial;               // [sum nwg][8]
     unsigned* bar;                 // [K]
     int* abort_flag;
@@ -799,6 +801,229 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     }
 }
 
+// Streaming batched PCG, for batches whose rows do not fit in the registers of
+// one cooperative grid.  Same iteration, same per-piece barriers and the same
+// fixed-order reductions as k_pcg, but e, r, z, p and q live in memory and each
+// wave walks any number of its workgroup's slices (s0 + wave + NW j).  z and p
+// are gathered by neighbours, so they are written and read through the
+// coherent path; e, r and q are only touched by the thread that owns the row.
+template <typename T, int BLK>
+__global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
+    using V2 = typename Vec2<T>::type;
+    constexpr int NW = BLK / 64;
+    __shared__ double lds[NW * 8 + 16];
+    __shared__ int lds_flag;
+    const int wg = blockIdx.x;
+    const int sub = a.wg_sub[wg];
+    if (sub < 0 || !a.active[sub]) return;
+    const int s0 = a.wg_s0[wg], s1 = a.wg_s1[wg];
+    const int rank = a.wg_rank[wg];
+    const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
+    const bool leader = rank == 0 && threadIdx.x == 0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned* bar = a.bar + sub;
+    unsigned nbar = 0;
+    double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
+    V2 zero;
+    zero.x = (T)0;
+    zero.y = (T)0;
+
+    // ---- start: e = 0, z = D^-1 r, p_old = 0
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = s0 + wave; s < s1; s += NW) {
+        const int64_t rw = (int64_t)s * 64 + lane;
+        V2 r = zero, z = zero;
+        if (!a.mask[rw]) {
+            const T dinv = (T)1 / a.diag[rw];
+            r = a.r[rw];
+            z.x = dinv * r.x;
+            z.y = dinv * r.y;
+        }
+        a.e[rw] = zero;
+        st_c(a.z + rw, z);
+        st_c(a.pa + rw, zero);
+        acc[0] += (double)r.x * (double)z.x;
+        acc[1] += (double)r.y * (double)z.y;
+        acc[2] += (double)r.x * (double)r.x;
+        acc[3] += (double)r.y * (double)r.y;
+    }
+    bsum<BLK, 4>(acc, lds);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
+    }
+    nbar++;
+    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        if (leader) a.status[sub] = 3;
+        return;
+    }
+    double st[4];
+    piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
+    double rz[2] = {st[0], st[1]};
+    double rr0[2] = {st[2], st[3]};
+    if (a.coupled) {
+        rz[0] = rz[1] = st[0] + st[1];
+        rr0[0] = rr0[1] = st[2] + st[3];
+    }
+    const double tgt[2] = {a.target_rel2[2 * sub] * rr0[0], a.target_rel2[2 * sub + 1] * rr0[1]};
+    bool done[2] = {rr0[0] <= tgt[0] || !(rz[0] > 0.0), rr0[1] <= tgt[1] || !(rz[1] > 0.0)};
+    double rrc[2] = {rr0[0], rr0[1]};
+    double beta[2] = {0.0, 0.0};
+    double best = (done[0] ? 0.0 : 1.0) + (done[1] ? 0.0 : 1.0);
+    int it_best = 0;
+    int it = 0;
+    int stat = 0;
+    V2* pold = a.pa;
+    V2* pnew = a.pb;
+
+    while (!(done[0] && done[1])) {
+        if (it >= a.max_iter) {
+            stat = 2;
+            break;
+        }
+        // ---- phase A: p_new = z + beta p_old on the fly for every column; q = A p_new; p.q
+        const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
+        const T cx = done[0] ? (T)0 : (T)1, cy = done[1] ? (T)0 : (T)1;
+        double pq[2] = {0.0, 0.0};
+        for (int s = s0 + wave; s < s1; s += NW) {
+            const int64_t rw = (int64_t)s * 64 + lane;
+            V2 zr = ld_c(a.z + rw), orw = ld_c(pold + rw);
+            V2 p;
+            p.x = cx * zr.x + bx * orw.x;
+            p.y = cy * zr.y + by * orw.y;
+            st_c(pnew + rw, p);
+            V2 q = zero;
+            if (!a.mask[rw]) {
+                const int64_t base = a.sl_ptr[s] + lane;
+                const int w = a.sl_w[s];
+                const T d = a.diag[rw];
+                T qx = d * p.x, qy = d * p.y;
+                for (int k = 0; k < w; ++k) {
+                    const int64_t el = base + (int64_t)k * 64;
+                    const T v = a.val[el];
+                    const int c = a.sl_col[el];
+                    V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
+                    qx += v * (cx * zc.x + bx * oc.x);
+                    qy += v * (cy * zc.y + by * oc.y);
+                }
+                if (a.coupled) {
+                    const int pv = a.rprev[rw];
+                    if (pv >= 0) {
+                        const int nx = a.rnext[rw];
+                        V2 zn = ld_c(a.z + nx), on = ld_c(pold + nx);
+                        V2 zp = ld_c(a.z + pv), op = ld_c(pold + pv);
+                        const T pNx = cx * zn.x + bx * on.x, pNy = cy * zn.y + by * on.y;
+                        const T pPx = cx * zp.x + bx * op.x, pPy = cy * zp.y + by * op.y;
+                        qx -= (T)0.5 * (pNy - pPy);
+                        qy += (T)0.5 * (pNx - pPx);
+                    }
+                }
+                q.x = qx;
+                q.y = qy;
+                pq[0] += (double)p.x * (double)qx;
+                pq[1] += (double)p.y * (double)qy;
+            }
+            a.q[rw] = q;
+        }
+        bsum<BLK, 2>(pq, lds);
+        if (threadIdx.x == 0) {
+            st_c(mypart + 0, pq[0]);
+            st_c(mypart + 1, pq[1]);
+        }
+        nbar++;
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+            stat = 3;
+            break;
+        }
+        double pqs[2];
+        piece_sum<BLK, 2>(a.partial, pbase, nwg, 0, pqs, lds);
+        double alpha[2] = {0.0, 0.0};
+        if (a.coupled) {
+            double den = pqs[0] + pqs[1];
+            if (!(den > 0.0) || !isfinite(den)) {
+                stat = 1;
+                break;
+            }
+            alpha[0] = alpha[1] = rz[0] / den;
+        } else {
+            for (int c = 0; c < 2; ++c) {
+                if (done[c]) continue;
+                if (!(pqs[c] > 0.0) || !isfinite(pqs[c])) {
+                    stat = 1;
+                    break;
+                }
+                alpha[c] = rz[c] / pqs[c];
+            }
+            if (stat) break;
+        }
+        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r
+        const T ax = (T)alpha[0], ay = (T)alpha[1];
+        double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = s0 + wave; s < s1; s += NW) {
+            const int64_t rw = (int64_t)s * 64 + lane;
+            if (a.mask[rw]) continue;
+            const V2 p = ld_c(pnew + rw), q = a.q[rw];
+            V2 e = a.e[rw], r = a.r[rw], z;
+            e.x += ax * p.x;
+            e.y += ay * p.y;
+            r.x -= ax * q.x;
+            r.y -= ay * q.y;
+            const T dinv = (T)1 / a.diag[rw];
+            z.x = dinv * r.x;
+            z.y = dinv * r.y;
+            a.e[rw] = e;
+            a.r[rw] = r;
+            st_c(a.z + rw, z);
+            acc2[0] += (double)r.x * (double)z.x;
+            acc2[1] += (double)r.y * (double)z.y;
+            acc2[2] += (double)r.x * (double)r.x;
+            acc2[3] += (double)r.y * (double)r.y;
+        }
+        bsum<BLK, 4>(acc2, lds);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
+        }
+        nbar++;
+        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+            stat = 3;
+            break;
+        }
+        piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
+        double rzn[2] = {st[0], st[1]};
+        double rrn[2] = {st[2], st[3]};
+        if (a.coupled) {
+            rzn[0] = rzn[1] = st[0] + st[1];
+            rrn[0] = rrn[1] = st[2] + st[3];
+        }
+        double prog = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            if (done[c]) continue;
+            rrc[c] = rrn[c];
+            beta[c] = rzn[c] / rz[c];
+            rz[c] = rzn[c];
+            if (rrn[c] <= tgt[c] || !(rzn[c] > 0.0)) done[c] = true;
+            else prog += rrn[c] / rr0[c];
+        }
+        if (a.coupled) done[1] = done[0];
+        ++it;
+        if (prog < 0.9 * best) {
+            best = prog;
+            it_best = it;
+        } else if (!(done[0] && done[1]) && it - it_best > a.stall) {
+            stat = 4;
+            break;
+        }
+        V2* t = pold;
+        pold = pnew;
+        pnew = t;
+    }
+    if (leader) {
+        a.iters[sub] = it;
+        a.status[sub] = stat;
+        a.rr_out[2 * sub] = rr0[0] > 0.0 ? rrc[0] / rr0[0] : 0.0;
+        a.rr_out[2 * sub + 1] = rr0[1] > 0.0 ? rrc[1] / rr0[1] : 0.0;
+    }
+}
+
 // ----------------------------------------------------------------- DNCP / harmonic set-up and gathers
 
 __global__ void k_init_dncp(int K, const int32_t* __restrict__ pin_row, const double* __restrict__ pin_x1,
@@ -812,7 +1037,9 @@ __global__ void k_init_dncp(int K, const int32_t* __restrict__ pin_row, const do
 __device__ __forceinline__ double2 chart_fwd(double2 z, double2 c, int cinf) {
     // w = (z - c) / (1 + conj(c) z); infinity -> 1/conj(c)
     if (isinf(z.x) || isinf(z.y)) {
+        if (cinf) return make_double2(0.0, 0.0);
         double d = c.x * c.x + c.y * c.y;
+        if (d == 0.0) return make_double2(INFINITY, INFINITY);
         return make_double2(c.x / d, c.y / d);
     }
     if (cinf) {   // chart centred at infinity: w = -1/z
@@ -857,6 +1084,41 @@ __device__ __forceinline__ void inv_stereo(double2 z, bool zinf, double* out) {
     out[0] = 2.0 * z.x / den;
     out[1] = -2.0 * z.y / den;
     out[2] = (r2 - 1.0) / den;
+}
+
+// One block per piece: the piece's rotation chart for the sphere.  The centre
+// is the stereographic image of the normalised mean of the piece's welded
+// boundary points on the sphere; chart[3i..3i+2] = (Re c, Im c, c is infinity).
+__global__ void __launch_bounds__(BLOCK) k_sphere_charts(const int32_t* __restrict__ loop_ptr,
+                                                          const int32_t* __restrict__ loop_seam,
+                                                          const double2* __restrict__ welded,
+                                                          double* __restrict__ chart) {
+    __shared__ double lds[32];
+    int i = blockIdx.x;
+    int e0 = loop_ptr[i], e1 = loop_ptr[i + 1];
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int e = e0 + threadIdx.x; e < e1; e += BLOCK) {
+        double p[3];
+        inv_stereo(welded[loop_seam[e]], false, p);
+        m[0] += p[0];
+        m[1] += p[1];
+        m[2] += p[2];
+    }
+    block_sum<3>(m, lds);
+    if (threadIdx.x == 0) {
+        double nrm = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+        double x = m[0] / nrm, y = m[1] / nrm, z = m[2] / nrm;
+        double d = 1.0 - z;
+        if (d > 0.0) {
+            chart[3 * i] = x / d;
+            chart[3 * i + 1] = -y / d;
+            chart[3 * i + 2] = 0.0;
+        } else {
+            chart[3 * i] = 0.0;
+            chart[3 * i + 1] = 0.0;
+            chart[3 * i + 2] = 1.0;
+        }
+    }
 }
 
 // u = welded values (in the piece's chart for the sphere) on loop rows, 0 elsewhere.
@@ -1137,12 +1399,19 @@ Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
     return Error{PGCP_OK, ""};
 }
 
-// Launch shapes of the batched PCG: (threads per workgroup, 64-row slices per wave).
+// Launch shapes of the batched PCG: threads per workgroup, 64-row slices per
+// wave, and which kernel (register-resident, or streaming through memory).
 struct PcgCfg {
-    int blk, R;
+    int blk, R, stream;
 };
-static const PcgCfg kPcgCfgs[] = {{256, 1}, {256, 2}, {256, 4}, {256, 8}, {512, 1},
-                                  {512, 2}, {512, 4}, {1024, 1}, {1024, 2}};
+static const PcgCfg kPcgCfgs[] = {{256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 8, 0}, {512, 1, 0},
+                                  {512, 2, 0}, {512, 4, 0}, {1024, 1, 0}, {1024, 2, 0}};
+
+template <typename T>
+static const void* pcg_stream_kernel(int blk) {
+    if (blk == 512) return reinterpret_cast<const void*>(&k_pcg_stream<T, 512>);
+    return reinterpret_cast<const void*>(&k_pcg_stream<T, 256>);
+}
 
 template <typename T>
 static const void* pcg_kernel(int blk, int R) {
@@ -1177,8 +1446,9 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     if (!coop) return Error{PGCP_E_HIP, "device does not support cooperative launches"};
     const int n_xcd = (n_cu >= 64 && n_cu % 32 == 0) ? n_cu / 32 : 1;
     int per_cu = 0;
-    const void* kern = prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R);
-    const size_t lds_bytes = (size_t)cfg.blk * cfg.R * (prec == 0 ? 16 : 8);
+    const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
+                                  : (prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R));
+    const size_t lds_bytes = cfg.stream ? 0 : (size_t)cfg.blk * cfg.R * (prec == 0 ? 16 : 8);
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
     const int64_t cap = (int64_t)per_cu * n_cu;
     const int64_t spw = (int64_t)(cfg.blk / 64) * cfg.R;   // slices per workgroup
@@ -1203,6 +1473,7 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     if (G > cap) return Error{PGCP_OK, ""};
     W->blk = cfg.blk;
     W->rows_per_thread = cfg.R;
+    W->stream = cfg.stream;
     W->n_xcd = n_xcd;
     W->n_wg = (int)G;
     W->wg_sub.assign(G, -1);
@@ -1269,6 +1540,7 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.z = (V2*)P->d_z.p;
     a.pa = (V2*)P->d_p0.p;
     a.pb = (V2*)P->d_p1.p;
+    a.q = (V2*)P->d_q.p;
     a.partial = (double*)P->d_partial.p;
     a.bar = (unsigned*)P->d_bar.p;
     a.abort_flag = (int*)P->d_abort.p;
@@ -1308,30 +1580,57 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
                                          (const float*)P->d_diag32.p);
         a.stall = stall;
         void* args[] = {&a};
-        HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
-                                          (size_t)W.blk * W.rows_per_thread * 8, s));
+        if (W.stream)
+            HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<float>(W.blk), grid, block, args, 0, s));
+        else
+            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
+                                              (size_t)W.blk * W.rows_per_thread * 8, s));
     } else {
         CGArgs<double> a = cg_args<double>(P, W, mask, coupled, max_iter, (const double*)P->d_val64.p,
                                            (const double*)P->d_diag64.p);
         a.stall = stall;
         void* args[] = {&a};
-        HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
-                                          (size_t)W.blk * W.rows_per_thread * 16, s));
+        if (W.stream)
+            HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<double>(W.blk), grid, block, args, 0, s));
+        else
+            HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
+                                              (size_t)W.blk * W.rows_per_thread * 16, s));
     }
     return Error{PGCP_OK, ""};
 }
 
-// Choose the launch shape: PGCP_PCG_CFG="blk,R" forces one; otherwise every
-// shape that fits is timed for a few iterations on the real batch (the first
-// time a plan solves in a precision) and the fastest per iteration is kept.
+// Smallest power-of-two slices per wave with which the streaming kernel's
+// grid fits in one cooperative launch (0 if none does).
+static Error stream_fit(pgcp_ctx* ctx, pgcp_part* P, int prec, int blk, int* R) {
+    *R = 0;
+    for (int r = 1; r <= 1 << 16; r *= 2) {
+        WorkMap T;
+        bool fits;
+        Error e = build_workmap(ctx, P, prec, PcgCfg{blk, r, 1}, &T, &fits);
+        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
+            dev_free(*b);
+        if (e.code) return e;
+        if (fits) {
+            *R = r;
+            return Error{PGCP_OK, ""};
+        }
+    }
+    return Error{PGCP_OK, ""};
+}
+
+// Choose the launch shape: PGCP_PCG_CFG="blk,R" (register-resident) or
+// "blk,R,1" (streaming) forces one; otherwise every shape that fits is timed
+// for a few iterations on the real batch (the first time a context solves a
+// batch of that shape) and the fastest per iteration is kept.  The streaming
+// kernel is tried with the fewest and twice the fewest slices per wave that fit.
 static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t* mask, int coupled) {
     WorkMap& W = prec ? P->wmap32 : P->wmap64;
     if (W.n_wg > 0) return Error{PGCP_OK, ""};
     hipStream_t s = ctx->stream;
     const char* force = getenv("PGCP_PCG_CFG");
     if (force) {
-        PcgCfg c{256, 1};
-        if (sscanf(force, "%d,%d", &c.blk, &c.R) == 2) {
+        PcgCfg c{256, 1, 0};
+        if (sscanf(force, "%d,%d,%d", &c.blk, &c.R, &c.stream) >= 2) {
             bool fits;
             Error e = build_workmap(ctx, P, prec, c, &W, &fits);
             if (e.code) return e;
@@ -1343,16 +1642,26 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     auto hit = ctx->tuned.find(key);
     if (hit != ctx->tuned.end()) {
         bool fits;
-        Error e = build_workmap(ctx, P, prec, PcgCfg{hit->second.first, hit->second.second}, &W, &fits);
+        Error e = build_workmap(ctx, P, prec, PcgCfg{hit->second[0], hit->second[1], hit->second[2]}, &W, &fits);
         if (e.code) return e;
         if (fits) return Error{PGCP_OK, ""};
     }
     const char* tune = getenv("PGCP_TUNE");
     const bool do_tune = !(tune && tune[0] == '0');
     float best_ms = 1e30f;
-    PcgCfg best{0, 0};
+    PcgCfg best{0, 0, 0};
     const int probe_iters = 40;
-    for (const PcgCfg& c : kPcgCfgs) {
+    std::vector<PcgCfg> cands(std::begin(kPcgCfgs), std::end(kPcgCfgs));
+    for (int blk : {256, 512}) {
+        int r = 0;
+        Error e = stream_fit(ctx, P, prec, blk, &r);
+        if (e.code) return e;
+        if (r > 0) {
+            cands.push_back(PcgCfg{blk, r, 1});
+            cands.push_back(PcgCfg{blk, 2 * r, 1});
+        }
+    }
+    for (const PcgCfg& c : cands) {
         WorkMap T;
         bool fits;
         Error e = build_workmap(ctx, P, prec, c, &T, &fits);
@@ -1383,7 +1692,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     bool fits;
     Error e = build_workmap(ctx, P, prec, best, &W, &fits);
     if (e.code) return e;
-    ctx->tuned[key] = {best.blk, best.R};
+    ctx->tuned[key] = {best.blk, best.R, best.stream};
     return Error{PGCP_OK, ""};
 }
 
@@ -1552,6 +1861,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         st->rows_per_thread = W.rows_per_thread;
         st->cg_workgroups = W.n_wg;
         st->cg_block = W.blk;
+        st->cg_stream = W.stream;
     }
     if (noconv) return Error{PGCP_E_NOCONV, "some piece missed the residual tolerance"};
     return Error{PGCP_OK, ""};
@@ -1576,19 +1886,11 @@ Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, dou
 Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp_solve_opts* o, double* out,
                    pgcp_solve_stats* st) {
     if (!P->assembled) return Error{PGCP_E_INVALID, "pgcp_assemble_cotan has not run"};
-    if (P->mode == PGCP_SPHERE && !P->welded) return Error{PGCP_E_INVALID, "sphere mode needs pgcp_weld first"};
     hipStream_t s = ctx->stream;
     const int sphere = P->mode == PGCP_SPHERE;
-    if (sphere) {
-        std::vector<double> ch(3 * P->K);
-        for (int i = 0; i < P->K; ++i) {
-            ch[3 * i] = P->chart[i].real();
-            ch[3 * i + 1] = P->chart[i].imag();
-            ch[3 * i + 2] = P->chart_inf[i];
-        }
-        Error e = upload(P->d_chart, ch, s);
-        if (e.code) return e;
-    }
+    if (sphere)
+        k_sphere_charts<<<P->K, BLOCK, 0, s>>>((const int32_t*)P->d_loop_ptr.p, (const int32_t*)P->d_loop_seam.p,
+                                                (const double2*)welded, (double*)P->d_chart.p);
     k_zero_d2<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (double2*)P->d_u64.p);
     k_init_harm<<<grid_for(P->n_bdy), BLOCK, 0, s>>>(P->n_bdy, P->K, (const int32_t*)P->d_loop_ptr.p,
                                                       (const int32_t*)P->d_loop_row.p,

@@ -404,8 +404,6 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         return Error{PGCP_E_WELD, "sphere mode needs at least two pieces"};
     }
     lap("merge plan");
-    P->chart.assign(K, cplx(0.0, 0.0));
-    P->chart_inf.assign(K, 0);
     return Error{PGCP_OK, ""};
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <complex>
+#include <array>
 #include <map>
 #include <cstdint>
 #include <string>
@@ -32,7 +33,8 @@ struct DevBuf {
 // owns a contiguous range of 64-row slices of exactly one piece.
 struct WorkMap {
     int blk = 0;                 // threads per workgroup
-    int rows_per_thread = 0;     // 64-row slices per wave
+    int rows_per_thread = 0;     // 64-row slices per wave (register-resident kernel)
+    int stream = 0;              // 1: vectors stream through memory, any number of slices per wave
     int n_xcd = 1;
     int n_wg = 0;                // grid size (0 = not built)
     int n_partials = 0;
@@ -51,7 +53,7 @@ struct pgcp_ctx {
     std::string last_error;
     // autotuned batched-CG launch shapes, keyed by precision, system kind and
     // the per-piece slice counts of the plan: (threads per workgroup, slices per wave)
-    std::map<std::string, std::pair<int, int>> tuned;
+    std::map<std::string, std::array<int, 3>> tuned;   // {threads per workgroup, slices per wave, streaming}
 };
 
 struct pgcp_part {
@@ -81,8 +83,6 @@ struct pgcp_part {
     std::vector<int32_t> loop_gv, loop_row, loop_seam;   // [n_bdy]
     std::vector<int32_t> seam_gv;             // [n_seam]
     std::vector<std::vector<std::pair<int, int>>> weld_rounds;
-    std::vector<pgcp::cplx> chart;            // [K] sphere chart centres (after the weld)
-    std::vector<int32_t> chart_inf;           // [K] chart centre is the point at infinity
 
     // ---------------- device mirrors
     pgcp::DevBuf d_row_gv, d_row_prev, d_row_next, d_row_kind, d_slice_sub;
@@ -90,10 +90,10 @@ struct pgcp_part {
     pgcp::DevBuf d_val64, d_val32, d_diag64, d_diag32;
     pgcp::DevBuf d_pin_row, d_pin_x1, d_loop_ptr, d_loop_row, d_loop_seam, d_seam_gv;
     pgcp::DevBuf d_mask_dncp, d_mask_harm;    // [N] uint8: 1 = Dirichlet row
-    pgcp::DevBuf d_chart;                     // [2K] doubles
+    pgcp::DevBuf d_chart;                     // [3K] doubles: sphere chart centre (re, im, is-infinity)
 
     // ---------------- solver work space
-    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1;
+    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q;
     pgcp::DevBuf d_partial, d_bar, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;

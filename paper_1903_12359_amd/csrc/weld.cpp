@@ -511,18 +511,27 @@ Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<i
         }
         std::sort(pairs.begin(), pairs.end());
         pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+        // a pair's "fatness" is its shared arc length over the shorter of the
+        // two loops: pairs that share a long arc first (a union glued along a
+        // short arc has a narrow neck, where the zipper crowds points), then
+        // the smaller combined face count, then the ids
         struct Cand {
-            int64_t s;
+            int64_t k, m, s;
             int i, j;
         };
         std::vector<Cand> cands;
         for (auto& pr : pairs) {
             int st;
             int k = shared_arc(comps[pr.first], comps[pr.second], &st);
-            if (k >= 2) cands.push_back(Cand{size[pr.first] + size[pr.second], pr.first, pr.second});
+            if (k >= 2) {
+                int64_t m = (int64_t)std::min(comps[pr.first].size(), comps[pr.second].size());
+                cands.push_back(Cand{k, m, size[pr.first] + size[pr.second], pr.first, pr.second});
+            }
         }
         if (cands.empty()) return Error{PGCP_E_WELD, "no pair of components can be welded"};
         std::sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) {
+            int64_t lx = x.k * y.m, ly = y.k * x.m;
+            if (lx != ly) return lx > ly;
             if (x.s != y.s) return x.s < y.s;
             if (x.i != y.i) return x.i < y.i;
             return x.j < y.j;
@@ -624,35 +633,6 @@ Error weld_all(pgcp_part* P, const double* bdy_uv, double* welded_uv) {
         for (int64_t s = 0; s < P->n_seam; ++s)
             if (!seen[s]) return Error{PGCP_E_WELD, "seam vertex without a welded coordinate"};
 
-        // sphere: one rotation chart per piece, centred on the mean of its
-        // welded boundary points on the sphere
-        if (P->mode == PGCP_SPHERE) {
-            for (int i = 0; i < K; ++i) {
-                double m[3] = {0, 0, 0};
-                for (int e = P->loop_ptr[i]; e < P->loop_ptr[i + 1]; ++e) {
-                    int64_t s = P->loop_seam[e];
-                    double x = welded_uv[2 * s], y = welded_uv[2 * s + 1];
-                    if (std::isinf(x)) {
-                        m[2] += 1.0;
-                        continue;
-                    }
-                    double r2 = x * x + y * y, den = r2 + 1.0;
-                    m[0] += 2.0 * x / den;
-                    m[1] += -2.0 * y / den;
-                    m[2] += (r2 - 1.0) / den;
-                }
-                double nrm = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
-                if (!(nrm > 0.0)) return Error{PGCP_E_WELD, "degenerate chart"};
-                for (double& c : m) c /= nrm;
-                if (1.0 - m[2] <= 0.0) {
-                    P->chart_inf[i] = 1;
-                    P->chart[i] = 0.0;
-                } else {
-                    P->chart_inf[i] = 0;
-                    P->chart[i] = cplx(m[0], -m[1]) / (1.0 - m[2]);
-                }
-            }
-        }
         P->welded = true;
         return Error{PGCP_OK, ""};
     } catch (const Error& e) {

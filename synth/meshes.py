@@ -278,21 +278,26 @@ def icosphere(level: int):
     return V, F.astype(np.int32)
 
 
-def _real_sph_harm(l, m, theta, phi):
-    """Real orthonormal spherical harmonic Y_lm (theta polar, phi azimuth)."""
+def _real_sph_harms(lmax, theta, phi):
+    """Real orthonormal spherical harmonics Y_lm, l = 1..lmax (theta polar, phi azimuth)."""
     from scipy.special import sph_harm_y
-    if m == 0:
-        return np.real(sph_harm_y(l, 0, theta, phi))
-    Y = sph_harm_y(l, abs(m), theta, phi)
-    if m > 0:
-        return math.sqrt(2.0) * (-1) ** m * np.real(Y)
-    return math.sqrt(2.0) * (-1) ** m * np.imag(Y)
+    Y = {}
+    for l in range(1, lmax + 1):
+        for m in range(0, l + 1):
+            Z = sph_harm_y(l, m, theta, phi)
+            if m == 0:
+                Y[(l, 0)] = np.real(Z)
+            else:
+                Y[(l, m)] = math.sqrt(2.0) * (-1) ** m * np.real(Z)
+                Y[(l, -m)] = math.sqrt(2.0) * (-1) ** m * np.imag(Z)
+    return Y
 
 
 def perturb_sphere(V: np.ndarray, rng: np.random.Generator, lmax: int = 8, scale: float = 0.05):
     """Radius r = 1 + sum_{l=1..lmax} sum_m c_lm Y_lm with c_lm ~ N(0, (scale/l)^2)."""
     theta = np.arccos(np.clip(V[:, 2], -1.0, 1.0))
     phi = np.arctan2(V[:, 1], V[:, 0])
+    Y = _real_sph_harms(lmax, theta, phi)
     while True:
         r = np.ones(V.shape[0])
         coef = {}
@@ -300,98 +305,110 @@ def perturb_sphere(V: np.ndarray, rng: np.random.Generator, lmax: int = 8, scale
             for m in range(-l, l + 1):
                 c = rng.normal(0.0, scale / l)
                 coef[(l, m)] = c
-                r += c * _real_sph_harm(l, m, theta, phi)
+                r += c * Y[(l, m)]
         if r.min() >= 0.5:
             return V * r[:, None], coef
 
 
-def _face_adjacency(F: np.ndarray):
-    """Pairs of faces sharing an edge (closed manifold mesh): returns (f0, f1, ea, eb)."""
+def _face_neighbours(F: np.ndarray) -> np.ndarray:
+    """nb[f, c] = the face across edge (F[f, c], F[f, c+1]) of a closed, consistently oriented mesh."""
     nf = F.shape[0]
-    e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]], axis=0).astype(np.int64)
-    fid = np.tile(np.arange(nf), 3)
     nv = int(F.max()) + 1
-    key = np.minimum(e[:, 0], e[:, 1]) * nv + np.maximum(e[:, 0], e[:, 1])
-    o = np.argsort(key, kind="stable")
-    ks = key[o]
-    same = ks[1:] == ks[:-1]
-    i0 = o[:-1][same]
-    i1 = o[1:][same]
-    return fid[i0], fid[i1], e[i0, 0], e[i0, 1]
+    a = F.astype(np.int64)
+    b = np.roll(a, -1, axis=1)
+    key = (a * nv + b).reshape(-1)
+    rkey = (b * nv + a).reshape(-1)
+    order = np.argsort(key)
+    sk = key[order]
+    pos = np.searchsorted(sk, rkey)
+    if not (pos < sk.size).all() or not (sk[np.minimum(pos, sk.size - 1)] == rkey).all():
+        raise ValueError("mesh must be closed, manifold and consistently oriented")
+    return (order[pos] // 3).reshape(nf, 3)
 
 
-def _label_components(nf, f0, f1, label):
-    """Connected components of faces through edges whose faces share a label."""
-    import scipy.sparse as sp
-    import scipy.sparse.csgraph as cg
-    keep = label[f0] == label[f1]
-    A = sp.coo_matrix((np.ones(keep.sum()), (f0[keep], f1[keep])), shape=(nf, nf))
-    _, comp = cg.connected_components(A, directed=False)
-    return comp
+def _smooth_labels(nb: np.ndarray, lab: np.ndarray, max_rounds: int = 200) -> np.ndarray:
+    """A face whose neighbours agree on another label (two of three) takes it.
+
+    This removes the one-triangle teeth that a vertex-based clustering leaves on
+    a triangulated surface: there the cut path turns by about 120 degrees, and
+    the geodesic zipper crowds boundary points at such sharp corners.
+    """
+    lab = lab.copy()
+    for _ in range(max_rounds):
+        l = lab[nb]
+        m = np.where(l[:, 0] == l[:, 1], l[:, 0],
+                     np.where(l[:, 1] == l[:, 2], l[:, 1], np.where(l[:, 0] == l[:, 2], l[:, 0], -1)))
+        chg = np.flatnonzero((m >= 0) & (m != lab))
+        if chg.size == 0:
+            break
+        # update an independent set only (no two changed faces adjacent), so it cannot oscillate
+        mark = np.zeros(lab.size, dtype=bool)
+        take = []
+        for f in chg:
+            if not mark[f]:
+                take.append(f)
+                mark[nb[f]] = True
+                mark[f] = True
+        take = np.array(take)
+        lab[take] = m[take]
+    return lab
 
 
-def _fix_pinches(F, label, max_rounds=50):
+def _vertex_rings(F: np.ndarray, nb: np.ndarray, verts: np.ndarray):
+    """Faces around each vertex of `verts`, in rotational order."""
+    nf = F.shape[0]
+    corner_v = F.reshape(-1)
+    o = np.argsort(corner_v, kind="stable")
+    nv = int(F.max()) + 1
+    starts = np.searchsorted(corner_v[o], np.arange(nv + 1))
+    rings = {}
+    for v in verts:
+        cs = o[starts[v]:starts[v + 1]]
+        where = {int(c // 3): int(c % 3) for c in cs}
+        f0 = int(cs[0] // 3)
+        ring = [f0]
+        f = f0
+        while True:
+            f = int(nb[f, (where[f] + 2) % 3])
+            if f == f0:
+                break
+            ring.append(f)
+        rings[int(v)] = ring
+    return rings
+
+
+def _fix_pinches(F: np.ndarray, nb: np.ndarray, label: np.ndarray, max_rounds: int = 50) -> np.ndarray:
     """Relabel faces so that around every vertex each label occupies one contiguous fan.
 
-    A label that appears in two separate runs around a vertex would make that
-    vertex a pinch point of the subdomain boundary.  The shorter run takes the
-    label of the run before it.  Repeats until no vertex has a split label.
+    A label met in two separate runs around a vertex would make that vertex a
+    pinch of the subdomain boundary.  Such a vertex has more cut edges than
+    labels around it; the shorter run of the repeated label takes the label of
+    the run before it.  Repeats until no vertex is a pinch.
     """
-    nf = F.shape[0]
+    label = label.copy()
     nv = int(F.max()) + 1
-    # corner table: for face f, corner c at vertex F[f,c]; next face around the vertex
-    e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]], axis=0).astype(np.int64)
-    fid = np.tile(np.arange(nf), 3)
-    dkey = e[:, 0] * nv + e[:, 1]
-    order = np.argsort(dkey)
-    sk = dkey[order]
-    # the face on the other side of directed edge a->b owns b->a
-    rkey = e[:, 1] * nv + e[:, 0]
-    pos = np.searchsorted(sk, rkey)
-    assert (sk[pos] == rkey).all(), "mesh must be closed and consistently oriented"
-    opp_face = fid[order[pos]]
-    # for vertex v = F[f,c], rotating CCW: the next face shares edge (v, F[f,c-1])
-    # the corner's "previous" directed edge is (F[f,c-1] -> v); its twin is (v -> F[f,c-1])
+    a = F.astype(np.int64)
+    b = np.roll(a, -1, axis=1)
     for _ in range(max_rounds):
-        changed = 0
-        # build fans per vertex by following twins
-        # corner (f,c): incoming edge index k = ((c+2)%3)*nf + f holds F[f,c-1] -> F[f,c]
-        nxt = np.empty((nf, 3), dtype=np.int64)
-        for c in range(3):
-            k = ((c + 2) % 3) * nf + np.arange(nf)
-            nxt[:, c] = opp_face[k]
-        # walk fans: group corners by vertex
-        corner_v = F.reshape(-1)
-        corner_f = np.repeat(np.arange(nf), 3)
-        o = np.argsort(corner_v, kind="stable")
-        starts = np.searchsorted(corner_v[o], np.arange(nv + 1))
-        lab = label
-        for v in range(nv):
-            cs = o[starts[v]:starts[v + 1]]
-            fs = corner_f[cs]
-            labs = lab[fs]
-            if np.unique(labs).size <= 1:
-                continue
-            # order faces around v
-            cfor = {int(corner_f[c]): int(c % 3) for c in cs}
-            f0 = int(fs[0])
-            ring = [f0]
-            f = f0
-            while True:
-                f = int(nxt[f, cfor[f]])
-                if f == f0:
-                    break
-                ring.append(f)
-            rl = lab[ring]
-            # rotate so that the ring starts at a label change
+        cut = label[:, None] != label[nb]                       # each cut edge seen from both faces
+        ncut = np.zeros(nv, dtype=np.int64)
+        np.add.at(ncut, a[cut], 1)
+        np.add.at(ncut, b[cut], 1)
+        ncut //= 2                                              # two faces, two endpoints each -> 2 per vertex
+        nl = int(label.max()) + 1
+        pairs = np.unique(a.reshape(-1) * nl + np.repeat(label, 3).astype(np.int64))
+        ndist = np.bincount(pairs // nl, minlength=nv)
+        bad = np.flatnonzero((ncut > ndist) & (ndist >= 2))
+        if bad.size == 0:
+            return label
+        rings = _vertex_rings(F, nb, bad)
+        for v in bad:
+            ring = rings[int(v)]
+            rl = label[ring]
             m = len(ring)
-            shift = None
-            for t in range(m):
-                if rl[t] != rl[t - 1]:
-                    shift = t
-                    break
+            shift = next(t for t in range(m) if rl[t] != rl[t - 1])
             ring = ring[shift:] + ring[:shift]
-            rl = lab[ring]
+            rl = label[ring]
             runs = []
             s0 = 0
             for t in range(1, m + 1):
@@ -399,25 +416,59 @@ def _fix_pinches(F, label, max_rounds=50):
                     runs.append((s0, t, int(rl[s0])))
                     s0 = t
             seen = {}
-            for (a, b, L) in runs:
-                seen.setdefault(L, []).append((a, b))
+            for (p, q, L) in runs:
+                seen.setdefault(L, []).append((p, q))
             for L, rs in seen.items():
                 if len(rs) > 1:
-                    rs = sorted(rs, key=lambda ab: ab[1] - ab[0])
-                    for (a, b) in rs[:-1]:
-                        prev_label = int(rl[a - 1]) if a > 0 else int(rl[-1])
-                        for t in range(a, b):
+                    rs = sorted(rs, key=lambda pq: pq[1] - pq[0])
+                    for (p, q) in rs[:-1]:
+                        prev_label = int(rl[p - 1]) if p > 0 else int(rl[-1])
+                        for t in range(p, q):
                             label[ring[t]] = prev_label
-                        changed += 1
-        if changed == 0:
-            return label
     raise RuntimeError("pinch removal did not converge")
 
 
+def _components(nb: np.ndarray, lab: np.ndarray) -> np.ndarray:
+    """Connected components of faces through edges whose two faces share a label."""
+    import scipy.sparse as sp
+    import scipy.sparse.csgraph as cg
+    nf = lab.size
+    f = np.repeat(np.arange(nf), 3)
+    g = nb.reshape(-1)
+    keep = lab[f] == lab[g]
+    A = sp.coo_matrix((np.ones(int(keep.sum())), (f[keep], g[keep])), shape=(nf, nf))
+    return cg.connected_components(A, directed=False)[1]
+
+
+def _euler(F: np.ndarray, comp: np.ndarray, ncomp: int) -> np.ndarray:
+    """V - E + F of every face component."""
+    nf = F.shape[0]
+    fc = np.bincount(comp, minlength=ncomp)
+    nv = int(F.max()) + 1
+    cc = np.repeat(comp, 3).astype(np.int64)
+    vc = np.unique(F.reshape(-1).astype(np.int64) * ncomp + cc)
+    vcount = np.bincount(vc % ncomp, minlength=ncomp)
+    a = F.astype(np.int64)
+    b = np.roll(a, -1, axis=1)
+    ekey = np.minimum(a, b).reshape(-1) * nv + np.maximum(a, b).reshape(-1)
+    ec = np.unique(ekey * ncomp + cc)
+    ecount = np.bincount(ec % ncomp, minlength=ncomp)
+    return vcount - ecount + fc
+
+
 def sphere_labels(V, F, k, rng, ratio_max=4.0, max_iter=50):
-    """k-means++ on vertex positions, face label by majority, cleaned into disks."""
+    """Seeded k-means on vertex positions, cleaned into disk-shaped pieces.
+
+    1. k-means++ seeding and Lloyd iterations on the vertex positions (stopping
+       once every cluster is non-empty and the size ratio is <= ratio_max);
+    2. a face takes the label of the majority of its vertices (three different
+       labels: the smallest);
+    3. one-triangle teeth are smoothed away, pinched vertices removed, and a
+       label split into several pieces keeps its largest; pieces smaller than
+       1% of the mean size join the neighbour they share most edges with.
+    Returns (labels numbered by first face, final size ratio of the k-means step).
+    """
     nv = V.shape[0]
-    # k-means++ seeding
     centres = [V[rng.integers(nv)]]
     d2 = np.sum((V - centres[0]) ** 2, axis=1)
     for _ in range(1, k):
@@ -428,15 +479,11 @@ def sphere_labels(V, F, k, rng, ratio_max=4.0, max_iter=50):
     C = np.array(centres)
     vl = None
     ratio = None
+    bs = 65536
     for it in range(max_iter):
-        dist = ((V[:, None, :] - C[None, :, :]) ** 2).sum(-1) if nv * k < 2e7 else None
-        if dist is None:
-            vl = np.empty(nv, dtype=np.int64)
-            bs = 65536
-            for s in range(0, nv, bs):
-                vl[s:s + bs] = np.argmin(((V[s:s + bs, None, :] - C[None]) ** 2).sum(-1), axis=1)
-        else:
-            vl = np.argmin(dist, axis=1)
+        vl = np.empty(nv, dtype=np.int64)
+        for s in range(0, nv, bs):
+            vl[s:s + bs] = np.argmin(((V[s:s + bs, None, :] - C[None]) ** 2).sum(-1), axis=1)
         cnt = np.bincount(vl, minlength=k)
         ratio = cnt.max() / max(cnt.min(), 1)
         if cnt.min() > 0 and ratio <= ratio_max and it > 0:
@@ -444,40 +491,42 @@ def sphere_labels(V, F, k, rng, ratio_max=4.0, max_iter=50):
         for j in range(k):
             if cnt[j] > 0:
                 C[j] = V[vl == j].mean(0)
-    # face majority; three distinct labels -> smallest
     fl3 = vl[F]
     a, b, c = fl3[:, 0], fl3[:, 1], fl3[:, 2]
     lab = np.where(a == b, a, np.where(b == c, b, np.where(a == c, a, np.minimum(np.minimum(a, b), c))))
     lab = lab.astype(np.int64)
     nf = F.shape[0]
-    f0, f1, _, _ = _face_adjacency(F)
-    for _ in range(20):
-        lab = _fix_pinches(F, lab)
-        comp = _label_components(nf, f0, f1, lab)
-        ncomp = comp.max() + 1
+    nb = _face_neighbours(F)
+    for _ in range(50):
+        lab = _smooth_labels(nb, lab)
+        lab = _fix_pinches(F, nb, lab)
+        comp = _components(nb, lab)
+        ncomp = int(comp.max()) + 1
         sizes = np.bincount(comp, minlength=ncomp)
-        # merge small components into the neighbour with the longest shared boundary
-        small = np.where(sizes < 0.01 * nf / k)[0]
-        # a label split into several components keeps only its largest one
-        best = {}
-        for cid in range(ncomp):
-            L = int(lab[np.argmax(comp == cid)])
-            if L not in best or sizes[cid] > sizes[best[L]]:
-                best[L] = cid
-        extra = [cid for cid in range(ncomp) if best[int(lab[np.argmax(comp == cid)])] != cid]
-        todo = sorted(set(small.tolist()) | set(extra))
+        comp_label = np.zeros(ncomp, dtype=np.int64)
+        comp_label[comp] = lab
+        best = np.full(int(lab.max()) + 1, -1, dtype=np.int64)
+        for cid in np.argsort(-sizes, kind="stable"):
+            if best[comp_label[cid]] < 0:
+                best[comp_label[cid]] = cid
+        todo = [cid for cid in range(ncomp)
+                if best[comp_label[cid]] != cid or sizes[cid] < 0.01 * nf / k]
+        chi = _euler(F, comp, ncomp)
+        todo += [cid for cid in range(ncomp) if chi[cid] != 1 and cid not in todo]
         if not todo:
             break
-        for cid in todo:
-            mask = comp[f0] != comp[f1]
-            sel = mask & ((comp[f0] == cid) | (comp[f1] == cid))
-            other = np.where(comp[f0[sel]] == cid, comp[f1[sel]], comp[f0[sel]])
+        f_all = np.repeat(np.arange(nf), 3)
+        g_all = nb.reshape(-1)
+        for cid in sorted(todo, key=lambda c: sizes[c]):
+            sel = (comp[f_all] == cid) & (comp[g_all] != cid)
+            other = comp[g_all[sel]]
             if other.size == 0:
                 continue
-            tgt = np.bincount(other).argmax()
-            lab[comp == cid] = lab[np.argmax(comp == tgt)]
+            tgt = int(np.bincount(other).argmax())
+            lab[comp == cid] = comp_label[tgt]
             comp[comp == cid] = tgt
-    # renumber labels 0..K-1 by first face
+    else:
+        raise RuntimeError("label clean-up did not converge")
     _, first = np.unique(lab, return_index=True)
     order = np.argsort(first)
     remap = np.empty(lab.max() + 1, dtype=np.int64)

@@ -12,7 +12,7 @@ import pytest
 
 from oracle.pipeline import local_params, prepare
 from oracle.weld import weld as oracle_weld
-from synth import case_c1, case_c2, small_grid_case
+from synth import case_c1, case_c2, small_grid_case, small_sphere_case
 
 pg = pytest.importorskip("paper_1903_12359_amd")
 HEADER = __import__("os").path.join(__import__("os").path.dirname(__file__), "..", "include", "pgcp.h")
@@ -42,6 +42,9 @@ CASES = [
     lambda: small_grid_case(23, 3, 2, seed=4, mode="disk"),
     case_c1,
     lambda: case_c2(n=96),
+    lambda: small_sphere_case(3, 6, seed=0),
+    lambda: small_sphere_case(4, 8, seed=1),
+    lambda: small_sphere_case(5, 12, seed=2),
 ]
 
 
@@ -74,7 +77,19 @@ def test_weld_matches_oracle(make):
     wc = pg.weld(None, plan, bh)
     zo = np.array([wo[g] for g in ex["seam_gv"]])
     zc = wc[:, 0] + 1j * wc[:, 1]
-    assert np.abs(zo - zc).max() <= 1e-10 * np.abs(zo).max()
+    io, ic = ~np.isfinite(zo), ~np.isfinite(zc)
+    assert np.array_equal(io, ic)
+    if case.mode == "sphere":
+        # on the sphere the error that matters is chordal: compare the points
+        # after inverse stereographic projection.  The closed weld composes
+        # every pair's maps over the whole loop, so rounding grows more than in
+        # the open welds; the bound is the FP64 parity bar of the whole path.
+        def sig(z):
+            r2 = np.abs(z) ** 2
+            return np.column_stack([2 * z.real, 2 * z.imag, r2 - 1]) / (r2 + 1)[:, None]
+        assert np.abs(sig(zo[~io]) - sig(zc[~ic])).max() <= 1e-9
+    else:
+        assert np.abs(zo - zc).max() <= 1e-10 * np.abs(zo).max()
     if case.mode == "disk":
         assert np.abs(np.abs(zc).max() - 1.0) < 1e-12
 

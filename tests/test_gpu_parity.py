@@ -16,7 +16,7 @@ from oracle.cotan import cotan_laplacian
 from oracle.distortion import distortion as oracle_distortion
 from oracle.pipeline import harmonic_all, local_params, pgcp, prepare
 from oracle.weld import weld as oracle_weld
-from synth import case_c1, case_c2, small_grid_case
+from synth import case_c1, case_c2, case_c3, small_grid_case, small_sphere_case
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,8 @@ CASES = {
     "g12_1x1": lambda: small_grid_case(12, 1, 1, seed=1),
     "C1": case_c1,
     "C2_n128": lambda: case_c2(n=128),
+    "S3_k6": lambda: small_sphere_case(3, 6, seed=0),
+    "S5_k12": lambda: small_sphere_case(5, 12, seed=2),
 }
 
 
@@ -117,7 +119,7 @@ def test_harmonic_matches_oracle(ctx, name, prec, tol, bound):
     assert err <= bound
 
 
-@pytest.mark.parametrize("name", ["g33_3x3_jit", "C1", "C2_n128"])
+@pytest.mark.parametrize("name", ["g33_3x3_jit", "C1", "C2_n128", "S5_k12"])
 def test_distortion_matches_oracle(ctx, name):
     import paper_1903_12359_amd as pg
     case = CASES[name]()
@@ -146,7 +148,7 @@ def test_distortion_flips_and_affine(ctx):
     assert st["n_flipped"] == case.nf and flip.cpu().numpy().all()
 
 
-@pytest.mark.parametrize("name", ["g17_2x2", "C1", "C2_n128"])
+@pytest.mark.parametrize("name", ["g17_2x2", "C1", "C2_n128", "S3_k6", "S5_k12"])
 def test_end_to_end(ctx, name):
     import paper_1903_12359_amd as pg
     case = CASES[name]()
@@ -196,9 +198,10 @@ def test_call_order_errors(ctx):
     assert ei.value.status == "INVALID"
 
 
-@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8"])
+@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8", "256,1,1", "256,4,1", "512,2,1"])
 def test_forced_launch_shapes(ctx, cfg, monkeypatch):
-    """Every launch shape, with pieces spread over several workgroups, gives the oracle's answer."""
+    """Every launch shape (register-resident, or streaming when the third field
+    is 1), with pieces spread over several workgroups, gives the oracle's answer."""
     import paper_1903_12359_amd as pg
     monkeypatch.setenv("PGCP_PCG_CFG", cfg)
     case = case_c2(n=160)
@@ -206,7 +209,8 @@ def test_forced_launch_shapes(ctx, cfg, monkeypatch):
     plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
     pg.assemble_cotan(ctx, plan, _dev(case.V))
     bdy, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13)
-    assert f"{rep.cg_block},{rep.rows_per_thread}" == cfg
+    shape = f"{rep.cg_block},{rep.rows_per_thread}" + (",1" if rep.cg_stream else "")
+    assert shape == cfg
     part, subs = prepare(case.V, case.F, case.label)
     ob = np.concatenate(local_params(subs))
     g = bdy.cpu().numpy()
@@ -243,4 +247,33 @@ def test_c2_full_size_stagewise(ctx):
         phi, rep = pg.harmonic_solve(ctx, plan, _dev(np.column_stack([w.real, w.imag])), precision=prec, tol=tol)
         err = np.abs(phi.cpu().numpy() - phi_o).max() / np.abs(phi_o).max()
         say("  harmonic err", err, "iters", rep.total_iters)
+        assert err <= bound
+
+
+def test_c3_full_size_stagewise(ctx):
+    """C3 at full size (655,362 vertices, 64 k-means pieces, sphere): DNCP and harmonic against the oracle."""
+    import paper_1903_12359_amd as pg
+    say("C3 full: generating")
+    case = case_c3()
+    say("C3 full: oracle")
+    part, subs, bdy, welded = _oracle_stages(case)
+    vals, _ = harmonic_all(subs, welded, case.mode)
+    from oracle.pipeline import assemble
+    phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+    ob = np.concatenate(bdy)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    seam = plan.export()["seam_gv"]
+    w = np.array([welded[int(v)] for v in seam])
+    wd = _dev(np.column_stack([w.real, w.imag]))
+    for prec, tol, bound in (("fp64", 1e-12, 1e-9), ("fp32", 1e-11, 1e-6)):
+        say("C3 full:", prec)
+        b, rep = pg.local_param(ctx, plan, precision=prec, tol=tol)
+        g = b.cpu().numpy()
+        err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+        say("  dncp err", err, "iters", rep.total_iters)
+        assert err <= bound
+        phi, rep = pg.harmonic_solve(ctx, plan, wd, precision=prec, tol=tol)
+        err = np.abs(phi.cpu().numpy() - phi_o).max()
+        say("  harmonic chordal err", err, "iters", rep.total_iters)
         assert err <= bound
