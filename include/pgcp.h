@@ -54,8 +54,12 @@ typedef enum {
 typedef enum { PGCP_FREE = 0, PGCP_DISK = 1, PGCP_SPHERE = 2 } pgcp_mode;
 typedef enum { PGCP_FP64 = 0, PGCP_FP32_REFINE = 1 } pgcp_precision;
 
+typedef enum { PGCP_PC_JACOBI = 0, PGCP_PC_LEARNED = 1 } pgcp_precond;
+typedef enum { PGCP_SYS_DNCP = 0, PGCP_SYS_HARMONIC = 1 } pgcp_system;
+
 typedef struct pgcp_ctx pgcp_ctx;
 typedef struct pgcp_part pgcp_part;
+typedef struct pgcp_lpc pgcp_lpc;
 
 /* Solver options.  tol: relative residual ||b - A x||_2 / ||b||_2 in FP64 with
  * the FP64 matrix, per piece (per coordinate for the harmonic solve).
@@ -65,7 +69,12 @@ typedef struct pgcp_part pgcp_part;
  * many iterations without a 10% reduction of its residual (restarted from the
  * FP64 residual by the next refinement pass).  Zero fields take the defaults
  * (1e-10, 1e-4, 20000, 30, 4000).  PGCP_VERBOSE=1 in the environment prints
- * one line per refinement pass to stderr. */
+ * one line per refinement pass to stderr.
+ * precond: PGCP_PC_JACOBI (default) or PGCP_PC_LEARNED with lpc set: the
+ * network's sparse approximate inverse of each piece is computed before the
+ * solve (pgcp_lpc_infer) and replaces D^-1; a piece whose learned solve breaks
+ * down or stagnates is finished with Jacobi (counted in stats.n_fallback), so
+ * the tolerance is met either way. */
 typedef struct {
     int32_t precision;        /* pgcp_precision */
     int32_t max_iter;
@@ -73,6 +82,9 @@ typedef struct {
     int32_t stall_iters;
     double tol;
     double inner_tol;
+    int32_t precond;          /* pgcp_precond */
+    int32_t reserved;
+    pgcp_lpc* lpc;            /* required for PGCP_PC_LEARNED */
 } pgcp_solve_opts;
 
 /* Per-call solver report.  Arrays are optional (NULL = not wanted), sized n_sub. */
@@ -94,6 +106,9 @@ typedef struct {
     int32_t cg_block;         /* out: threads per workgroup of the batched-CG launch   */
     int32_t cg_stream;        /* out: 1 if the launch streamed its vectors through memory
                                  (rows beyond what registers of one cooperative grid hold) */
+    int32_t n_fallback;       /* out: pieces finished with Jacobi after the learned
+                                 preconditioner broke down or stagnated              */
+    int32_t reserved3;
 } pgcp_solve_stats;
 
 /* Distortion statistics over all 3|F| angles (Table 5 of the paper). */
@@ -203,6 +218,50 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                             const int32_t* F_dev, int64_t nf, const double* param_dev,
                             int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Learned sparse approximate inverse (the GPU path's preconditioner; the paper
+ * solves each piece directly).  One message-passing network (width 64, three
+ * rounds, 62,466 parameters; weight matrices used in bf16 on the matrix cores,
+ * fp32 accumulation) reads a piece's cotangent Laplacian and Dirichlet mask and
+ * emits M = D^-1/2 (diag(exp(o_p) + sum_q |o_pq|) + O) D^-1/2 with L's
+ * sparsity: symmetric positive definite for any parameters, and equal to the
+ * Jacobi preconditioner D^-1 when the outputs are zero.  The flat parameter
+ * vector (fp32) is W_x[3][64], b_x[64], W_y[3][64], b_y[64], per round
+ * W_e[192][64], b_e[64], W_v[128][64], b_v[64], then u_e[64], c_e, u_v[64], c_v.
+ * A system is PGCP_SYS_DNCP (pins masked) or PGCP_SYS_HARMONIC (boundary masked).
+ * ------------------------------------------------------------------------- */
+
+int64_t pgcp_lpc_num_params(void);
+/* params_host [num_params] fp32, or NULL for all zeros (= Jacobi).  The
+ * network lives on the context's device; release with pgcp_lpc_destroy. */
+pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** out);
+pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* params_host);
+void pgcp_lpc_destroy(pgcp_lpc* lpc);
+/* Run the network on every piece of an assembled plan and store the SPAI
+ * values for `system` in the plan.  Async. */
+pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* part, const pgcp_lpc* lpc, int32_t system);
+/* Copy one piece's network outputs and SPAI values (after pgcp_lpc_infer) to
+ * host arrays, off-diagonal entries in the order of pgcp_laplacian_export
+ * without the diagonal: o_off/m_off [sub_nnz], o_diag/m_diag [sub_nv]; any may
+ * be NULL.  Masked rows and columns of M are zero.  Synchronous. */
+pgcp_status pgcp_lpc_export(pgcp_ctx* ctx, const pgcp_part* part, int32_t piece, double* o_off,
+                            double* o_diag, double* m_off, double* m_diag);
+/* Training loss over every piece of the plan:
+ *   loss = mean over pieces of mean over probes k of |M A v_k - v_k|^2 / |v_k|^2
+ * with A the piece's Laplacian on its free rows.  probes_dev [n_probes][n_rows]
+ * fp32 in packed-row order (pgcp_part_rows), 1 <= n_probes <= 16; values on
+ * masked rows are ignored.  pgcp_lpc_grad also writes the gradient
+ * (grad_host [num_params], may be NULL); pgcp_lpc_train_step takes one Adam
+ * step (beta 0.9, 0.999, eps 1e-8) of size lr on the parameters.  Synchronous. */
+pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* part, pgcp_lpc* lpc, int32_t system,
+                          const float* probes_dev, int32_t n_probes, double* loss, float* grad_host);
+pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* part, pgcp_lpc* lpc, int32_t system,
+                                const float* probes_dev, int32_t n_probes, float lr, double* loss);
+/* Packed-row ranges of the pieces: piece i owns rows row0[i] .. row0[i+1]-1,
+ * its local vertex j (ascending global index) on row row0[i] + j; rows past
+ * sub_nv[i] are padding.  row0 [n_sub+1]. */
+pgcp_status pgcp_part_rows(const pgcp_part* part, int64_t* row0);
 
 #ifdef __cplusplus
 }

@@ -33,7 +33,8 @@ class PGCPError(RuntimeError):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
-                ("stall_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double)]
+                ("stall_iters", ctypes.c_int32), ("tol", ctypes.c_double), ("inner_tol", ctypes.c_double),
+                ("precond", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lpc", ctypes.c_void_p)]
 
 
 class SolveStats(ctypes.Structure):
@@ -42,7 +43,7 @@ class SolveStats(ctypes.Structure):
                 ("status", ctypes.POINTER(ctypes.c_int32)), ("seconds", ctypes.c_double),
                 ("cg_kernel_ms", ctypes.c_double), ("cg_bytes", ctypes.c_double), ("cg_launches", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("cg_block", ctypes.c_int32),
-                ("cg_stream", ctypes.c_int32)]
+                ("cg_stream", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
 
 
 class DistStats(ctypes.Structure):
@@ -60,7 +61,11 @@ class PartInfo(ctypes.Structure):
 
 EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_set_stream", "pgcp_partition",
            "pgcp_part_query", "pgcp_part_export", "pgcp_part_destroy", "pgcp_laplacian_export",
-           "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion"]
+           "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion",
+           "pgcp_lpc_num_params", "pgcp_lpc_create", "pgcp_lpc_get_params", "pgcp_lpc_destroy", "pgcp_lpc_infer",
+           "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows"]
+PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
+SYSTEMS = {"dncp": 0, "harmonic": 1}
 
 _lib = None
 
@@ -89,6 +94,15 @@ def load_library(path: str = LIB_PATH):
         "pgcp_weld": (I32, [P, P, P, P]),
         "pgcp_harmonic_solve": (I32, [P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
         "pgcp_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P, P, I32, ctypes.POINTER(DistStats)]),
+        "pgcp_lpc_num_params": (I64, []),
+        "pgcp_lpc_create": (I32, [P, P, ctypes.POINTER(P)]),
+        "pgcp_lpc_get_params": (I32, [P, P, P]),
+        "pgcp_lpc_destroy": (None, [P]),
+        "pgcp_lpc_infer": (I32, [P, P, P, I32]),
+        "pgcp_lpc_export": (I32, [P, P, I32, P, P, P, P]),
+        "pgcp_lpc_grad": (I32, [P, P, P, I32, P, I32, ctypes.POINTER(D), P]),
+        "pgcp_lpc_train_step": (I32, [P, P, P, I32, P, I32, ctypes.c_float, ctypes.POINTER(D)]),
+        "pgcp_part_rows": (I32, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -106,9 +120,12 @@ def _ptr(a):
     return a.data_ptr()
 
 
-def _opts(precision="fp64", tol=1e-10, inner_tol=0.0, max_iter=0, max_refine=0, stall_iters=0):
+def _opts(precision="fp64", tol=1e-10, inner_tol=0.0, max_iter=0, max_refine=0, stall_iters=0, lpc=None):
     o = SolveOpts()
     o.stall_iters = stall_iters
+    if lpc is not None:
+        o.precond = PGCP_PC_LEARNED
+        o.lpc = lpc.h
     o.precision = PGCP_FP32_REFINE if precision in ("fp32", "fp32_refine", PGCP_FP32_REFINE) else PGCP_FP64
     o.tol = tol
     o.inner_tol = inner_tol
@@ -133,6 +150,7 @@ class SolveReport:
     cg_workgroups: int = 0
     cg_block: int = 0
     cg_stream: int = 0
+    n_fallback: int = 0
 
 
 class Context:
@@ -226,9 +244,76 @@ class Plan:
                                                           _ptr(val)))
         return sp.csr_matrix((val, col, rowptr), shape=(n, n))
 
+    def rows(self):
+        """Packed-row ranges of the pieces ([K+1]) and the total row count."""
+        row0 = np.empty(self.K + 1, np.int64)
+        self.ctx.check(self.ctx.lib.pgcp_part_rows(self.h, _ptr(row0)))
+        return row0
+
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.pgcp_part_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+
+class LPC:
+    """The learned SPAI preconditioner network (pgcp_lpc) on a context's device."""
+
+    def __init__(self, ctx: Context, params: np.ndarray | None = None):
+        self.ctx = ctx
+        self.n_params = int(ctx.lib.pgcp_lpc_num_params())
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            if p.size != self.n_params:
+                raise ValueError(f"expected {self.n_params} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.pgcp_lpc_create(ctx.h, _ptr(p), ctypes.byref(h)))
+        self.h = h
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        self.ctx.check(self.ctx.lib.pgcp_lpc_get_params(self.ctx.h, self.h, _ptr(out)))
+        return out
+
+    def infer(self, plan: Plan, system="harmonic"):
+        self.ctx.check(self.ctx.lib.pgcp_lpc_infer(self.ctx.h, plan.h, self.h, SYSTEMS[system]))
+
+    def export(self, plan: Plan, piece: int):
+        """(o_off, o_diag, m_off, m_diag) of one piece after infer(), CSR order without the diagonal."""
+        nv = int(plan.export()["sub_nv"][piece])
+        L = plan.laplacian(piece)
+        nnz = L.nnz - nv
+        o_off, m_off = np.empty(nnz), np.empty(nnz)
+        o_diag, m_diag = np.empty(nv), np.empty(nv)
+        self.ctx.check(self.ctx.lib.pgcp_lpc_export(self.ctx.h, plan.h, piece, _ptr(o_off), _ptr(o_diag),
+                                                    _ptr(m_off), _ptr(m_diag)))
+        return o_off, o_diag, m_off, m_diag
+
+    def grad(self, plan: Plan, probes_dev, system="harmonic"):
+        loss = ctypes.c_double()
+        g = np.empty(self.n_params, np.float32)
+        self.ctx.check(self.ctx.lib.pgcp_lpc_grad(self.ctx.h, plan.h, self.h, SYSTEMS[system], _ptr(probes_dev),
+                                                  int(probes_dev.shape[0]), ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, plan: Plan, probes_dev, lr: float, system="harmonic") -> float:
+        loss = ctypes.c_double()
+        self.ctx.check(self.ctx.lib.pgcp_lpc_train_step(self.ctx.h, plan.h, self.h, SYSTEMS[system],
+                                                        _ptr(probes_dev), int(probes_dev.shape[0]), float(lr),
+                                                        ctypes.byref(loss)))
+        return loss.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.pgcp_lpc_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -253,7 +338,7 @@ def _report(st, keep):
     it, rr, ss = keep
     return SolveReport(st.n_sub, st.refine_steps, st.total_iters, it.copy(), rr.reshape(-1, 2).copy(),
                        ss.copy(), st.seconds, st.cg_kernel_ms, st.cg_bytes, st.cg_launches, st.rows_per_thread,
-                       st.cg_workgroups, st.cg_block, st.cg_stream)
+                       st.cg_workgroups, st.cg_block, st.cg_stream, st.n_fallback)
 
 
 def assemble_cotan(ctx: Context, plan: Plan, V_dev):

@@ -25,7 +25,7 @@ DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang
                 "-munsafe-fp-atomics"]
 HOST_SOURCES = ["partition.cpp", "weld.cpp", "api.cpp"]
 HOST_EXTRA = {"weld.cpp": ["-fcx-limited-range"]}
-DEVICE_SOURCES = ["device.hip"]
+DEVICE_SOURCES = ["device.hip", "lpc.hip"]
 
 
 def _hipcc():

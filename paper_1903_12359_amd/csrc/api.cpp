@@ -171,3 +171,57 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, cons
 }
 
 }  // extern "C"
+
+extern "C" {
+
+int64_t pgcp_lpc_num_params(void) { return pgcp::lpc_num_params(); }
+
+pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** out) {
+    if (!ctx || !out) return bad(ctx, "null argument");
+    *out = nullptr;
+    return fail(ctx, pgcp::lpc_create(ctx, params_host, out));
+}
+
+pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* params_host) {
+    if (!ctx || !lpc || !params_host) return bad(ctx, "null argument");
+    return fail(ctx, pgcp::lpc_get_params(ctx, lpc, params_host));
+}
+
+void pgcp_lpc_destroy(pgcp_lpc* lpc) { pgcp::lpc_destroy(lpc); }
+
+pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* lpc, int32_t system) {
+    if (!ctx || !P || !lpc) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    return fail(ctx, pgcp::lpc_infer(ctx, P, lpc, system));
+}
+
+pgcp_status pgcp_lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, double* o_off, double* o_diag,
+                            double* m_off, double* m_diag) {
+    if (!ctx || !P) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
+    return fail(ctx, pgcp::lpc_export(ctx, P, piece, o_off, o_diag, m_off, m_diag));
+}
+
+pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t system, const float* probes_dev,
+                          int32_t n_probes, double* loss, float* grad_host) {
+    if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    return fail(ctx, pgcp::lpc_grad(ctx, P, lpc, system, probes_dev, n_probes, loss, grad_host, 0, 0.f));
+}
+
+pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t system,
+                                const float* probes_dev, int32_t n_probes, float lr, double* loss) {
+    if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    if (!(lr > 0.f)) return bad(ctx, "learning rate must be positive");
+    return fail(ctx, pgcp::lpc_grad(ctx, P, lpc, system, probes_dev, n_probes, loss, nullptr, 1, lr));
+}
+
+pgcp_status pgcp_part_rows(const pgcp_part* P, int64_t* row0) {
+    if (!P || !row0) return PGCP_E_INVALID;
+    for (int i = 0; i <= P->K; ++i) row0[i] = P->row0[i];
+    return PGCP_OK;
+}
+
+}  // extern "C"

@@ -38,51 +38,14 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include "device_util.h"
 #include "pgcp_internal.h"
 
 namespace pgcp {
 
-#define HIPCHK(x)                                                                   \
-    do {                                                                           \
-        hipError_t _e = (x);                                                       \
-        if (_e != hipSuccess)                                                      \
-            return Error{PGCP_E_HIP, std::string(#x) + ": " + hipGetErrorString(_e)}; \
-    } while (0)
-
-static constexpr int BLOCK = 256;
-static constexpr int WAVES = BLOCK / 64;
-static constexpr long long SPIN_MAX = 1ll << 24;
-
-// ----------------------------------------------------------------- buffers
-
-static Error dev_alloc(DevBuf& b, size_t bytes) {
-    if (b.bytes >= bytes && b.p) return Error{PGCP_OK, ""};
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-    if (bytes == 0) bytes = 16;
-    HIPCHK(hipMalloc(&b.p, bytes));
-    b.bytes = bytes;
-    return Error{PGCP_OK, ""};
-}
-
-static void dev_free(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-}
-
-template <typename T>
-static Error upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
-    Error e = dev_alloc(b, v.size() * sizeof(T));
-    if (e.code != PGCP_OK) return e;
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return Error{PGCP_OK, ""};
-}
-
 void free_part_device(pgcp_part* P) {
     DevBuf* all[] = {&P->d_row_gv, &P->d_row_prev, &P->d_row_next, &P->d_row_kind, &P->d_slice_sub,
-                     &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_val64, &P->d_val32,
+                     &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_sl_rev, &P->d_val64, &P->d_val32,
                      &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
                      &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q,
@@ -98,6 +61,7 @@ void free_part_device(pgcp_part* P) {
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
     P->ev0 = P->ev1 = nullptr;
+    lpc_free_part(P);
 }
 
 Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
@@ -115,6 +79,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     UP(P->d_sl_w, P->sl_w);
     UP(P->d_sl_col, P->sl_col);
     UP(P->d_sl_opp, P->sl_opp);
+    UP(P->d_sl_rev, P->sl_rev);
     UP(P->d_pin_row, P->pin_row);
     UP(P->d_pin_x1, P->pin_x1);
     UP(P->d_loop_ptr, P->loop_ptr);
@@ -162,48 +127,6 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_slicepart, (size_t)P->nslices * 2 * 8)).code) return e;
     HIPCHK(hipMemsetAsync(P->d_flags.p, 0, 64, s));
     return Error{PGCP_OK, ""};
-}
-
-// ----------------------------------------------------------------- small vector helpers
-
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
-
-template <typename V, typename S>
-__device__ __forceinline__ V axpy2(V x, S ax, S ay, V y) {   // y + a*x per component
-    V o;
-    o.x = y.x + ax * x.x;
-    o.y = y.y + ay * x.y;
-    return o;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Fixed-order block sum of NV values per thread; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double s = 0.0;
-            for (int w = 0; w < WAVES; ++w) s += lds[w * NV + i];
-            v[i] = s;
-        }
-    }
-    __syncthreads();
 }
 
 // ----------------------------------------------------------------- assembly
@@ -389,6 +312,9 @@ struct CGArgs {
     typename Vec2<T>::type* pa;
     typename Vec2<T>::type* pb;
     typename Vec2<T>::type* q;     // streaming kernel only: A p of the own rows
+    const T* mval;                 // learned SPAI off-diagonal values (SELL layout), or null
+    const T* mdiag;                // learned SPAI diagonal
+    const int32_t* pc;             // [K] 1 = the piece uses the SPAI, 0 = Jacobi (null: all Jacobi)
     double* partial;               // [sum nwg][8]
     unsigned* bar;                 // [K]
     int* abort_flag;
@@ -514,6 +440,31 @@ __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int 
     bsum<BLK, NV>(out, lds);
 }
 
+// z = M r for one row with the learned SPAI (M has the Laplacian's pattern):
+// own-workgroup columns from LDS (register kernel) or all from the coherent path.
+template <typename T, typename V2>
+__device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, const V2* lds_r, int64_t lo,
+                                       int64_t hi, const V2* rglob) {
+    const int64_t s = rw >> 6;
+    const int64_t base = a.sl_ptr[s] + (rw & 63);
+    const int w = a.sl_w[s];
+    const T d = a.mdiag[rw];
+    T zx = d * rown.x, zy = d * rown.y;
+    for (int k = 0; k < w; ++k) {
+        const int64_t el = base + (int64_t)k * 64;
+        const T m = a.mval[el];
+        if (m == (T)0) continue;
+        const int c = a.sl_col[el];
+        const V2 rc = (c >= lo && c < hi) ? lds_r[c - lo] : ld_c(rglob + c);
+        zx += m * rc.x;
+        zy += m * rc.y;
+    }
+    V2 z;
+    z.x = zx;
+    z.y = zy;
+    return z;
+}
+
 // Register-resident batched PCG.  Thread t of a workgroup owns the rows
 // (s0 + wave + NW j) * 64 + lane, j < R, for the whole solve: e, r, z, p of its
 // rows live in registers.  Each iteration the workgroup stages p_new of its
@@ -536,6 +487,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     const int rank = a.wg_rank[wg];
     const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
     const bool leader = rank == 0 && threadIdx.x == 0;
+    const bool spai = a.pc != nullptr && a.pc[sub] != 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t lo = (int64_t)s0 * 64, hi = (int64_t)s1 * 64;
     unsigned* bar = a.bar + sub;
@@ -572,8 +524,10 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         if (!msk[j]) {
             dinv[j] = (T)1 / dg[j];
             r[j] = a.r[rw];
-            z[j].x = dinv[j] * r[j].x;
-            z[j].y = dinv[j] * r[j].y;
+            if (!spai) {
+                z[j].x = dinv[j] * r[j].x;
+                z[j].y = dinv[j] * r[j].y;
+            }
         }
         const int64_t base = a.sl_ptr[s] + lane;
         const int w = a.sl_w[s];
@@ -590,9 +544,24 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             }
         }
         expo[j] = ex;
-        if (ex) {
-            st_c(a.z + rw, z[j]);
-            st_c(a.pa + rw, zero);
+    }
+    if (spai) {
+        // z = M r: own rows' r through LDS, the rest from the input residual
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (valid[j]) lds_p[rows[j] - lo] = r[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (valid[j] && !msk[j]) z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, a.r);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (!valid[j]) continue;
+        if (expo[j]) {
+            st_c(a.z + rows[j], z[j]);
+            st_c(a.pa + rows[j], zero);
         }
         acc[0] += (double)r[j].x * (double)z[j].x;
         acc[1] += (double)r[j].y * (double)z[j].y;
@@ -731,7 +700,8 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             }
             if (stat) break;
         }
-        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r
+        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r (Jacobi) or, after
+        // one more barrier that publishes r, z = M r (learned SPAI); r.z, r.r
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -742,6 +712,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             e[j].y += ay * pn[j].y;
             r[j].x -= ax * q[j].x;
             r[j].y -= ay * q[j].y;
+            if (spai) continue;
             z[j].x = dinv[j] * r[j].x;
             z[j].y = dinv[j] * r[j].y;
             if (expo[j]) st_c(a.z + rows[j], z[j]);
@@ -749,6 +720,29 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             acc2[1] += (double)r[j].y * (double)z[j].y;
             acc2[2] += (double)r[j].x * (double)r[j].x;
             acc2[3] += (double)r[j].y * (double)r[j].y;
+        }
+        if (spai) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (!valid[j]) continue;
+                lds_p[rows[j] - lo] = r[j];
+                if (expo[j]) st_c(a.r + rows[j], r[j]);
+            }
+            nbar++;
+            if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+                stat = 3;
+                break;
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (!valid[j] || msk[j]) continue;
+                z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, a.r);
+                if (expo[j]) st_c(a.z + rows[j], z[j]);
+                acc2[0] += (double)r[j].x * (double)z[j].x;
+                acc2[1] += (double)r[j].y * (double)z[j].y;
+                acc2[2] += (double)r[j].x * (double)r[j].x;
+                acc2[3] += (double)r[j].y * (double)r[j].y;
+            }
         }
         bsum<BLK, 4>(acc2, lds);
         if (threadIdx.x == 0) {
@@ -820,6 +814,7 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
     const int rank = a.wg_rank[wg];
     const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
     const bool leader = rank == 0 && threadIdx.x == 0;
+    const bool spai = a.pc != nullptr && a.pc[sub] != 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned* bar = a.bar + sub;
     unsigned nbar = 0;
@@ -834,10 +829,14 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         const int64_t rw = (int64_t)s * 64 + lane;
         V2 r = zero, z = zero;
         if (!a.mask[rw]) {
-            const T dinv = (T)1 / a.diag[rw];
             r = a.r[rw];
-            z.x = dinv * r.x;
-            z.y = dinv * r.y;
+            if (spai) {
+                z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
+            } else {
+                const T dinv = (T)1 / a.diag[rw];
+                z.x = dinv * r.x;
+                z.y = dinv * r.y;
+            }
         }
         a.e[rw] = zero;
         st_c(a.z + rw, z);
@@ -962,21 +961,43 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             const int64_t rw = (int64_t)s * 64 + lane;
             if (a.mask[rw]) continue;
             const V2 p = ld_c(pnew + rw), q = a.q[rw];
-            V2 e = a.e[rw], r = a.r[rw], z;
+            V2 e = a.e[rw], r = spai ? ld_c(a.r + rw) : a.r[rw], z;
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
             r.y -= ay * q.y;
+            a.e[rw] = e;
+            if (spai) {
+                st_c(a.r + rw, r);   // gathered by the neighbours for z = M r
+                continue;
+            }
             const T dinv = (T)1 / a.diag[rw];
             z.x = dinv * r.x;
             z.y = dinv * r.y;
-            a.e[rw] = e;
             a.r[rw] = r;
             st_c(a.z + rw, z);
             acc2[0] += (double)r.x * (double)z.x;
             acc2[1] += (double)r.y * (double)z.y;
             acc2[2] += (double)r.x * (double)r.x;
             acc2[3] += (double)r.y * (double)r.y;
+        }
+        if (spai) {
+            nbar++;
+            if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+                stat = 3;
+                break;
+            }
+            for (int s = s0 + wave; s < s1; s += NW) {
+                const int64_t rw = (int64_t)s * 64 + lane;
+                if (a.mask[rw]) continue;
+                const V2 r = ld_c(a.r + rw);
+                const V2 z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
+                st_c(a.z + rw, z);
+                acc2[0] += (double)r.x * (double)z.x;
+                acc2[1] += (double)r.y * (double)z.y;
+                acc2[2] += (double)r.x * (double)r.x;
+                acc2[3] += (double)r.y * (double)r.y;
+            }
         }
         bsum<BLK, 4>(acc2, lds);
         if (threadIdx.x == 0) {
@@ -1383,7 +1404,6 @@ __global__ void k_zero_d2(int64_t n, double2* p) {
 
 // ----------------------------------------------------------------- host side: launches
 
-static inline unsigned grid_for(int64_t n) { return (unsigned)((n + BLOCK - 1) / BLOCK); }
 
 Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
     hipStream_t s = ctx->stream;
@@ -1541,6 +1561,9 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.pa = (V2*)P->d_p0.p;
     a.pb = (V2*)P->d_p1.p;
     a.q = (V2*)P->d_q.p;
+    a.mval = nullptr;
+    a.mdiag = nullptr;
+    a.pc = nullptr;
     a.partial = (double*)P->d_partial.p;
     a.bar = (unsigned*)P->d_bar.p;
     a.abort_flag = (int*)P->d_abort.p;
@@ -1573,12 +1596,17 @@ static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
 }
 
 static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t* mask, int coupled, int max_iter,
-                        int stall, hipStream_t s) {
+                        int stall, hipStream_t s, const int32_t* pc = nullptr) {
     dim3 grid(W.n_wg), block(W.blk);
     if (prec) {
         CGArgs<float> a = cg_args<float>(P, W, mask, coupled, max_iter, (const float*)P->d_val32.p,
                                          (const float*)P->d_diag32.p);
         a.stall = stall;
+        if (pc) {
+            a.pc = pc;
+            a.mval = (const float*)P->d_mval32.p;
+            a.mdiag = (const float*)P->d_mdiag32.p;
+        }
         void* args[] = {&a};
         if (W.stream)
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<float>(W.blk), grid, block, args, 0, s));
@@ -1589,6 +1617,11 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
         CGArgs<double> a = cg_args<double>(P, W, mask, coupled, max_iter, (const double*)P->d_val64.p,
                                            (const double*)P->d_diag64.p);
         a.stall = stall;
+        if (pc) {
+            a.pc = pc;
+            a.mval = (const double*)P->d_mval64.p;
+            a.mdiag = (const double*)P->d_mdiag64.p;
+        }
         void* args[] = {&a};
         if (W.stream)
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<double>(W.blk), grid, block, args, 0, s));
@@ -1703,9 +1736,23 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
 // the FP64 residual, then runs one batched PCG (FP64, or FP32 on the scaled
 // residual) on the pieces that have not converged, and adds its correction.
 static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_t* mask,
-                          const pgcp_solve_opts* o, pgcp_solve_stats* st) {
+                          const pgcp_solve_opts* o, pgcp_solve_stats* st, int system) {
     hipStream_t s = ctx->stream;
     const int K = P->K;
+    // learned preconditioner: network outputs for this system, every piece on
+    // the SPAI until it breaks down or stagnates (then Jacobi)
+    const bool learned = o && o->precond == PGCP_PC_LEARNED;
+    std::vector<int32_t> pc(K, learned ? 1 : 0);
+    int n_fallback = 0;
+    if (learned) {
+        if (!o->lpc) return Error{PGCP_E_INVALID, "PGCP_PC_LEARNED needs opts.lpc"};
+        if (P->spai_sys != system) {
+            Error e0 = lpc_infer(ctx, P, o->lpc, system);
+            if (e0.code) return e0;
+        }
+        Error e0 = dev_alloc(P->d_pc, (size_t)K * 4);
+        if (e0.code) return e0;
+    }
     const int prec = (o && o->precision == PGCP_FP32_REFINE) ? 1 : 0;
     const double tol = (o && o->tol > 0) ? o->tol : 1e-10;
     const double inner_tol = (o && o->inner_tol > 0) ? o->inner_tol : 1e-4;
@@ -1734,7 +1781,10 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     // read+written, z written (phase B), the diagonal twice and the mask twice.
     const double tsz = prec ? 4.0 : 8.0;
     auto iter_bytes = [&](int i) {
-        return (double)P->sub_nnz[i] * (tsz + 4.0) + (double)P->sub_nv[i] * (8.0 * 2.0 * tsz + 2.0 * tsz + 2.0);
+        double b = (double)P->sub_nnz[i] * (tsz + 4.0) + (double)P->sub_nv[i] * (8.0 * 2.0 * tsz + 2.0 * tsz + 2.0);
+        // the SPAI apply reads M (values + column indices, diagonal) and writes and gathers r once more
+        if (pc[i]) b += (double)P->sub_nnz[i] * (tsz + 4.0) + (double)P->sub_nv[i] * (tsz + 2.0 * 2.0 * tsz);
+        return b;
     };
     for (int outer = 0; outer < max_refine; ++outer) {
         k_residual64<<<grid_for(P->N), BLOCK, 0, s>>>(
@@ -1795,7 +1845,10 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         if ((e = choose_workmap(ctx, P, prec, mask, coupled)).code) return e;
         if ((e = prep_inner(P, prec, s)).code) return e;
         HIPCHK(hipEventRecord(P->ev0, s));
-        if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s)).code) return e;
+        if (learned) HIPCHK(hipMemcpyAsync(P->d_pc.p, pc.data(), K * 4, hipMemcpyHostToDevice, s));
+        if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s,
+                            learned ? (const int32_t*)P->d_pc.p : nullptr)).code)
+            return e;
         HIPCHK(hipEventRecord(P->ev1, s));
         if (prec) {
             k_apply_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
@@ -1834,6 +1887,11 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
             it_total[i] += iters[i];
             total += iters[i];
             cg_bytes += iters[i] * iter_bytes(i);
+            if (pc[i] && (status[i] == 1 || status[i] == 4)) {
+                pc[i] = 0;   // learned SPAI broke down or stagnated: Jacobi from here on
+                n_fallback++;
+                continue;
+            }
             if (status[i] == 1 && iters[i] == 0) fail[i] = 1;   // breakdown before any progress
         }
     }
@@ -1862,6 +1920,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         st->cg_workgroups = W.n_wg;
         st->cg_block = W.blk;
         st->cg_stream = W.stream;
+        st->n_fallback = n_fallback;
     }
     if (noconv) return Error{PGCP_E_NOCONV, "some piece missed the residual tolerance"};
     return Error{PGCP_OK, ""};
@@ -1875,7 +1934,7 @@ Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, dou
     k_init_dncp<<<grid_for(P->K), BLOCK, 0, s>>>(P->K, (const int32_t*)P->d_pin_row.p,
                                                   (const double*)P->d_pin_x1.p, (double2*)P->d_u64.p);
     HIPCHK(hipGetLastError());
-    Error e = refine_solve(ctx, P, 1, (const uint8_t*)P->d_mask_dncp.p, o, st);
+    Error e = refine_solve(ctx, P, 1, (const uint8_t*)P->d_mask_dncp.p, o, st, 0);
     if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
     k_dncp_bdy<<<P->K, BLOCK, 0, s>>>((const int32_t*)P->d_loop_ptr.p, (const int32_t*)P->d_loop_row.p,
                                        (const double2*)P->d_u64.p, bdy);
@@ -1898,7 +1957,7 @@ Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp
                                                       (const int32_t*)P->d_slice_sub.p, (const double2*)welded,
                                                       (const double*)P->d_chart.p, sphere, (double2*)P->d_u64.p);
     HIPCHK(hipGetLastError());
-    Error e = refine_solve(ctx, P, 0, (const uint8_t*)P->d_mask_harm.p, o, st);
+    Error e = refine_solve(ctx, P, 0, (const uint8_t*)P->d_mask_harm.p, o, st, 1);
     if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
     k_harm_out<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p, (const int32_t*)P->d_row_gv.p,
                                                  (const int32_t*)P->d_slice_sub.p, (const double2*)P->d_u64.p,

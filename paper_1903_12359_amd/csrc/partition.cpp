@@ -366,8 +366,10 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     for (int i = 0; i < K; ++i)
         for (int64_t r = P->row0[i]; r < P->row0[i + 1]; ++r) P->sub_nnz[i] += deg[r];
     P->sell_elems = P->sl_ptr[P->nslices];
+    if (P->sell_elems > INT32_MAX) return Error{PGCP_E_INVALID, "too many matrix entries for int32 slot indices"};
     P->sl_col.resize(P->sell_elems);
     P->sl_opp.resize(2 * P->sell_elems);
+    P->sl_rev.resize(P->sell_elems);
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < P->nslices; ++s) {
         int64_t base = P->sl_ptr[s];
@@ -376,13 +378,19 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
             for (int32_t k = 0; k < P->sl_w[s]; ++k) {
                 int64_t el = base + (int64_t)k * 64 + l;
                 if (k < deg[r]) {
-                    P->sl_col[el] = u_col[rptr[r] + k];
+                    const int32_t c = u_col[rptr[r] + k];
+                    P->sl_col[el] = c;
                     P->sl_opp[2 * el] = u_o1[rptr[r] + k];
                     P->sl_opp[2 * el + 1] = u_o2[rptr[r] + k];
+                    // the slot of the reverse entry (c, r): columns of a row are ascending
+                    const int32_t* cb = u_col.data() + rptr[c];
+                    const int32_t kk = (int32_t)(std::lower_bound(cb, cb + deg[c], (int32_t)r) - cb);
+                    P->sl_rev[el] = (int32_t)(P->sl_ptr[c / 64] + (int64_t)kk * 64 + c % 64);
                 } else {
                     P->sl_col[el] = (int32_t)r;
                     P->sl_opp[2 * el] = -1;
                     P->sl_opp[2 * el + 1] = -1;
+                    P->sl_rev[el] = -1;
                 }
             }
         }

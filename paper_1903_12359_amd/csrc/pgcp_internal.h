@@ -77,6 +77,7 @@ struct pgcp_part {
     std::vector<int32_t> sl_w;                // [nslices] slice width (max off-diagonals per row)
     std::vector<int32_t> sl_col;              // [sell_elems] packed column; padding = own row
     std::vector<int32_t> sl_opp;              // [2*sell_elems] opposite vertices (global ids) or -1
+    std::vector<int32_t> sl_rev;              // [sell_elems] slot of the reverse entry, -1 for padding
     std::vector<int32_t> pin_row;             // [2K] DNCP pins p0, p1 (packed rows)
     std::vector<double> pin_x1;               // [K] x coordinate of p1 (|v_p1 - v_p0|)
     std::vector<int32_t> loop_ptr;            // [K+1]
@@ -86,7 +87,7 @@ struct pgcp_part {
 
     // ---------------- device mirrors
     pgcp::DevBuf d_row_gv, d_row_prev, d_row_next, d_row_kind, d_slice_sub;
-    pgcp::DevBuf d_sl_ptr, d_sl_w, d_sl_col, d_sl_opp;
+    pgcp::DevBuf d_sl_ptr, d_sl_w, d_sl_col, d_sl_opp, d_sl_rev;
     pgcp::DevBuf d_val64, d_val32, d_diag64, d_diag32;
     pgcp::DevBuf d_pin_row, d_pin_x1, d_loop_ptr, d_loop_row, d_loop_seam, d_seam_gv;
     pgcp::DevBuf d_mask_dncp, d_mask_harm;    // [N] uint8: 1 = Dirichlet row
@@ -98,6 +99,13 @@ struct pgcp_part {
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
     pgcp::WorkMap wmap32, wmap64;
+
+    // ---------------- learned preconditioner (network states, SPAI values, training work space)
+    int spai_sys = -1;                        // system whose SPAI values are current, -1 = none
+    pgcp::DevBuf d_lpc_val, d_lpc_h, d_lpc_e, d_lpc_oe, d_lpc_ov;
+    pgcp::DevBuf d_mval32, d_mdiag32, d_mval64, d_mdiag64;
+    pgcp::DevBuf d_lpc_av, d_lpc_R, d_lpc_sp, d_lpc_piece, d_lpc_c, d_lpc_goe, d_lpc_gov;
+    pgcp::DevBuf d_lpc_dh, d_lpc_dhown, d_lpc_de0, d_lpc_de1, d_lpc_dx, d_pc;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     bool assembled = false;
@@ -105,7 +113,27 @@ struct pgcp_part {
     bool host_only = false;
 };
 
+// Learned preconditioner: fp32 master parameters, Adam moments, the bf16
+// weight blocks the kernels read, and gradient work space.
+struct pgcp_lpc {
+    int device = 0;
+    pgcp::DevBuf theta, adam_m, adam_v, wb, grad, gp;
+    int64_t step = 0;
+};
+
 namespace pgcp {
+
+// learned preconditioner (lpc.hip)
+int64_t lpc_num_params();
+Error lpc_create(pgcp_ctx* ctx, const float* params, pgcp_lpc** out);
+void lpc_destroy(pgcp_lpc* L);
+Error lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* L, float* out);
+Error lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* L, int system);
+Error lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int piece, double* o_off, double* o_diag, double* m_off,
+                 double* m_diag);
+Error lpc_grad(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* L, int system, const float* probes, int n_probes,
+               double* loss, float* grad_host, int adam, float lr);
+void lpc_free_part(pgcp_part* P);
 
 // host plan (partition.cpp)
 Error build_plan(pgcp_part* part, const double* V, int64_t nv, const int32_t* F, int64_t nf,

@@ -1,0 +1,257 @@
+"""Learned SPAI preconditioner on the GPU (libpgcp) against the FP64 oracle.
+
+The network's weight matrices are bf16 on the device; the oracle gets the same
+bf16-rounded values, so what remains is the bf16 rounding of activations and
+gradient tiles (8 significant bits, about 0.4% per rounding) and the order of
+fp32 accumulation: outputs agree to a few percent of their scale and the
+gradient to a few percent in norm, far inside what matters for a
+preconditioner.  Everything the network feeds exactly is checked exactly: zero
+outputs give Jacobi, and a learned solve reaches the same solution as Jacobi to
+the parity bound.  Training on the GPU must lower the loss and cut CG
+iterations on held-out pieces.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lpc as olpc
+from oracle.cotan import cotan_laplacian
+from oracle.dncp import choose_pins
+from oracle.pipeline import harmonic_all, local_params, prepare
+from oracle.weld import weld as oracle_weld
+from synth import small_grid_case, small_sphere_case
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-lpc]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    import paper_1903_12359_amd as pg
+    pg.load_library()
+    assert torch.cuda.is_available()
+    return pg.Context(0)
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def bf16_round(x):
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def random_params(seed=0):
+    rng = np.random.default_rng(seed)
+    P = olpc.init_params(rng, zero_heads=False)
+    for k in P:
+        if k.startswith("b_") or k.startswith("c_"):
+            P[k] = rng.normal(0, 0.05, np.shape(P[k]))
+    return olpc.flatten(P).astype(np.float32)
+
+
+def oracle_params(theta32):
+    """The parameters as the device uses them: weight matrices rounded to bf16."""
+    P = olpc.unflatten(theta32.astype(np.float64))
+    for k in P:
+        if k.startswith("W_"):
+            P[k] = bf16_round(P[k])
+    return P
+
+
+def piece_masks(case):
+    part, subs = prepare(case.V, case.F, case.label)
+    out = []
+    for s in subs:
+        L = cotan_laplacian(s["P"], s["T"])
+        mh = np.zeros(L.shape[0], bool)
+        mh[s["loop_local"]] = True
+        p0, p1, _, _ = choose_pins(s["P"], s["loop_local"], s["loop"])
+        md = np.zeros(L.shape[0], bool)
+        md[[p0, p1]] = True
+        out.append(dict(L=L, harmonic=mh, dncp=md))
+    return out
+
+
+CASES = {
+    "g33_2x2": lambda: small_grid_case(33, 2, 2, seed=3, jitter=0.3),
+    "S4_k8": lambda: small_sphere_case(4, 8, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("system", ["harmonic", "dncp"])
+def test_forward_matches_oracle(ctx, name, system):
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    theta = random_params(1)
+    Po = oracle_params(theta)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    net = pg.LPC(ctx, theta)
+    net.infer(plan, system)
+    for i, pm in enumerate(piece_masks(case)):
+        G = olpc.graph(pm["L"], pm[system])
+        o_e, o_v = olpc.forward(Po, G)
+        M = olpc.spai(G, o_e, o_v)
+        go_e, go_v, gm_e, gm_d = net.export(plan, i)
+        scale = max(np.abs(o_e).max(), np.abs(o_v).max())
+        err = max(np.abs(go_e - o_e).max(), np.abs(go_v - o_v).max()) / scale
+        say(name, system, "piece", i, "output rel err", err)
+        assert err < 3e-2
+        # M from the device outputs must be exactly the oracle's formula of them
+        off = olpc.spai(G, go_e, go_v).tocsr()
+        dm = off.diagonal()
+        assert np.abs(gm_d - dm).max() <= 1e-12 * np.abs(dm).max()
+        offv = np.asarray(off[G["src"], G["dst"]]).ravel()
+        assert np.abs(gm_e - offv).max() <= 1e-12 * max(np.abs(offv).max(), 1e-300)
+        # and close to the oracle's M
+        assert np.abs(gm_d - M.diagonal()).max() <= 5e-2 * np.abs(M.diagonal()).max()
+
+
+def test_zero_network_is_jacobi(ctx):
+    import paper_1903_12359_amd as pg
+    case = CASES["g33_2x2"]()
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    net = pg.LPC(ctx, None)
+    net.infer(plan, "harmonic")
+    for i, pm in enumerate(piece_masks(case)):
+        o_e, o_v, m_e, m_d = net.export(plan, i)
+        assert not o_e.any() and not o_v.any() and not m_e.any()
+        d = plan.laplacian(i).diagonal()   # the device's own assembled diagonal
+        assert np.array_equal(m_d, np.where(pm["harmonic"], 0.0, 1.0 / d))
+
+
+def _probes(plan, n_probes, seed):
+    import torch
+    N = int(plan.rows()[-1])
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    return (torch.randint(0, 2, (n_probes, N), generator=g, device="cuda:0", dtype=torch.int8)
+            .to(torch.float32) * 2 - 1).contiguous()
+
+
+def _probe_batch(plan, V, case, system):
+    """The oracle's batch for the same probes: per piece (G, A, V restricted to the piece's rows)."""
+    row0 = plan.rows()
+    Vh = V.cpu().numpy().astype(np.float64)
+    batch = []
+    for i, pm in enumerate(piece_masks(case)):
+        n = pm["L"].shape[0]
+        Vi = Vh[:, row0[i]:row0[i] + n].T.copy()
+        Vi[pm[system]] = 0.0
+        batch.append((olpc.graph(pm["L"], pm[system]), olpc.system(pm["L"], pm[system]), Vi))
+    return batch
+
+
+@pytest.mark.parametrize("system", ["harmonic", "dncp"])
+def test_gradient_matches_oracle(ctx, system):
+    import paper_1903_12359_amd as pg
+    case = CASES["g33_2x2"]()
+    theta = random_params(2)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    net = pg.LPC(ctx, theta)
+    V = _probes(plan, 6, seed=5)
+    loss, g = net.grad(plan, V, system)
+    lo, go = olpc.loss_and_grad(oracle_params(theta), _probe_batch(plan, V, case, system))
+    go = olpc.flatten(go)
+    rel = np.linalg.norm(g - go) / np.linalg.norm(go)
+    cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
+    say(system, "loss", loss, lo, "grad rel err", rel, "cos", cos)
+    assert abs(loss - lo) <= 2e-2 * lo
+    assert rel < 5e-2 and cos > 0.998
+    # every parameter block gets its share of the gradient
+    o = 0
+    for name, shape in olpc.PARAM_SHAPES:
+        k = int(np.prod(shape, dtype=np.int64))
+        a, b = g[o:o + k], go[o:o + k]
+        if np.linalg.norm(b) > 1e-6 * np.linalg.norm(go):
+            assert np.linalg.norm(a - b) <= 0.1 * np.linalg.norm(b) + 1e-6 * np.linalg.norm(go), name
+        o += k
+
+
+@pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
+def test_learned_solves_reach_the_oracle(ctx, prec, tol, bound):
+    """With a (random) learned SPAI the refined solves converge to the oracle's solution."""
+    import paper_1903_12359_amd as pg
+    case = small_grid_case(40, 2, 2, seed=6, jitter=0.3)
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    welded = oracle_weld([s["loop"] for s in subs], bdy, case.mode, sizes=[len(s["T"]) for s in subs])
+    vals, _ = harmonic_all(subs, welded, case.mode)
+    from oracle.pipeline import assemble
+    phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    net = pg.LPC(ctx, random_params(3) * 0.5)
+    b, rep = pg.local_param(ctx, plan, precision=prec, tol=tol, lpc=net)
+    ob = np.concatenate(bdy)
+    g = b.cpu().numpy()
+    err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+    say("learned dncp", prec, "err", err, "iters", rep.total_iters, "fallback", rep.n_fallback)
+    assert err <= bound
+    seam = plan.export()["seam_gv"]
+    w = np.array([welded[int(v)] for v in seam])
+    phi, rep = pg.harmonic_solve(ctx, plan, _dev(np.column_stack([w.real, w.imag])), precision=prec, tol=tol,
+                                 lpc=net)
+    err = np.abs(phi.cpu().numpy() - phi_o).max() / np.abs(phi_o).max()
+    say("learned harmonic", prec, "err", err, "iters", rep.total_iters, "fallback", rep.n_fallback)
+    assert err <= bound
+
+
+@pytest.mark.parametrize("cfg", ["256,2", "256,2,1"])
+def test_learned_solve_both_kernels(ctx, cfg, monkeypatch):
+    """The SPAI apply in the register-resident and in the streaming kernel, pieces over several workgroups."""
+    import paper_1903_12359_amd as pg
+    monkeypatch.setenv("PGCP_PCG_CFG", cfg)
+    case = small_grid_case(96, 2, 2, seed=8, jitter=0.3)
+    part, subs = prepare(case.V, case.F, case.label)
+    ob = np.concatenate(local_params(subs))
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    net = pg.LPC(ctx, random_params(4) * 0.5)
+    b, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13, lpc=net)
+    assert rep.cg_workgroups > plan.K
+    g = b.cpu().numpy()
+    err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+    say("kernel", cfg, "err", err, "iters", rep.total_iters)
+    assert err <= 1e-9
+
+
+def test_training_lowers_loss_and_iterations(ctx):
+    """A short GPU training run lowers the loss and cuts CG iterations on held-out pieces."""
+    import paper_1903_12359_amd as pg
+    from paper_1903_12359_amd.lpc_train import TrainingSet, init_params, train
+    train_cases = [small_grid_case(65, 3, 3, seed=20 + t, jitter=0.15, nbumps=6) for t in range(3)] + \
+                  [small_sphere_case(5, 8, seed=30 + t) for t in range(2)]
+    tset = TrainingSet(ctx, train_cases)
+    net = pg.LPC(ctx, init_params(0))
+    hist = train(ctx, net, tset, steps=300, lr=2e-3, seed=0)
+    first, last = np.mean(hist[:20]), np.mean(hist[-20:])
+    say("loss", first, "->", last)
+    assert last < 0.8 * first
+    # held out: harmonic solves of a new mesh, Jacobi vs learned
+    case = small_grid_case(129, 3, 3, seed=99, jitter=0.15, nbumps=6)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    bdy, _ = pg.local_param(ctx, plan, precision="fp64", tol=1e-10)
+    welded = pg.weld(ctx, plan, bdy.cpu().numpy())
+    wd = _dev(welded)
+    _, rj = pg.harmonic_solve(ctx, plan, wd, precision="fp64", tol=1e-10)
+    _, rl = pg.harmonic_solve(ctx, plan, wd, precision="fp64", tol=1e-10, lpc=net)
+    say("held-out harmonic iterations: jacobi", rj.total_iters, "learned", rl.total_iters)
+    assert rl.relres.max() <= 1e-10
+    assert rl.total_iters < 0.85 * rj.total_iters
