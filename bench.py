@@ -1,6 +1,7 @@
 """PGCP hot-path benchmark on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--workload c2|c1|c3|c5]
+                    [--precond both|jacobi|learned] [--lpc-steps S]
 
 One step is Algorithm 3 end to end on one synthetic mesh already resident in
 device memory (V, F; labels and the host copy of the connectivity for the
@@ -9,6 +10,12 @@ partition): partition + plan upload, cotangent assembly, DNCP of every piece
 (batched PCG), gather, and the distortion / Beltrami / flip check.  Every solve
 reaches an FP64 relative residual of 1e-10 (per piece; per coordinate for the
 harmonic solve).  Prints one JSON line.
+
+The step is timed twice on the same GPU: with Jacobi-PCG, and with the learned
+SPAI preconditioner (network inference inside the step).  The network is
+first trained on the GPU for --lpc-steps Adam steps on seeded training meshes
+disjoint from the workload; that time is reported separately and is not part
+of a step.  `value` is the learned-PCG throughput; both variants are listed.
 
 The roofline object is for the dominant kernel, the batched persistent PCG
 (k_pcg): achieved = algorithmic bytes of all its launches in the timed steps /
@@ -23,6 +30,8 @@ import os
 import subprocess
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -63,6 +72,60 @@ def cpu_baseline(workload: str, timeout: float = 600.0):
     return rec
 
 
+def train_lpc(ctx, steps, seed=0):
+    """Train the learned preconditioner on the GPU (seeded training meshes, disjoint from the workloads)."""
+    import paper_1903_12359_amd as pg
+    from paper_1903_12359_amd.lpc_train import TrainingSet, init_params, train, training_meshes
+    t0 = time.perf_counter()
+    tset = TrainingSet(ctx, training_meshes(seed=seed))
+    t1 = time.perf_counter()
+    lpc = pg.LPC(ctx, init_params(seed))
+    hist = train(ctx, lpc, tset, steps, lr=2e-3, seed=seed)
+    t2 = time.perf_counter()
+    info = {"steps": steps, "train_s": round(t2 - t1, 3), "set_up_s": round(t1 - t0, 3),
+            "plans": len(tset.items), "pieces": int(sum(p.K for p, _, _ in tset.items)),
+            "loss_first": round(float(np.mean(hist[:20])), 5), "loss_last": round(float(np.mean(hist[-20:])), 5),
+            "n_params": lpc.n_params}
+    return lpc, info
+
+
+def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc):
+    def step():
+        times = {}
+        return pg.run(ctx, case.V, case.F, case.label, case.mode, precision=args.precision, tol=args.tol,
+                      V_dev=V_dev, F_dev=F_dev, times=times, lpc=lpc)
+
+    import torch
+    for w in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stage = {}
+    cg_ms = cg_bytes = 0.0
+    cg_launch = 0
+    iters = 0
+    fallback = 0
+    last = None
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        phi, st, info = step()
+        for key, v in info["times"].items():
+            stage[key] = stage.get(key, 0.0) + v
+        for rep in (info["dncp"], info["harmonic"]):
+            cg_ms += rep.cg_kernel_ms
+            cg_bytes += rep.cg_bytes
+            cg_launch += rep.cg_launches
+            iters += rep.total_iters
+            fallback += rep.n_fallback
+        last = (st, info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = 1e3 * elapsed / args.steps
+    st, info = last
+    return dict(ms_per_step=ms_per_step, value=case.nv / (ms_per_step / 1e3) / 1e6, cg_ms=cg_ms,
+                cg_bytes=cg_bytes, cg_launch=cg_launch, iters=iters // args.steps, fallback=fallback,
+                stage={k: round(1e3 * v / args.steps, 3) for k, v in stage.items()}, st=st, info=info)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +134,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
+    ap.add_argument("--lpc-steps", type=int, default=400, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a kernel of known traffic for counter scaling)")
@@ -80,7 +145,6 @@ def main():
               "single device; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1903_12359_amd as pg
@@ -101,46 +165,28 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        times = {}
-        phi, st, info = pg.run(ctx, case.V, case.F, case.label, case.mode, precision=args.precision,
-                               tol=args.tol, V_dev=V_dev, F_dev=F_dev, times=times)
-        return phi, st, info
-
-    for w in range(args.warmup):
-        step()
-        print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    stage = {}
-    cg_ms = cg_bytes = 0.0
-    cg_launch = 0
-    iters = 0
-    last = None
-    t_start = time.perf_counter()
-    for k in range(args.steps):
-        phi, st, info = step()
-        for key, v in info["times"].items():
-            stage[key] = stage.get(key, 0.0) + v
-        for rep in (info["dncp"], info["harmonic"]):
-            cg_ms += rep.cg_kernel_ms
-            cg_bytes += rep.cg_bytes
-            cg_launch += rep.cg_launches
-            iters += rep.total_iters
-        last = (st, info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = case.nv / (ms_per_step / 1e3) / 1e6
-    st, info = last
-    achieved = cg_bytes / (cg_ms / 1e3) / 1e9 if cg_ms > 0 else 0.0
+    res = {}
+    lpc_info = None
+    if args.precond in ("jacobi", "both"):
+        res["jacobi"] = time_variant(pg, ctx, case, V_dev, F_dev, args, None)
+        print(f"[bench] jacobi: {res['jacobi']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    if args.precond in ("learned", "both"):
+        lpc, lpc_info = train_lpc(ctx, args.lpc_steps)
+        print(f"[bench] learned preconditioner trained: {lpc_info}", file=sys.stderr, flush=True)
+        res["learned"] = time_variant(pg, ctx, case, V_dev, F_dev, args, lpc)
+        print(f"[bench] learned: {res['learned']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    head = res["learned"] if "learned" in res else res["jacobi"]
+    headname = "learned" if "learned" in res else "jacobi"
+    achieved = head["cg_bytes"] / (head["cg_ms"] / 1e3) / 1e9 if head["cg_ms"] > 0 else 0.0
+    st, info = head["st"], head["info"]
     rec = {
-        "metric": "Mvertices/s end-to-end PGCP at rel. residual 1e-10 (Jacobi-PCG)",
-        "value": round(value, 4),
+        "metric": "Mvertices/s end-to-end PGCP at rel. residual 1e-10; learned-PCG vs Jacobi-PCG",
+        "value": round(head["value"], 4),
         "unit": "Mvertices/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(head["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -148,17 +194,28 @@ def main():
         "data": "synthetic",
         "config": {"workload": describe(case, info["dncp"].n_sub),
                    "nv": case.nv, "nf": case.nf, "pieces": info["dncp"].n_sub, "precision": args.precision,
-                   "tol": args.tol, "preconditioner": "jacobi"},
+                   "tol": args.tol, "preconditioner": headname},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_pcg (batched persistent PCG)", "launches": cg_launch,
-                     "avg_launch_ms": round(cg_ms / max(cg_launch, 1), 4),
-                     "cg_iterations_per_step": iters // args.steps},
-        "stages_ms": {k: round(1e3 * v / args.steps, 3) for k, v in stage.items()},
+                     "kernel": "k_pcg (batched persistent PCG)", "launches": head["cg_launch"],
+                     "avg_launch_ms": round(head["cg_ms"] / max(head["cg_launch"], 1), 4),
+                     "cg_iterations_per_step": head["iters"]},
+        "stages_ms": head["stage"],
         "quality": {"mean_abs_d_deg": st["mean_abs_d"], "max_mu": st["max_mu"], "n_flipped": st["n_flipped"],
                     "dncp_max_relres": float(info["dncp"].relres.max()),
                     "harmonic_max_relres": float(info["harmonic"].relres.max())},
     }
+    for name, r in res.items():
+        rec[name] = {"value": round(r["value"], 4), "ms_per_step": round(r["ms_per_step"], 3),
+                     "cg_iterations_per_step": r["iters"], "cg_ms_per_step": round(r["cg_ms"] / args.steps, 3),
+                     "stages_ms": r["stage"], "n_fallback": r["fallback"]}
+    if "learned" in res and "jacobi" in res:
+        rec["learned_vs_jacobi"] = {
+            "speedup_end_to_end": round(res["jacobi"]["ms_per_step"] / res["learned"]["ms_per_step"], 4),
+            "iteration_ratio": round(res["jacobi"]["iters"] / max(res["learned"]["iters"], 1), 4),
+            "cg_time_ratio": round(res["jacobi"]["cg_ms"] / max(res["learned"]["cg_ms"], 1e-9), 4)}
+    if lpc_info is not None:
+        rec["lpc_training"] = lpc_info
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle (one thread) on the same mesh", file=sys.stderr, flush=True)
         cb = cpu_baseline(args.workload)

@@ -411,14 +411,16 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
 
 
 def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,
-        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64"):
+        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64", lpc=None):
     """Algorithm 3 end to end; returns (phi_dev, dist_stats, reports).
 
     V, F, label are host arrays (the partition runs on the host); V_dev/F_dev
     are their device copies (made here if not given).  `precision` is the
     inner-solve precision of the harmonic solve; the DNCP solve uses
     `dncp_precision` (FP64 by default: its free-boundary system has a
-    near-null space that FP32 CG cannot resolve, see the design notes).
+    near-null space that FP32 CG cannot resolve).  With `lpc` (an LPC) both
+    solves use the learned sparse approximate inverse instead of Jacobi; the
+    network runs on the device right before each solve (inside the timing).
     """
     import torch
     dev = f"cuda:{ctx.device}"
@@ -436,7 +438,7 @@ def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inn
     times["partition"] = time.perf_counter() - t
     t = time.perf_counter()
     assemble_cotan(ctx, plan, V_dev)
-    bdy, rep1 = local_param(ctx, plan, precision=dncp_precision, tol=tol, inner_tol=inner_tol)
+    bdy, rep1 = local_param(ctx, plan, precision=dncp_precision, tol=tol, inner_tol=inner_tol, lpc=lpc)
     bdy_h = bdy.cpu().numpy()
     times["assemble+dncp"] = time.perf_counter() - t
     t = time.perf_counter()
@@ -444,7 +446,8 @@ def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inn
     times["weld"] = time.perf_counter() - t
     t = time.perf_counter()
     welded_dev = torch.from_numpy(welded).to(dev)
-    phi, rep2 = harmonic_solve(ctx, plan, welded_dev, precision=precision, tol=tol, inner_tol=inner_tol)
+    phi, rep2 = harmonic_solve(ctx, plan, welded_dev, precision=precision, tol=tol, inner_tol=inner_tol,
+                               lpc=lpc)
     sync()
     times["harmonic"] = time.perf_counter() - t
     t = time.perf_counter()

@@ -25,7 +25,8 @@ DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang
                 "-munsafe-fp-atomics"]
 HOST_SOURCES = ["partition.cpp", "weld.cpp", "api.cpp"]
 HOST_EXTRA = {"weld.cpp": ["-fcx-limited-range"]}
-DEVICE_SOURCES = ["device.hip", "lpc.hip"]
+DEVICE_EXTRA = {"weld_dev.hip": ["-fcx-limited-range"]}
+DEVICE_SOURCES = ["device.hip", "lpc.hip", "weld_dev.hip"]
 
 
 def _hipcc():
@@ -46,7 +47,7 @@ def build(verbose: bool = True) -> str:
     objs = []
     for src in DEVICE_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([hipcc, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([hipcc, *COMMON, *DEVICE_FLAGS, *DEVICE_EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))

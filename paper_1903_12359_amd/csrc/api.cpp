@@ -136,6 +136,7 @@ pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts*
 
 pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv_host, double* welded_uv_host) {
     if (!P || !bdy_uv_host || !welded_uv_host) return bad(ctx, "null argument");
+    if (ctx && !P->host_only) return fail(ctx, pgcp::weld_all_device(ctx, P, bdy_uv_host, welded_uv_host));
     return fail(ctx, pgcp::weld_all(P, bdy_uv_host, welded_uv_host));
 }
 

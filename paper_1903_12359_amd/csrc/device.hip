@@ -48,7 +48,7 @@ void free_part_device(pgcp_part* P) {
                      &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_sl_rev, &P->d_val64, &P->d_val32,
                      &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
-                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q,
+                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2,
                      &P->d_partial, &P->d_bar, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
                      &P->d_flags, &P->wmap32.d_wg_sub, &P->wmap32.d_wg_s0, &P->wmap32.d_wg_s1,
                      &P->wmap32.d_sub_pbase, &P->wmap32.d_sub_nwg, &P->wmap32.d_wg_rank,
@@ -112,6 +112,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_p0, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_p1, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_q, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_r2, N * 16)).code) return e;
     const size_t K = (size_t)P->K;
     if ((e = dev_alloc(P->d_rnorm, K * 2 * 8)).code) return e;
     if ((e = dev_alloc(P->d_scale, K * 2 * 8)).code) return e;
@@ -311,7 +312,8 @@ struct CGArgs {
     typename Vec2<T>::type* z;
     typename Vec2<T>::type* pa;
     typename Vec2<T>::type* pb;
-    typename Vec2<T>::type* q;     // streaming kernel only: A p of the own rows
+    typename Vec2<T>::type* q;     // A p (streaming kernel: all rows; SPAI: published halo rows)
+    typename Vec2<T>::type* r2;    // second residual buffer (SPAI: r alternates between r and r2)
     const T* mval;                 // learned SPAI off-diagonal values (SELL layout), or null
     const T* mdiag;                // learned SPAI diagonal
     const int32_t* pc;             // [K] 1 = the piece uses the SPAI, 0 = Jacobi (null: all Jacobi)
@@ -442,9 +444,14 @@ __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int 
 
 // z = M r for one row with the learned SPAI (M has the Laplacian's pattern):
 // own-workgroup columns from LDS (register kernel) or all from the coherent path.
+// Columns outside [lo, hi) take r from rglob, or, when qglob is given, rebuild
+// this iteration's residual there as rglob - alpha qglob from the previous
+// residual and A p that the owning workgroup published before the barrier, so
+// the SPAI needs no barrier of its own.
 template <typename T, typename V2>
 __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, const V2* lds_r, int64_t lo,
-                                       int64_t hi, const V2* rglob) {
+                                       int64_t hi, const V2* rglob, const V2* qglob = nullptr, T ax = (T)0,
+                                       T ay = (T)0) {
     const int64_t s = rw >> 6;
     const int64_t base = a.sl_ptr[s] + (rw & 63);
     const int w = a.sl_w[s];
@@ -455,7 +462,17 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
         const T m = a.mval[el];
         if (m == (T)0) continue;
         const int c = a.sl_col[el];
-        const V2 rc = (c >= lo && c < hi) ? lds_r[c - lo] : ld_c(rglob + c);
+        V2 rc;
+        if (c >= lo && c < hi) {
+            rc = lds_r[c - lo];
+        } else {
+            rc = ld_c(rglob + c);
+            if (qglob) {
+                const V2 qc = ld_c(qglob + c);
+                rc.x -= ax * qc.x;
+                rc.y -= ay * qc.y;
+            }
+        }
         zx += m * rc.x;
         zy += m * rc.y;
     }
@@ -595,6 +612,8 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     int stat = 0;
     V2* pold = a.pa;
     V2* pnew = a.pb;
+    V2* rcur = a.r;    // residual of the previous iteration as published (SPAI halo)
+    V2* rnext = a.r2;
 
     while (!(done[0] && done[1])) {
         if (it >= a.max_iter) {
@@ -666,6 +685,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             }
             q[j].x = qx;
             q[j].y = qy;
+            if (spai && expo[j]) st_c(a.q + rw, q[j]);
             pq[0] += (double)pn[j].x * (double)qx;
             pq[1] += (double)pn[j].y * (double)qy;
         }
@@ -726,17 +746,13 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             for (int j = 0; j < R; ++j) {
                 if (!valid[j]) continue;
                 lds_p[rows[j] - lo] = r[j];
-                if (expo[j]) st_c(a.r + rows[j], r[j]);
+                if (expo[j]) st_c(rnext + rows[j], r[j]);
             }
-            nbar++;
-            if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
-                stat = 3;
-                break;
-            }
+            __syncthreads();
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (!valid[j] || msk[j]) continue;
-                z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, a.r);
+                z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, rcur, a.q, ax, ay);
                 if (expo[j]) st_c(a.z + rows[j], z[j]);
                 acc2[0] += (double)r[j].x * (double)z[j].x;
                 acc2[1] += (double)r[j].y * (double)z[j].y;
@@ -782,6 +798,9 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         V2* t = pold;
         pold = pnew;
         pnew = t;
+        t = rcur;
+        rcur = rnext;
+        rnext = t;
     }
     // the correction leaves through plain stores (read by the next kernel)
 #pragma unroll
@@ -873,6 +892,8 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
     int stat = 0;
     V2* pold = a.pa;
     V2* pnew = a.pb;
+    V2* rcur = a.r;
+    V2* rnext = a.r2;
 
     while (!(done[0] && done[1])) {
         if (it >= a.max_iter) {
@@ -921,7 +942,10 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
                 pq[0] += (double)p.x * (double)qx;
                 pq[1] += (double)p.y * (double)qy;
             }
-            a.q[rw] = q;
+            if (spai)
+                st_c(a.q + rw, q);   // gathered by the neighbours to rebuild their halo residual
+            else
+                a.q[rw] = q;
         }
         bsum<BLK, 2>(pq, lds);
         if (threadIdx.x == 0) {
@@ -960,15 +984,22 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
             if (a.mask[rw]) continue;
-            const V2 p = ld_c(pnew + rw), q = a.q[rw];
-            V2 e = a.e[rw], r = spai ? ld_c(a.r + rw) : a.r[rw], z;
+            const V2 p = ld_c(pnew + rw), q = spai ? ld_c(a.q + rw) : a.q[rw];
+            V2 e = a.e[rw], r = spai ? ld_c(rcur + rw) : a.r[rw], z;
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
             r.y -= ay * q.y;
             a.e[rw] = e;
             if (spai) {
-                st_c(a.r + rw, r);   // gathered by the neighbours for z = M r
+                // z = M r with the neighbours' new residual rebuilt from rcur and q
+                st_c(rnext + rw, r);
+                z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, rcur, a.q, ax, ay);
+                st_c(a.z + rw, z);
+                acc2[0] += (double)r.x * (double)z.x;
+                acc2[1] += (double)r.y * (double)z.y;
+                acc2[2] += (double)r.x * (double)r.x;
+                acc2[3] += (double)r.y * (double)r.y;
                 continue;
             }
             const T dinv = (T)1 / a.diag[rw];
@@ -981,24 +1012,7 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             acc2[2] += (double)r.x * (double)r.x;
             acc2[3] += (double)r.y * (double)r.y;
         }
-        if (spai) {
-            nbar++;
-            if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
-                stat = 3;
-                break;
-            }
-            for (int s = s0 + wave; s < s1; s += NW) {
-                const int64_t rw = (int64_t)s * 64 + lane;
-                if (a.mask[rw]) continue;
-                const V2 r = ld_c(a.r + rw);
-                const V2 z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
-                st_c(a.z + rw, z);
-                acc2[0] += (double)r.x * (double)z.x;
-                acc2[1] += (double)r.y * (double)z.y;
-                acc2[2] += (double)r.x * (double)r.x;
-                acc2[3] += (double)r.y * (double)r.y;
-            }
-        }
+
         bsum<BLK, 4>(acc2, lds);
         if (threadIdx.x == 0) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
@@ -1036,6 +1050,11 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         V2* t = pold;
         pold = pnew;
         pnew = t;
+        if (spai) {
+            t = rcur;
+            rcur = rnext;
+            rnext = t;
+        }
     }
     if (leader) {
         a.iters[sub] = it;
@@ -1473,10 +1492,68 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     const int64_t cap = (int64_t)per_cu * n_cu;
     const int64_t spw = (int64_t)(cfg.blk / 64) * cfg.R;   // slices per workgroup
     const int K = P->K;
-    std::vector<int64_t> nw(K);
-    for (int i = 0; i < K; ++i) {
-        int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
-        nw[i] = std::max<int64_t>(1, (ns + spw - 1) / spw);
+    std::vector<int64_t> nw(K, 1);
+    if (cfg.R <= 0 && !cfg.stream) return Error{PGCP_E_INVALID, "slices per wave must be positive"};
+    if (spw > 0)
+        for (int i = 0; i < K; ++i) {
+            int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            nw[i] = std::max<int64_t>(1, (ns + spw - 1) / spw);
+        }
+    if (cfg.stream && cfg.R <= 0) {
+        // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
+        // in proportion to ns_i^1.5 (its rows times its expected CG iterations,
+        // which grow like sqrt(ns_i) for these Laplacians), at least one and at
+        // most one per slice.  Pieces span all XCDs.
+        double tw = 0.0;
+        for (int i = 0; i < K; ++i) tw += std::pow((double)((P->row0[i + 1] - P->row0[i]) / 64), 1.5);
+        int64_t G = 0;
+        for (double target = (double)cap; target >= K; target *= 0.97) {
+            G = 0;
+            for (int i = 0; i < K; ++i) {
+                const int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+                const double want = target * std::pow((double)ns, 1.5) / tw;
+                nw[i] = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)std::floor(want)));
+                G += nw[i];
+            }
+            if (G <= cap) break;
+        }
+        if (G > cap) return Error{PGCP_OK, ""};
+        W->blk = cfg.blk;
+        W->rows_per_thread = 0;
+        W->stream = 1;
+        W->n_xcd = n_xcd;
+        W->n_wg = (int)G;
+        W->wg_sub.assign(G, -1);
+        W->wg_rank.assign(G, 0);
+        W->wg_s0.assign(G, 0);
+        W->wg_s1.assign(G, 0);
+        W->sub_pbase.assign(K, 0);
+        W->sub_nwg.assign(K, 0);
+        int32_t pb = 0;
+        int64_t g = 0;
+        for (int i = 0; i < K; ++i) {
+            W->sub_pbase[i] = pb;
+            W->sub_nwg[i] = (int32_t)nw[i];
+            pb += (int32_t)nw[i];
+            const int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            for (int64_t t = 0; t < nw[i]; ++t, ++g) {
+                W->wg_sub[g] = i;
+                W->wg_rank[g] = (int32_t)t;
+                W->wg_s0[g] = (int32_t)(sb + ns * t / nw[i]);
+                W->wg_s1[g] = (int32_t)(sb + ns * (t + 1) / nw[i]);
+            }
+        }
+        W->n_partials = pb;
+        Error e{PGCP_OK, ""};
+        if ((e = upload(W->d_wg_sub, W->wg_sub, ctx->stream)).code) return e;
+        if ((e = upload(W->d_wg_rank, W->wg_rank, ctx->stream)).code) return e;
+        if ((e = upload(W->d_wg_s0, W->wg_s0, ctx->stream)).code) return e;
+        if ((e = upload(W->d_wg_s1, W->wg_s1, ctx->stream)).code) return e;
+        if ((e = upload(W->d_sub_pbase, W->sub_pbase, ctx->stream)).code) return e;
+        if ((e = upload(W->d_sub_nwg, W->sub_nwg, ctx->stream)).code) return e;
+        if ((e = dev_alloc(P->d_partial, (size_t)pb * 8 * 8)).code) return e;
+        *fits = true;
+        return Error{PGCP_OK, ""};
     }
     std::vector<int> order(K);
     for (int i = 0; i < K; ++i) order[i] = i;
@@ -1561,6 +1638,7 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.pa = (V2*)P->d_p0.p;
     a.pb = (V2*)P->d_p1.p;
     a.q = (V2*)P->d_q.p;
+    a.r2 = (V2*)P->d_r2.p;
     a.mval = nullptr;
     a.mdiag = nullptr;
     a.pc = nullptr;
@@ -1693,6 +1771,34 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             cands.push_back(PcgCfg{blk, r, 1});
             cands.push_back(PcgCfg{blk, 2 * r, 1});
         }
+    }
+    // The probes time every piece for the same number of iterations, which
+    // cannot show that the streaming kernel's size-weighted map lets large
+    // pieces (that need more iterations) finish sooner; when the pieces'
+    // sizes differ by more than 2x it is used whenever the register-resident
+    // kernel does not fit.
+    int64_t ns_min = INT64_MAX, ns_max = 0;
+    for (int i = 0; i < P->K; ++i) {
+        const int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+        ns_min = std::min(ns_min, ns);
+        ns_max = std::max(ns_max, ns);
+    }
+    const bool uneven = ns_max > 2 * ns_min;
+    bool reg_fits = false;
+    for (const PcgCfg& c : cands) {
+        if (c.stream) continue;
+        WorkMap T;
+        bool fits;
+        Error e = build_workmap(ctx, P, prec, c, &T, &fits);
+        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
+            dev_free(*b);
+        if (e.code) return e;
+        reg_fits |= fits;
+    }
+    if (uneven && !reg_fits) {
+        cands.clear();
+        cands.push_back(PcgCfg{256, 0, 1});
+        cands.push_back(PcgCfg{512, 0, 1});
     }
     for (const PcgCfg& c : cands) {
         WorkMap T;

@@ -94,7 +94,7 @@ struct pgcp_part {
     pgcp::DevBuf d_chart;                     // [3K] doubles: sphere chart centre (re, im, is-infinity)
 
     // ---------------- solver work space
-    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q;
+    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q, d_r2;
     pgcp::DevBuf d_partial, d_bar, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
@@ -122,6 +122,9 @@ struct pgcp_lpc {
 };
 
 namespace pgcp {
+
+// weld with the point replay on the device (weld_dev.hip)
+Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double* welded_uv);
 
 // learned preconditioner (lpc.hip)
 int64_t lpc_num_params();

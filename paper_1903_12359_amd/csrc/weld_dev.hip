@@ -1,0 +1,566 @@
+// Partial welding with the point replay on the GPU (Sections 3.4, 4.3, 4.4).
+//
+// Every map of a weld is fixed by its shared arc (see weld_maps.h): the host
+// runs the zipper on the arcs of every pair of a round (O(k^2) per pair, pairs
+// in parallel), records the map parameters, and then one kernel sends every
+// other point of the round through its pair's recorded chain
+//     z -> Moebius(close(zip_side(z)))
+// one thread per point.  Points inside a welded union ("tracked": earlier
+// seams) have one coordinate each and stay on the device, indexed by seam
+// slot, for the whole weld.  Loop points keep one coordinate per component
+// until they are glued (a vertex on the boundary between two components has a
+// coordinate in each plane), so the non-arc loop points of a round are
+// uploaded, replayed by the same kernel and read back for the next round's
+// arcs.  The disk step replays tracked points through the geodesic chain of
+// the outer loop and the Cayley map.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "device_util.h"
+#include "pgcp_internal.h"
+#include "weld_maps.h"
+
+namespace pgcp {
+
+using namespace weldmaps;
+
+namespace {
+
+#define HIPTHROW(x)                                                                     \
+    do {                                                                               \
+        hipError_t _e = (x);                                                           \
+        if (_e != hipSuccess) throw Error{PGCP_E_HIP, std::string(#x) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+// ------------------------------------------------------------------ device maps (same branches as the host replay)
+
+struct DZ {
+    double x, y;
+    bool inf;
+};
+
+__device__ __forceinline__ DZ dz(double x, double y, bool inf = false) { return DZ{x, y, inf}; }
+__device__ __forceinline__ void cmul(double ax, double ay, double bx, double by, double& rx, double& ry) {
+    rx = ax * bx - ay * by;
+    ry = ax * by + ay * bx;
+}
+__device__ __forceinline__ void cdiv(double ax, double ay, double bx, double by, double& rx, double& ry) {
+    const double den = bx * bx + by * by;
+    rx = (ax * bx + ay * by) / den;
+    ry = (ay * bx - ax * by) / den;
+}
+__device__ __forceinline__ void csqrtp(double x, double y, double& rx, double& ry) {
+    const double r = sqrt(x * x + y * y);
+    if (r == 0.0) {
+        rx = 0.0;
+        ry = y;
+        return;
+    }
+    if (x >= 0.0) {
+        const double t = sqrt(0.5 * (r + x));
+        rx = t;
+        ry = y / (2.0 * t);
+    } else {
+        const double t = sqrt(0.5 * (r - x));
+        rx = fabs(y) / (2.0 * t);
+        ry = copysign(t, y);
+    }
+}
+
+// zip record: k, z0, z1, zeta, zeta_inf, squared, c[k-1], d[k-1]
+__device__ DZ d_zip(const double* __restrict__ R, DZ p) {
+    const int k = (int)R[0];
+    const double z0x = R[1], z0y = R[2], z1x = R[3], z1y = R[4], zex = R[5], zey = R[6];
+    const bool zeta_inf = R[7] != 0.0, squared = R[8] != 0.0;
+    const double* c = R + 9;
+    const double* d = R + 9 + (k - 1);
+    if (p.inf) {
+        p = dz(1.0, 0.0);
+    } else {
+        const double dx = p.x - z0x, dy = p.y - z0y;
+        if (dx == 0.0 && dy == 0.0) {
+            p = dz(0.0, 0.0, true);
+        } else {
+            double qx, qy;
+            cdiv(p.x - z1x, p.y - z1y, dx, dy, qx, qy);
+            csqrtp(qx, qy, p.x, p.y);
+        }
+    }
+    for (int j = 0; j + 2 <= k; ++j) {
+        const double cj = c[j], dj = d[j];
+        if (p.inf) {
+            if (dj != 0.0) p = dz(0.0, -cj / dj);
+            else continue;
+        } else {
+            // L = c z / (1 + i d z)
+            const double denx = 1.0 - dj * p.y, deny = dj * p.x;
+            if (denx == 0.0 && deny == 0.0) {
+                p = dz(0.0, 0.0, true);
+                continue;
+            }
+            double lx, ly;
+            cdiv(cj * p.x, cj * p.y, denx, deny, lx, ly);
+            p.x = lx;
+            p.y = ly;
+        }
+        double sx, sy;
+        cmul(p.x, p.y, p.x, p.y, sx, sy);
+        csqrtp(sx - 1.0, sy, p.x, p.y);
+    }
+    if (p.inf) {
+        if (zeta_inf) return p;
+        p = dz(-zex, -zey);
+    } else if (!zeta_inf) {
+        double qx, qy;
+        cdiv(p.x, p.y, zex, zey, qx, qy);
+        const double denx = 1.0 - qx, deny = -qy;
+        if (denx == 0.0 && deny == 0.0) return dz(0.0, 0.0, true);
+        double rx, ry;
+        cdiv(p.x, p.y, denx, deny, rx, ry);
+        p.x = rx;
+        p.y = ry;
+    }
+    if (squared) {
+        double sx, sy;
+        cmul(p.x, p.y, p.x, p.y, sx, sy);
+        p.x = sx;
+        p.y = sy;
+    }
+    return p;
+}
+
+// close record: n, eta, eta_inf, c0[n], c1[n]
+__device__ DZ d_close(const double* __restrict__ R, DZ p) {
+    const int n = (int)R[0];
+    const double etx = R[1], ety = R[2];
+    const bool eta_inf = R[3] != 0.0;
+    const double* c0 = R + 4;
+    const double* c1 = R + 4 + n;
+    for (int t = 0; t < n; ++t) {
+        // T(z) = z / (c0 - i c1 z); T(inf) = i / c1
+        if (p.inf) {
+            if (c1[t] != 0.0) p = dz(0.0, 1.0 / c1[t]);
+            else continue;
+        } else {
+            const double denx = c0[t] + c1[t] * p.y, deny = -c1[t] * p.x;
+            if (denx == 0.0 && deny == 0.0) {
+                p = dz(0.0, 0.0, true);
+                continue;
+            }
+            double tx, ty;
+            cdiv(p.x, p.y, denx, deny, tx, ty);
+            p.x = tx;
+            p.y = ty;
+        }
+        double sx, sy;
+        cmul(p.x, p.y, p.x, p.y, sx, sy);
+        csqrtp(sx + 1.0, sy, p.x, p.y);
+    }
+    // h_0
+    if (eta_inf) {
+        if (p.inf) return p;
+        double sx, sy;
+        cmul(p.x, p.y, p.x, p.y, sx, sy);
+        return dz(sx, sy);
+    }
+    if (p.inf) {
+        double sx, sy;
+        cmul(etx, ety, etx, ety, sx, sy);
+        return dz(sx, sy);
+    }
+    double qx, qy;
+    cdiv(p.x, p.y, etx, ety, qx, qy);
+    const double denx = 1.0 - qx, deny = -qy;
+    if (denx == 0.0 && deny == 0.0) return dz(0.0, 0.0, true);
+    double wx, wy;
+    cdiv(p.x, p.y, denx, deny, wx, wy);
+    double sx, sy;
+    cmul(wx, wy, wx, wy, sx, sy);
+    return dz(sx, sy);
+}
+
+// Moebius record: a, b, c, d
+__device__ DZ d_mobius(const double* __restrict__ M, DZ p) {
+    if (p.inf) {
+        double rx, ry;
+        cdiv(M[0], M[1], M[4], M[5], rx, ry);
+        return dz(rx, ry);
+    }
+    double nx, ny, dx, dy;
+    cmul(M[0], M[1], p.x, p.y, nx, ny);
+    nx += M[2];
+    ny += M[3];
+    cmul(M[4], M[5], p.x, p.y, dx, dy);
+    dx += M[6];
+    dy += M[7];
+    if (dx == 0.0 && dy == 0.0) return dz(0.0, 0.0, true);
+    double rx, ry;
+    cdiv(nx, ny, dx, dy, rx, ry);
+    return dz(rx, ry);
+}
+
+__device__ DZ d_cayley(DZ p) {
+    if (p.inf) return dz(1.0, 0.0);
+    double rx, ry;
+    cdiv(p.x, p.y - 1.0, p.x, p.y + 1.0, rx, ry);
+    return dz(rx, ry);
+}
+
+// Per pair: offsets of the side-A and side-B zip records, of the close record
+// and of the Moebius record (-1: absent), and 1 for the Cayley map at the end.
+struct PairDesc {
+    int64_t zip[2], close, mob;
+    int64_t cayley;
+};
+
+// Points: uidx < n_seam addresses the tracked array, otherwise the round's
+// uploaded loop points; pair; side (0 = A, 1 = B).
+__global__ void __launch_bounds__(BLOCK) k_weld_replay(int64_t npts, const int32_t* __restrict__ pts,
+                                                        const PairDesc* __restrict__ desc,
+                                                        const double* __restrict__ rec, int64_t n_seam,
+                                                        double2* __restrict__ zt, double2* __restrict__ ztmp) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= npts) return;
+    const int64_t u = pts[3 * t];
+    const PairDesc D = desc[pts[3 * t + 1]];
+    const int side = pts[3 * t + 2];
+    double2* slot = u < n_seam ? zt + u : ztmp + (u - n_seam);
+    const double2 v = *slot;
+    DZ p = isinf(v.x) ? dz(0.0, 0.0, true) : dz(v.x, v.y);
+    p = d_zip(rec + D.zip[side], p);
+    if (D.close >= 0) p = d_close(rec + D.close, p);
+    if (D.mob >= 0) p = d_mobius(rec + D.mob, p);
+    if (D.cayley) p = d_cayley(p);
+    const double inf = __builtin_inf();
+    *slot = p.inf ? make_double2(inf, inf) : make_double2(p.x, p.y);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_weld_scatter(int64_t n, const int32_t* __restrict__ slot,
+                                                         const double2* __restrict__ val, double2* __restrict__ zt) {
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < n) zt[slot[t]] = val[t];
+}
+
+// ------------------------------------------------------------------ host side
+
+struct DComp {
+    std::vector<int> outer;
+    std::vector<EP> zo;
+    std::vector<int32_t> tslot;   // seam slots of the tracked points
+};
+
+void put_zip(std::vector<double>& r, const ZipRecord& Z) {
+    r.push_back((double)Z.k);
+    r.push_back(Z.z0.real());
+    r.push_back(Z.z0.imag());
+    r.push_back(Z.z1.real());
+    r.push_back(Z.z1.imag());
+    r.push_back(Z.zeta.real());
+    r.push_back(Z.zeta.imag());
+    r.push_back(Z.zeta_inf ? 1.0 : 0.0);
+    r.push_back(Z.squared ? 1.0 : 0.0);
+    r.insert(r.end(), Z.c.begin(), Z.c.end());
+    r.insert(r.end(), Z.d.begin(), Z.d.end());
+}
+void put_close(std::vector<double>& r, const CloseRecord& C) {
+    r.push_back((double)C.c0.size());
+    r.push_back(C.eta.real());
+    r.push_back(C.eta.imag());
+    r.push_back(C.eta_inf ? 1.0 : 0.0);
+    r.insert(r.end(), C.c0.begin(), C.c0.end());
+    r.insert(r.end(), C.c1.begin(), C.c1.end());
+}
+void put_mobius(std::vector<double>& r, const Mobius& M) {
+    for (const cplx& v : {M.a, M.b, M.c, M.d}) {
+        r.push_back(v.real());
+        r.push_back(v.imag());
+    }
+}
+inline double2 to_d2(const EP& p) {
+    const double inf = std::numeric_limits<double>::infinity();
+    return p.inf ? make_double2(inf, inf) : make_double2(p.z.real(), p.z.imag());
+}
+inline EP from_d2(const double2& v) { return std::isinf(v.x) ? EP{0.0, true} : EP{cplx(v.x, v.y), false}; }
+
+// One weld's host part: arcs, records, the new component's structure.
+struct Job {
+    ZipRecord ZA, ZB;
+    CloseRecord CR;
+    Mobius M;
+    DComp C;
+    std::vector<EP> restA, restB;   // non-arc loop points (replayed on the device)
+    std::vector<int32_t> arc_slot;  // arc points that become tracked, and their values
+    std::vector<EP> arc_val;
+    int na_rest = 0, nb_rest = 0;
+    EP a_k, a_0;
+    bool closed = false;
+};
+
+Job weld_job(const DComp& A, const DComp& B, bool closed, const std::vector<int32_t>& slot_of) {
+    Job J;
+    J.closed = closed;
+    int start, k;
+    const int La = (int)A.outer.size(), Lb = (int)B.outer.size();
+    if (closed) {
+        if (La != Lb) throw Error{PGCP_E_WELD, "closed weld of loops of different length"};
+        start = (int)(std::min_element(A.outer.begin(), A.outer.end()) - A.outer.begin());
+        k = La - 1;
+    } else {
+        k = shared_arc(A.outer, B.outer, &start);
+        if (k < 2) throw Error{PGCP_E_WELD, "components do not share one contiguous arc"};
+    }
+    std::vector<int> Aid(La), Bid(Lb);
+    std::vector<EP> Az(La), Bz(Lb);
+    for (int s = 0; s < La; ++s) {
+        Aid[s] = A.outer[(start + s) % La];
+        Az[s] = A.zo[(start + s) % La];
+    }
+    const int i0 = (int)(std::find(B.outer.begin(), B.outer.end(), Aid[0]) - B.outer.begin());
+    if (i0 >= Lb) throw Error{PGCP_E_WELD, "arc correspondence broken"};
+    for (int s = 0; s < Lb; ++s) {
+        const int t = ((i0 - s) % Lb + Lb) % Lb;
+        Bid[s] = B.outer[t];
+        Bz[s] = B.zo[t];
+    }
+    for (int s = 0; s <= k; ++s)
+        if (Aid[s] != Bid[s]) throw Error{PGCP_E_WELD, "arc correspondence broken"};
+    std::vector<EP> arcA(Az.begin(), Az.begin() + k + 1), arcB(Bz.begin(), Bz.begin() + k + 1);
+    J.ZA = zip_arc(arcA, k, +1, false);
+    J.ZB = zip_arc(arcB, k, -1, false);
+    J.CR = close_arcs(arcA, arcB, k);
+    // auxiliary points 0 and infinity of both sides fix the normalisation
+    const EP a0 = close_point(J.CR, zip_point(J.ZA, EP{0.0, false}));
+    const EP ai = close_point(J.CR, zip_point(J.ZA, EP{0.0, true}));
+    const EP b0 = close_point(J.CR, zip_point(J.ZB, EP{0.0, false}));
+    const EP bi = close_point(J.CR, zip_point(J.ZB, EP{0.0, true}));
+    if (a0.inf || b0.inf || ai.inf || bi.inf) throw Error{PGCP_E_WELD, "auxiliary point sent to infinity"};
+    J.M = mobius3(a0.z, b0.z, 0.5 * (ai.z + bi.z));
+    for (auto& p : arcA) p = mobius_apply(J.M, p);
+    J.na_rest = La - k - 1;
+    J.nb_rest = Lb - k - 1;
+    J.restA.assign(Az.begin() + k + 1, Az.end());
+    J.restB.assign(Bz.begin() + k + 1, Bz.end());
+    if (!closed) {
+        J.C.outer.reserve(La - k + Lb - k);
+        J.C.outer.push_back(Aid[k]);
+        for (int s = 0; s < J.na_rest; ++s) J.C.outer.push_back(Aid[k + 1 + s]);
+        J.C.outer.push_back(Aid[0]);
+        for (int s = J.nb_rest - 1; s >= 0; --s) J.C.outer.push_back(Bid[k + 1 + s]);
+        J.a_k = arcA[k];
+        J.a_0 = arcA[0];
+        for (int s = 1; s < k; ++s) {
+            J.arc_slot.push_back(slot_of[Aid[s]]);
+            J.arc_val.push_back(arcA[s]);
+        }
+    } else {
+        for (int s = 0; s <= k; ++s) {
+            J.arc_slot.push_back(slot_of[Aid[s]]);
+            J.arc_val.push_back(arcA[s]);
+        }
+    }
+    J.C.tslot = A.tslot;
+    J.C.tslot.insert(J.C.tslot.end(), B.tslot.begin(), B.tslot.end());
+    J.C.tslot.insert(J.C.tslot.end(), J.arc_slot.begin(), J.arc_slot.end());
+    return J;
+}
+
+}  // namespace
+
+Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double* welded_uv) {
+    hipStream_t s = ctx->stream;
+    const int K = P->K;
+    const int64_t ns = P->n_seam;
+    DevBuf zt, ztmp, recb, descb, ptsb, sslot, sval;
+    auto release = [&]() {
+        for (DevBuf* b : {&zt, &ztmp, &recb, &descb, &ptsb, &sslot, &sval}) dev_free(*b);
+    };
+    try {
+        std::vector<int32_t> slot_of(P->nv, -1);
+        for (int64_t t = 0; t < ns; ++t) slot_of[P->seam_gv[t]] = (int32_t)t;
+        Error e{PGCP_OK, ""};
+        if ((e = dev_alloc(zt, (size_t)std::max<int64_t>(ns, 1) * 16)).code) throw e;
+        std::vector<DComp> comps(K);
+        std::vector<char> alive(K, 1);
+        for (int i = 0; i < K; ++i) {
+            const int e0 = P->loop_ptr[i], e1 = P->loop_ptr[i + 1];
+            comps[i].outer.assign(P->loop_gv.begin() + e0, P->loop_gv.begin() + e1);
+            comps[i].zo.resize(e1 - e0);
+            for (int t = e0; t < e1; ++t) comps[i].zo[t - e0] = EP{cplx(bdy_uv[2 * t], bdy_uv[2 * t + 1]), false};
+        }
+        const int nrounds = (int)P->weld_rounds.size();
+        // upload (slot, value) pairs and scatter them into the tracked array
+        auto scatter = [&](const std::vector<int32_t>& sl, const std::vector<double2>& v) -> Error {
+            if (sl.empty()) return Error{PGCP_OK, ""};
+            Error er{PGCP_OK, ""};
+            if ((er = upload(sslot, sl, s)).code) return er;
+            if ((er = upload(sval, v, s)).code) return er;
+            k_weld_scatter<<<grid_for((int64_t)sl.size()), BLOCK, 0, s>>>((int64_t)sl.size(),
+                                                                          (const int32_t*)sslot.p,
+                                                                          (const double2*)sval.p, (double2*)zt.p);
+            HIPTHROW(hipGetLastError());
+            return Error{PGCP_OK, ""};
+        };
+        for (int r = 0; r < nrounds; ++r) {
+            const auto& rnd = P->weld_rounds[r];
+            const bool closed = P->mode == PGCP_SPHERE && r == nrounds - 1;
+            std::vector<Job> jobs(rnd.size());
+            std::vector<Error> errs(rnd.size(), Error{PGCP_OK, ""});
+#pragma omp parallel for schedule(dynamic) if (rnd.size() > 1)
+            for (size_t t = 0; t < rnd.size(); ++t) {
+                try {
+                    jobs[t] = weld_job(comps[rnd[t].first], comps[rnd[t].second], closed, slot_of);
+                } catch (const Error& er) {
+                    errs[t] = er;
+                }
+            }
+            for (auto& er : errs)
+                if (er.code != PGCP_OK) throw er;
+            // pack the records and the point list of the round
+            std::vector<double> rec;
+            std::vector<PairDesc> desc(rnd.size());
+            std::vector<int32_t> pts;
+            std::vector<double2> tmp;
+            for (size_t t = 0; t < rnd.size(); ++t) {
+                Job& J = jobs[t];
+                desc[t].zip[0] = (int64_t)rec.size();
+                put_zip(rec, J.ZA);
+                desc[t].zip[1] = (int64_t)rec.size();
+                put_zip(rec, J.ZB);
+                desc[t].close = (int64_t)rec.size();
+                put_close(rec, J.CR);
+                desc[t].mob = (int64_t)rec.size();
+                put_mobius(rec, J.M);
+                desc[t].cayley = 0;
+                const DComp& A = comps[rnd[t].first];
+                const DComp& B = comps[rnd[t].second];
+                for (int32_t sl : A.tslot) pts.insert(pts.end(), {sl, (int32_t)t, 0});
+                for (int32_t sl : B.tslot) pts.insert(pts.end(), {sl, (int32_t)t, 1});
+                for (const EP& p : J.restA) {
+                    pts.insert(pts.end(), {(int32_t)(ns + (int64_t)tmp.size()), (int32_t)t, 0});
+                    tmp.push_back(to_d2(p));
+                }
+                for (const EP& p : J.restB) {
+                    pts.insert(pts.end(), {(int32_t)(ns + (int64_t)tmp.size()), (int32_t)t, 1});
+                    tmp.push_back(to_d2(p));
+                }
+            }
+            if (ns + (int64_t)tmp.size() > INT32_MAX) throw Error{PGCP_E_INVALID, "weld point index overflow"};
+            const int64_t npts = (int64_t)pts.size() / 3;
+            if ((e = upload(recb, rec, s)).code) throw e;
+            if ((e = upload(descb, desc, s)).code) throw e;
+            if ((e = upload(ptsb, pts, s)).code) throw e;
+            if ((e = upload(ztmp, tmp, s)).code) throw e;
+            if (npts > 0) {
+                k_weld_replay<<<grid_for(npts), BLOCK, 0, s>>>(npts, (const int32_t*)ptsb.p,
+                                                               (const PairDesc*)descb.p, (const double*)recb.p, ns,
+                                                               (double2*)zt.p, (double2*)ztmp.p);
+                HIPTHROW(hipGetLastError());
+            }
+            // arc points of this round become tracked points with their final values
+            std::vector<int32_t> asl;
+            std::vector<double2> aval;
+            for (const Job& J : jobs)
+                for (size_t u = 0; u < J.arc_slot.size(); ++u) {
+                    asl.push_back(J.arc_slot[u]);
+                    aval.push_back(to_d2(J.arc_val[u]));
+                }
+            if ((e = scatter(asl, aval)).code) throw e;
+            if (!tmp.empty())
+                HIPTHROW(hipMemcpyAsync(tmp.data(), ztmp.p, tmp.size() * 16, hipMemcpyDeviceToHost, s));
+            HIPTHROW(hipStreamSynchronize(s));
+            // new components: loop coordinates from the replayed points
+            size_t off = 0;
+            for (size_t t = 0; t < rnd.size(); ++t) {
+                Job& J = jobs[t];
+                std::vector<EP> ra(J.na_rest), rb(J.nb_rest);
+                for (int u = 0; u < J.na_rest; ++u) ra[u] = from_d2(tmp[off++]);
+                for (int u = 0; u < J.nb_rest; ++u) rb[u] = from_d2(tmp[off++]);
+                if (!J.closed) {
+                    J.C.zo.reserve(J.C.outer.size());
+                    J.C.zo.push_back(J.a_k);
+                    for (int u = 0; u < J.na_rest; ++u) J.C.zo.push_back(ra[u]);
+                    J.C.zo.push_back(J.a_0);
+                    for (int u = J.nb_rest - 1; u >= 0; --u) J.C.zo.push_back(rb[u]);
+                }
+                comps[rnd[t].first] = std::move(J.C);
+                comps[rnd[t].second] = DComp();
+                alive[rnd[t].second] = 0;
+            }
+        }
+        int last = -1, nlive = 0;
+        for (int i = 0; i < K; ++i)
+            if (alive[i]) {
+                last = i;
+                nlive++;
+            }
+        if (nlive != 1) throw Error{PGCP_E_WELD, "weld plan did not finish"};
+        DComp& C = comps[last];
+        if (P->mode == PGCP_DISK) {
+            // geodesic algorithm on the outer loop (squared final map), then Cayley
+            const int L = (int)C.outer.size();
+            const int st = (int)(std::min_element(C.outer.begin(), C.outer.end()) - C.outer.begin());
+            std::vector<int> id(L);
+            std::vector<EP> arc(L);
+            for (int u = 0; u < L; ++u) {
+                id[u] = C.outer[(st + u) % L];
+                arc[u] = C.zo[(st + u) % L];
+            }
+            ZipRecord Z = zip_arc(arc, L - 1, +1, true);
+            std::vector<double> rec;
+            put_zip(rec, Z);
+            std::vector<PairDesc> desc(1);
+            desc[0].zip[0] = desc[0].zip[1] = 0;
+            desc[0].close = -1;
+            desc[0].mob = -1;
+            desc[0].cayley = 1;
+            std::vector<int32_t> pts;
+            for (int32_t sl : C.tslot) pts.insert(pts.end(), {sl, 0, 0});
+            const int64_t npts = (int64_t)pts.size() / 3;
+            if (npts > 0) {
+                if ((e = upload(recb, rec, s)).code) throw e;
+                if ((e = upload(descb, desc, s)).code) throw e;
+                if ((e = upload(ptsb, pts, s)).code) throw e;
+                k_weld_replay<<<grid_for(npts), BLOCK, 0, s>>>(npts, (const int32_t*)ptsb.p,
+                                                               (const PairDesc*)descb.p, (const double*)recb.p, ns,
+                                                               (double2*)zt.p, (double2*)zt.p);
+                HIPTHROW(hipGetLastError());
+            }
+            for (int u = 0; u < L; ++u) {
+                const EP& p = arc[u];
+                arc[u] = p.inf ? EP{1.0, false}
+                               : EP{(p.z - cplx(0.0, 1.0)) / (p.z + cplx(0.0, 1.0)), false};
+            }
+            C.outer = id;
+            C.zo = arc;
+            HIPTHROW(hipStreamSynchronize(s));
+        }
+        std::vector<int32_t> osl;
+        std::vector<double2> oval;
+        for (size_t u = 0; u < C.outer.size(); ++u) {
+            osl.push_back(slot_of[C.outer[u]]);
+            oval.push_back(to_d2(C.zo[u]));
+        }
+        if ((e = scatter(osl, oval)).code) throw e;
+        // every seam vertex must have been written exactly once: tracked + outer
+        if ((int64_t)(C.tslot.size() + C.outer.size()) != ns)
+            throw Error{PGCP_E_WELD, "seam vertex without a welded coordinate"};
+        HIPTHROW(hipMemcpyAsync(welded_uv, zt.p, (size_t)ns * 16, hipMemcpyDeviceToHost, s));
+        HIPTHROW(hipStreamSynchronize(s));
+        P->welded = true;
+        release();
+        return Error{PGCP_OK, ""};
+    } catch (const Error& er) {
+        release();
+        return er;
+    } catch (const std::exception& ex) {
+        release();
+        return Error{PGCP_E_WELD, ex.what()};
+    }
+}
+
+}  // namespace pgcp

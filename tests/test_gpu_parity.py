@@ -198,10 +198,12 @@ def test_call_order_errors(ctx):
     assert ei.value.status == "INVALID"
 
 
-@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8", "256,1,1", "256,4,1", "512,2,1"])
+@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8", "256,1,1", "256,4,1", "512,2,1",
+                                 "256,0,1", "512,0,1"])
 def test_forced_launch_shapes(ctx, cfg, monkeypatch):
     """Every launch shape (register-resident, or streaming when the third field
-    is 1), with pieces spread over several workgroups, gives the oracle's answer."""
+    is 1; streaming with 0 slices per wave is the size-weighted map), with
+    pieces spread over several workgroups, gives the oracle's answer."""
     import paper_1903_12359_amd as pg
     monkeypatch.setenv("PGCP_PCG_CFG", cfg)
     case = case_c2(n=160)
@@ -277,3 +279,40 @@ def test_c3_full_size_stagewise(ctx):
         err = np.abs(phi.cpu().numpy() - phi_o).max()
         say("  harmonic chordal err", err, "iters", rep.total_iters)
         assert err <= bound
+
+
+def _sigma(z):
+    r2 = np.abs(z) ** 2
+    return np.column_stack([2 * z.real, -2 * z.imag, r2 - 1]) / (r2 + 1)[:, None]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_device_weld_matches_oracle_and_host(ctx, name):
+    """The weld with the point replay on the GPU against the oracle's weld and the host-only weld."""
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("device weld", name)
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    wo = oracle_weld([s["loop"] for s in subs], bdy, case.mode, sizes=[len(s["T"]) for s in subs])
+    bh = np.concatenate([np.column_stack([b.real, b.imag]) for b in bdy])
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    wd = pg.weld(ctx, plan, bh)
+    wh = pg.weld(None, pg.Plan(None, case.V, case.F, case.label, case.mode), bh)
+    seam = plan.export()["seam_gv"]
+    zo = np.array([wo[int(g)] for g in seam])
+    zd = wd[:, 0] + 1j * wd[:, 1]
+    zh = wh[:, 0] + 1j * wh[:, 1]
+    io = ~np.isfinite(zo)
+    assert np.array_equal(io, ~np.isfinite(zd)) and np.array_equal(io, ~np.isfinite(zh))
+    if case.mode == "sphere":
+        e_or = np.abs(_sigma(zd[~io]) - _sigma(zo[~io])).max()
+        e_host = np.abs(_sigma(zd[~io]) - _sigma(zh[~io])).max()
+        bound = 1e-9
+    else:
+        sc = np.abs(zo).max()
+        e_or = np.abs(zd - zo).max() / sc
+        e_host = np.abs(zd - zh).max() / sc
+        bound = 1e-10
+    say("  vs oracle", e_or, "vs host", e_host)
+    assert e_or <= bound and e_host <= bound
