@@ -15,14 +15,17 @@
 // Batched persistent PCG.  One cooperative launch covers all pieces.  Each
 // workgroup owns a contiguous range of slices of exactly one piece; the
 // workgroups of a piece meet at per-piece barriers (a monotonically increasing
-// arrival counter), exchange partial dot products through a small global
-// array and sum them in a fixed order, so every workgroup of a piece takes the
-// same alpha, beta and convergence decision and results are bitwise
-// deterministic.  Per iteration there are two barriers:
+// arrival counter).  Each writes its partial dot products to a small global
+// array; the workgroup that arrives last sums them in a fixed order and
+// publishes the sums, so every workgroup of a piece takes the same alpha, beta
+// and convergence decision and results are bitwise deterministic.  Per
+// iteration there are two barriers:
 //   A: beta; p_new = z + beta p_old (own rows, written to the other p buffer);
 //      q = A p_new computed by gathering z and p_old of neighbour rows (so
 //      p_new need not be visible yet); partial p.q
-//   B: alpha; e += alpha p; r -= alpha q; z = D^-1 r; partial r.z and r.r
+//   B: alpha; e += alpha p; r -= alpha q; z = D^-1 r, or z = M r with the
+//      learned SPAI (neighbours' new r rebuilt from their published old r and
+//      q); partial r.z and r.r
 // q and p_new stay in registers between the phases.  Every wait is bounded:
 // a workgroup that spins too long raises a global abort flag and all
 // workgroups leave their loops.
@@ -49,7 +52,7 @@ void free_part_device(pgcp_part* P) {
                      &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
                      &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2,
-                     &P->d_partial, &P->d_bar, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
+                     &P->d_partial, &P->d_bar, &P->d_gen, &P->d_res, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
                      &P->d_flags, &P->wmap32.d_wg_sub, &P->wmap32.d_wg_s0, &P->wmap32.d_wg_s1,
                      &P->wmap32.d_sub_pbase, &P->wmap32.d_sub_nwg, &P->wmap32.d_wg_rank,
                      &P->wmap64.d_wg_sub, &P->wmap64.d_wg_s0, &P->wmap64.d_wg_s1, &P->wmap64.d_wg_rank,
@@ -122,6 +125,8 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_status, K * 4)).code) return e;
     if ((e = dev_alloc(P->d_active, K * 4)).code) return e;
     if ((e = dev_alloc(P->d_bar, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_gen, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_res, K * 8 * 8)).code) return e;
     if ((e = dev_alloc(P->d_abort, 64)).code) return e;
     if ((e = dev_alloc(P->d_flags, 64)).code) return e;
     if ((e = dev_alloc(P->d_chart, K * 3 * 8)).code) return e;
@@ -289,6 +294,11 @@ __global__ void __launch_bounds__(BLOCK) k_apply_inner(int64_t N, const int32_t*
 
 // ----------------------------------------------------------------- persistent batched PCG
 
+// Matrix slots of a row read per batch of loads in the SpMVs (triangle-mesh
+// valences rarely exceed 8; wider rows take several batches).
+constexpr int KB = 8;
+constexpr int KBR = 4;   // register-resident kernel: own columns come from LDS, fewer registers to spare
+
 template <typename T>
 struct CGArgs {
     const int64_t* sl_ptr;
@@ -319,6 +329,8 @@ struct CGArgs {
     const int32_t* pc;             // [K] 1 = the piece uses the SPAI, 0 = Jacobi (null: all Jacobi)
     double* partial;               // [sum nwg][8]
     unsigned* bar;                 // [K]
+    unsigned* gen;                 // [K] reductions published by the last arriving workgroup
+    double* res;                   // [K][8] their values
     int* abort_flag;
     int32_t* iters;                // [K] out
     double* rr_out;                // [K*2] out: final recursive |r|^2 / |r0|^2
@@ -394,40 +406,6 @@ __device__ __forceinline__ void st_c(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Barrier of the workgroups of one piece: every wave waits until its stores
-// (the atomics above included) have completed, then one wave bumps the
-// piece's arrival counter and polls it.  A workgroup that sees the counter
-// reach its target can therefore read everything published before it.
-// Polling is bounded; a workgroup that waits too long raises the abort flag,
-// and every waiting workgroup leaves when it sees the flag.
-__device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned target, int* abort_flag, int* lds_flag) {
-    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        long long spins = 0;
-        int ab = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            ++spins;
-            if ((spins & 255) == 0) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ab = 1;
-                    break;
-                }
-                if (spins > SPIN_MAX) {
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ab = 1;
-                    break;
-                }
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        *lds_flag = ab;
-    }
-    __syncthreads();
-    return *lds_flag != 0;
-}
-
 // Fixed-order sum of the piece's partial records (slots off .. off+NV-1).
 template <int BLK, int NV>
 __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int nwg, int off, double (&out)[NV],
@@ -448,7 +426,7 @@ __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int 
 // this iteration's residual there as rglob - alpha qglob from the previous
 // residual and A p that the owning workgroup published before the barrier, so
 // the SPAI needs no barrier of its own.
-template <typename T, typename V2>
+template <typename T, typename V2, int NB = KB>
 __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, const V2* lds_r, int64_t lo,
                                        int64_t hi, const V2* rglob, const V2* qglob = nullptr, T ax = (T)0,
                                        T ay = (T)0) {
@@ -457,29 +435,98 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
     const int w = a.sl_w[s];
     const T d = a.mdiag[rw];
     T zx = d * rown.x, zy = d * rown.y;
-    for (int k = 0; k < w; ++k) {
-        const int64_t el = base + (int64_t)k * 64;
-        const T m = a.mval[el];
-        if (m == (T)0) continue;
-        const int c = a.sl_col[el];
-        V2 rc;
-        if (c >= lo && c < hi) {
-            rc = lds_r[c - lo];
-        } else {
-            rc = ld_c(rglob + c);
-            if (qglob) {
-                const V2 qc = ld_c(qglob + c);
-                rc.x -= ax * qc.x;
-                rc.y -= ay * qc.y;
+    for (int k0 = 0; k0 < w; k0 += NB) {
+        int cc[NB];
+        T mm[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int64_t el = base + (int64_t)(k0 + t) * 64;
+            const bool in = k0 + t < w;
+            mm[t] = in ? a.mval[el] : (T)0;
+            cc[t] = in ? a.sl_col[el] : (int)rw;
+        }
+        V2 rr[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int c = cc[t];
+            if (mm[t] == (T)0) {
+                rr[t].x = (T)0;
+                rr[t].y = (T)0;
+            } else if (c >= lo && c < hi) {
+                rr[t] = lds_r[c - lo];
+            } else {
+                rr[t] = ld_c(rglob + c);
+                if (qglob) {
+                    const V2 qc = ld_c(qglob + c);
+                    rr[t].x -= ax * qc.x;
+                    rr[t].y -= ay * qc.y;
+                }
             }
         }
-        zx += m * rc.x;
-        zy += m * rc.y;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            zx += mm[t] * rr[t].x;
+            zy += mm[t] * rr[t].y;
+        }
     }
     V2 z;
     z.x = zx;
     z.y = zy;
     return z;
+}
+
+// Barrier of a piece's workgroups fused with the fixed-order sum of their
+// partial records: the workgroup that arrives last (it sees the counter at
+// target - 1, so every other workgroup's stores have completed) sums the
+// records, publishes the sums and bumps the piece's generation; the others wait
+// for the generation and read the sums.  One workgroup reads the nwg records
+// instead of every workgroup reading all of them.  Returns true on abort.
+template <int BLK, int NV>
+__device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsigned nb, int nwg,
+                                             const double* partial, int pbase, int off, double* res,
+                                             double (&out)[NV], int* abort_flag, int* lds_flag, double* lds) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lds_flag[1] = (old == nb * (unsigned)nwg - 1u) ? 1 : 0;
+    }
+    __syncthreads();
+    if (lds_flag[1]) {
+        piece_sum<BLK, NV>(partial, pbase, nwg, off, out, lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) st_c(res + off + i, out[i]);
+            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __hip_atomic_store(gen, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return false;
+    }
+    if (threadIdx.x == 0) {
+        long long spins = 0;
+        int ab = 0;
+        while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) {
+            ++spins;
+            if ((spins & 255) == 0) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ab = 1;
+                    break;
+                }
+                if (spins > SPIN_MAX) {
+                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ab = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        lds_flag[0] = ab;
+    }
+    __syncthreads();
+    if (lds_flag[0]) return true;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = ld_c(res + off + i);
+    return false;
 }
 
 // Register-resident batched PCG.  Thread t of a workgroup owns the rows
@@ -496,7 +543,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     V2* lds_p = reinterpret_cast<V2*>(smem_raw);
     __shared__ double lds[NW * 8 + 16];
-    __shared__ int lds_flag;
+    __shared__ int lds_flag[2];
     const int wg = blockIdx.x;
     const int sub = a.wg_sub[wg];
     if (sub < 0 || !a.active[sub]) return;
@@ -570,7 +617,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            if (valid[j] && !msk[j]) z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, a.r);
+            if (valid[j] && !msk[j]) z[j] = spai_row<T, V2, KBR>(a, rows[j], r[j], lds_p, lo, hi, a.r);
         __syncthreads();
     }
 #pragma unroll
@@ -590,12 +637,12 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
     }
     nbar++;
-    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+    double st[4];
+    if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
+                             a.abort_flag, lds_flag, lds)) {
         if (leader) a.status[sub] = 3;
         return;
     }
-    double st[4];
-    piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
     double rz[2] = {st[0], st[1]};
     double rr0[2] = {st[2], st[3]};
     if (a.coupled) {
@@ -645,20 +692,33 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             const int64_t base = a.sl_ptr[s] + lane;
             const int w = a.sl_w[s];
             T qx = dg[j] * pn[j].x, qy = dg[j] * pn[j].y;
-            for (int k = 0; k < w; ++k) {
-                const int64_t el = base + (int64_t)k * 64;
-                const T v = a.val[el];
-                const int c = a.sl_col[el];
-                V2 pc;
-                if (c >= lo && c < hi) {
-                    pc = lds_p[c - lo];
-                } else {
-                    V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
-                    pc.x = zc.x + bx * oc.x;
-                    pc.y = zc.y + by * oc.y;
+            for (int k0 = 0; k0 < w; k0 += KBR) {
+                int cc[KBR];
+                T vv[KBR];
+#pragma unroll
+                for (int t = 0; t < KBR; ++t) {
+                    const int64_t el = base + (int64_t)(k0 + t) * 64;
+                    const bool in = k0 + t < w;
+                    cc[t] = in ? a.sl_col[el] : (int)rw;
+                    vv[t] = in ? a.val[el] : (T)0;
                 }
-                qx += v * pc.x;
-                qy += v * pc.y;
+                V2 pc[KBR];
+#pragma unroll
+                for (int t = 0; t < KBR; ++t) {
+                    const int c = cc[t];
+                    if (c >= lo && c < hi) {
+                        pc[t] = lds_p[c - lo];
+                    } else {
+                        const V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
+                        pc[t].x = zc.x + bx * oc.x;
+                        pc[t].y = zc.y + by * oc.y;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < KBR; ++t) {
+                    qx += vv[t] * pc[t].x;
+                    qy += vv[t] * pc[t].y;
+                }
             }
             if (a.coupled) {
                 const int pv = a.rprev[rw];
@@ -695,12 +755,12 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             st_c(mypart + 1, pq[1]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        double pqs[2];
+        if (piece_reduce<BLK, 2>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, pqs,
+                                 a.abort_flag, lds_flag, lds)) {
             stat = 3;
             break;
         }
-        double pqs[2];
-        piece_sum<BLK, 2>(a.partial, pbase, nwg, 0, pqs, lds);
         double alpha[2] = {0.0, 0.0};
         if (a.coupled) {
             double den = pqs[0] + pqs[1];
@@ -752,7 +812,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (!valid[j] || msk[j]) continue;
-                z[j] = spai_row<T, V2>(a, rows[j], r[j], lds_p, lo, hi, rcur, a.q, ax, ay);
+                z[j] = spai_row<T, V2, KBR>(a, rows[j], r[j], lds_p, lo, hi, rcur, a.q, ax, ay);
                 if (expo[j]) st_c(a.z + rows[j], z[j]);
                 acc2[0] += (double)r[j].x * (double)z[j].x;
                 acc2[1] += (double)r[j].y * (double)z[j].y;
@@ -765,11 +825,11 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
+                                 a.abort_flag, lds_flag, lds)) {
             stat = 3;
             break;
         }
-        piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
         double rzn[2] = {st[0], st[1]};
         double rrn[2] = {st[2], st[3]};
         if (a.coupled) {
@@ -825,7 +885,7 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
     using V2 = typename Vec2<T>::type;
     constexpr int NW = BLK / 64;
     __shared__ double lds[NW * 8 + 16];
-    __shared__ int lds_flag;
+    __shared__ int lds_flag[2];
     const int wg = blockIdx.x;
     const int sub = a.wg_sub[wg];
     if (sub < 0 || !a.active[sub]) return;
@@ -870,12 +930,12 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
     }
     nbar++;
-    if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+    double st[4];
+    if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
+                             a.abort_flag, lds_flag, lds)) {
         if (leader) a.status[sub] = 3;
         return;
     }
-    double st[4];
-    piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
     double rz[2] = {st[0], st[1]};
     double rr0[2] = {st[2], st[3]};
     if (a.coupled) {
@@ -917,13 +977,30 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
                 const int w = a.sl_w[s];
                 const T d = a.diag[rw];
                 T qx = d * p.x, qy = d * p.y;
-                for (int k = 0; k < w; ++k) {
-                    const int64_t el = base + (int64_t)k * 64;
-                    const T v = a.val[el];
-                    const int c = a.sl_col[el];
-                    V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
-                    qx += v * (cx * zc.x + bx * oc.x);
-                    qy += v * (cy * zc.y + by * oc.y);
+                // KB slots per batch: all column and value loads, then all
+                // gathers, then one wait (slots past the width read the own
+                // row with value 0)
+                for (int k0 = 0; k0 < w; k0 += KB) {
+                    int cc[KB];
+                    T vv[KB];
+#pragma unroll
+                    for (int t = 0; t < KB; ++t) {
+                        const int64_t el = base + (int64_t)(k0 + t) * 64;
+                        const bool in = k0 + t < w;
+                        cc[t] = in ? a.sl_col[el] : (int)rw;
+                        vv[t] = in ? a.val[el] : (T)0;
+                    }
+                    V2 zz[KB], oo[KB];
+#pragma unroll
+                    for (int t = 0; t < KB; ++t) {
+                        zz[t] = ld_c(a.z + cc[t]);
+                        oo[t] = ld_c(pold + cc[t]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < KB; ++t) {
+                        qx += vv[t] * (cx * zz[t].x + bx * oo[t].x);
+                        qy += vv[t] * (cy * zz[t].y + by * oo[t].y);
+                    }
                 }
                 if (a.coupled) {
                     const int pv = a.rprev[rw];
@@ -953,12 +1030,12 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             st_c(mypart + 1, pq[1]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        double pqs[2];
+        if (piece_reduce<BLK, 2>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, pqs,
+                                 a.abort_flag, lds_flag, lds)) {
             stat = 3;
             break;
         }
-        double pqs[2];
-        piece_sum<BLK, 2>(a.partial, pbase, nwg, 0, pqs, lds);
         double alpha[2] = {0.0, 0.0};
         if (a.coupled) {
             double den = pqs[0] + pqs[1];
@@ -1018,11 +1095,11 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
         }
         nbar++;
-        if (piece_barrier(bar, nbar * nwg, a.abort_flag, &lds_flag)) {
+        if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
+                                 a.abort_flag, lds_flag, lds)) {
             stat = 3;
             break;
         }
-        piece_sum<BLK, 4>(a.partial, pbase, nwg, 2, st, lds);
         double rzn[2] = {st[0], st[1]};
         double rrn[2] = {st[2], st[3]};
         if (a.coupled) {
@@ -1644,6 +1721,8 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.pc = nullptr;
     a.partial = (double*)P->d_partial.p;
     a.bar = (unsigned*)P->d_bar.p;
+    a.gen = (unsigned*)P->d_gen.p;
+    a.res = (double*)P->d_res.p;
     a.abort_flag = (int*)P->d_abort.p;
     a.iters = (int32_t*)P->d_iters.p;
     a.rr_out = (double*)P->d_rrout.p;
@@ -1668,6 +1747,7 @@ static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
                                                                (double2*)P->d_e.p);
     }
     k_zero_u32<<<grid_for(P->K), BLOCK, 0, s>>>(P->K, (unsigned*)P->d_bar.p);
+    k_zero_u32<<<grid_for(P->K), BLOCK, 0, s>>>(P->K, (unsigned*)P->d_gen.p);
     k_zero_u32<<<1, 64, 0, s>>>(16, (unsigned*)P->d_abort.p);
     HIPCHK(hipGetLastError());
     return Error{PGCP_OK, ""};

@@ -95,7 +95,7 @@ struct pgcp_part {
 
     // ---------------- solver work space
     pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q, d_r2;
-    pgcp::DevBuf d_partial, d_bar, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
+    pgcp::DevBuf d_partial, d_bar, d_gen, d_res, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
     pgcp::WorkMap wmap32, wmap64;
