@@ -38,6 +38,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# Per-launch HBM traffic of k_pcg (FETCH_SIZE x2.0 + WRITE_SIZE x1.0 from
+# rocprofv3 counter passes over one timed step, scale factors from a 256 MiB
+# copy), for the kernel source and launch shapes it was measured with; the
+# summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
+TRAFFIC = {}
+
+
+def kernel_source_sha():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_1903_12359_amd", "csrc", "device.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def make_case(name):
     from synth import case_c1, case_c2, case_c3, case_c5
@@ -205,10 +217,21 @@ def main():
                     "dncp_max_relres": float(info["dncp"].relres.max()),
                     "harmonic_max_relres": float(info["harmonic"].relres.max())},
     }
+    def shape(rep):
+        return f"{rep.cg_block},{rep.rows_per_thread},{rep.cg_stream}"
+
     for name, r in res.items():
         rec[name] = {"value": round(r["value"], 4), "ms_per_step": round(r["ms_per_step"], 3),
                      "cg_iterations_per_step": r["iters"], "cg_ms_per_step": round(r["cg_ms"] / args.steps, 3),
-                     "stages_ms": r["stage"], "n_fallback": r["fallback"]}
+                     "stages_ms": r["stage"], "n_fallback": r["fallback"],
+                     "pcg_shapes": {"dncp": shape(r["info"]["dncp"]), "harmonic": shape(r["info"]["harmonic"])}}
+    # HBM traffic of the k_pcg launches, from the counter runs recorded in
+    # profiles/ (see TRAFFIC): reported only for the same kernel source, workload,
+    # preconditioner and launch shapes
+    tr = TRAFFIC.get(args.workload)
+    if tr is not None and tr["variant"] == headname and tr["source_sha256"] == kernel_source_sha() and \
+            tr["pcg_shapes"] == rec[headname]["pcg_shapes"] and args.precision == tr["precision"]:
+        rec["roofline"]["traffic"] = tr["bytes_per_launch"]
     if "learned" in res and "jacobi" in res:
         rec["learned_vs_jacobi"] = {
             "speedup_end_to_end": round(res["jacobi"]["ms_per_step"] / res["learned"]["ms_per_step"], 4),
