@@ -42,7 +42,12 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter passes over one timed step, scale factors from a 256 MiB
 # copy), for the kernel source and launch shapes it was measured with; the
 # summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
-TRAFFIC = {}
+TRAFFIC = {
+    "c2": {"variant": "learned", "precision": "fp32",
+           "source_sha256": "a8ff198a83b88bc458dc4c4d4dfc71c71065d02e35054c06cf41c438fe402fa4",
+           "pcg_shapes": {"dncp": "512,4,0", "harmonic": "256,4,0"},
+           "bytes_per_launch": 6.432e9},
+}
 
 
 def kernel_source_sha():
