@@ -1,7 +1,7 @@
 """PGCP hot-path benchmark on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--workload c2|c1|c3|c5]
-                    [--precond both|jacobi|learned] [--lpc-steps S]
+                    [--precond both|jacobi|learned] [--lpc-steps S] [--no-pipeline]
 
 One step is Algorithm 3 end to end on one synthetic mesh already resident in
 device memory (V, F; labels and the host copy of the connectivity for the
@@ -10,6 +10,12 @@ partition): partition + plan upload, cotangent assembly, DNCP of every piece
 (batched PCG), gather, and the distortion / Beltrami / flip check.  Every solve
 reaches an FP64 relative residual of 1e-10 (per piece; per coordinate for the
 harmonic solve).  Prints one JSON line.
+
+The steps run as a stream (pg.run_stream): while the device works on one step,
+a host thread partitions the mesh of the next one, as a service that processes
+a stream of meshes would.  Every step still runs every stage; `value` is the
+throughput of the stream, and "sequential" reports a few steps run one after
+the other (the latency of a single mesh).  --no-pipeline times the latter only.
 
 The step is timed twice on the same GPU: with Jacobi-PCG, and with the learned
 SPAI preconditioner (network inference inside the step).  The network is
@@ -106,15 +112,27 @@ def train_lpc(ctx, steps, seed=0):
     return lpc, info
 
 
-def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc):
-    def step():
-        times = {}
-        return pg.run(ctx, case.V, case.F, case.label, case.mode, precision=args.precision, tol=args.tol,
-                      V_dev=V_dev, F_dev=F_dev, times=times, lpc=lpc)
-
+def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, steps=None, pipeline=True):
+    """Time `steps` complete steps on the same mesh.  With pipeline=True the steps
+    run through pg.run_stream, which partitions the next mesh on the host while
+    the device works on the current one (every step still runs every stage);
+    otherwise one step after the other."""
     import torch
-    for w in range(args.warmup):
-        step()
+    steps = args.steps if steps is None else steps
+    kw = dict(precision=args.precision, tol=args.tol, lpc=lpc)
+    item = dict(V=case.V, F=case.F, label=case.label, mode=case.mode, V_dev=V_dev, F_dev=F_dev)
+
+    def steps_iter(n):
+        if pipeline:
+            yield from pg.run_stream(ctx, [item] * n, **kw)
+        else:
+            for _ in range(n):
+                times = {}
+                yield pg.run(ctx, case.V, case.F, case.label, case.mode, V_dev=V_dev, F_dev=F_dev, times=times,
+                             **kw)
+
+    for _ in steps_iter(args.warmup):
+        pass
     torch.cuda.synchronize()
     stage = {}
     cg_ms = cg_bytes = 0.0
@@ -123,8 +141,7 @@ def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc):
     fallback = 0
     last = None
     t_start = time.perf_counter()
-    for k in range(args.steps):
-        phi, st, info = step()
+    for phi, st, info in steps_iter(steps):
         for key, v in info["times"].items():
             stage[key] = stage.get(key, 0.0) + v
         for rep in (info["dncp"], info["harmonic"]):
@@ -136,11 +153,11 @@ def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc):
         last = (st, info)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    ms_per_step = 1e3 * elapsed / args.steps
+    ms_per_step = 1e3 * elapsed / steps
     st, info = last
     return dict(ms_per_step=ms_per_step, value=case.nv / (ms_per_step / 1e3) / 1e6, cg_ms=cg_ms,
-                cg_bytes=cg_bytes, cg_launch=cg_launch, iters=iters // args.steps, fallback=fallback,
-                stage={k: round(1e3 * v / args.steps, 3) for k, v in stage.items()}, st=st, info=info)
+                cg_bytes=cg_bytes, cg_launch=cg_launch, iters=iters // steps, fallback=fallback,
+                stage={k: round(1e3 * v / steps, 3) for k, v in stage.items()}, st=st, info=info)
 
 
 def main():
@@ -154,6 +171,8 @@ def main():
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
     ap.add_argument("--lpc-steps", type=int, default=400, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="run the steps one after the other (no host partition of the next step during device work)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device copy first (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
@@ -185,13 +204,18 @@ def main():
     res = {}
     lpc_info = None
     if args.precond in ("jacobi", "both"):
-        res["jacobi"] = time_variant(pg, ctx, case, V_dev, F_dev, args, None)
+        res["jacobi"] = time_variant(pg, ctx, case, V_dev, F_dev, args, None, pipeline=not args.no_pipeline)
         print(f"[bench] jacobi: {res['jacobi']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     if args.precond in ("learned", "both"):
         lpc, lpc_info = train_lpc(ctx, args.lpc_steps)
         print(f"[bench] learned preconditioner trained: {lpc_info}", file=sys.stderr, flush=True)
-        res["learned"] = time_variant(pg, ctx, case, V_dev, F_dev, args, lpc)
+        res["learned"] = time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, pipeline=not args.no_pipeline)
         print(f"[bench] learned: {res['learned']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
+    # one step after the other (latency of a single mesh), a few steps of the headline variant
+    seq = None
+    if not args.no_pipeline:
+        seq = time_variant(pg, ctx, case, V_dev, F_dev, args, lpc if "learned" in res else None,
+                           steps=min(args.steps, 4), pipeline=False)
     head = res["learned"] if "learned" in res else res["jacobi"]
     headname = "learned" if "learned" in res else "jacobi"
     achieved = head["cg_bytes"] / (head["cg_ms"] / 1e3) / 1e9 if head["cg_ms"] > 0 else 0.0
@@ -218,6 +242,7 @@ def main():
                      "avg_launch_ms": round(head["cg_ms"] / max(head["cg_launch"], 1), 4),
                      "cg_iterations_per_step": head["iters"]},
         "stages_ms": head["stage"],
+        "pipelined": not args.no_pipeline,
         "quality": {"mean_abs_d_deg": st["mean_abs_d"], "max_mu": st["max_mu"], "n_flipped": st["n_flipped"],
                     "dncp_max_relres": float(info["dncp"].relres.max()),
                     "harmonic_max_relres": float(info["harmonic"].relres.max())},
@@ -242,6 +267,9 @@ def main():
             "speedup_end_to_end": round(res["jacobi"]["ms_per_step"] / res["learned"]["ms_per_step"], 4),
             "iteration_ratio": round(res["jacobi"]["iters"] / max(res["learned"]["iters"], 1), 4),
             "cg_time_ratio": round(res["jacobi"]["cg_ms"] / max(res["learned"]["cg_ms"], 1e-9), 4)}
+    if seq is not None:
+        rec["sequential"] = {"ms_per_step": round(seq["ms_per_step"], 3), "value": round(seq["value"], 4),
+                             "steps": min(args.steps, 4), "stages_ms": seq["stage"]}
     if lpc_info is not None:
         rec["lpc_training"] = lpc_info
     if not args.no_cpu_baseline:

@@ -410,6 +410,48 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
     return out, d, mu, flip
 
 
+def run_stream(ctx: Context, cases, **kw):
+    """Algorithm 3 over a sequence of meshes, overlapping host and device work.
+
+    `cases` is an iterable of dicts with keys V, F, label and optionally mode,
+    V_dev, F_dev.  While the device runs the stages of one mesh, a worker
+    thread partitions the next one on the host (pgcp_partition releases the
+    interpreter lock; its plan upload is ordered on the context's stream), so
+    the host partition is hidden behind device work.  Every mesh still goes
+    through every stage.  Yields run()'s (phi_dev, dist_stats, reports) per
+    mesh; reports["times"]["partition"] is the time spent waiting for the
+    prefetched plan and ["partition_overlapped"] the worker's partition time.
+    Remaining keyword arguments go to run().
+    """
+    from concurrent.futures import ThreadPoolExecutor
+
+    def build(c):
+        t = time.perf_counter()
+        p = Plan(ctx, c["V"], c["F"], c["label"], c.get("mode", "free"))
+        return p, time.perf_counter() - t
+
+    it = iter(cases)
+    with ThreadPoolExecutor(max_workers=1) as ex:
+        nxt = next(it, None)
+        fut = ex.submit(build, nxt) if nxt is not None else None
+        while fut is not None:
+            cur = nxt
+            t = time.perf_counter()
+            plan, t_build = fut.result()
+            wait = time.perf_counter() - t
+            nxt = next(it, None)
+            fut = ex.submit(build, nxt) if nxt is not None else None
+            times = {}
+            try:
+                out = run(ctx, cur["V"], cur["F"], cur["label"], cur.get("mode", "free"), V_dev=cur.get("V_dev"),
+                          F_dev=cur.get("F_dev"), plan=plan, times=times, **kw)
+            finally:
+                plan.close()
+            times["partition"] = wait
+            times["partition_overlapped"] = t_build
+            yield out
+
+
 def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,
         V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64", lpc=None):
     """Algorithm 3 end to end; returns (phi_dev, dist_stats, reports).

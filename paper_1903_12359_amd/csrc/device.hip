@@ -1906,6 +1906,10 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             if (ab) return Error{PGCP_E_HIP, "batched CG barrier timed out while tuning"};
             ms = std::min(ms, m1);
         }
+        const char* vb = getenv("PGCP_VERBOSE");
+        if (vb && vb[0] == '1')
+            fprintf(stderr, "[pgcp] tune prec=%d coupled=%d shape %d,%d,%d: %d workgroups, %.3f ms / %d iterations\n",
+                    prec, coupled, c.blk, c.R, c.stream, T.n_wg, ms, probe_iters);
         if (ms < best_ms) {
             best_ms = ms;
             best = c;

@@ -316,3 +316,23 @@ def test_device_weld_matches_oracle_and_host(ctx, name):
         bound = 1e-10
     say("  vs oracle", e_or, "vs host", e_host)
     assert e_or <= bound and e_host <= bound
+
+
+@pytest.mark.parametrize("name", ["g33_3x3_jit", "S3_k6"])
+def test_run_stream_matches_run(ctx, name):
+    """The pipelined driver (host partition of the next mesh overlapped with the
+    device stages of the current one) gives what one run per mesh gives."""
+    import torch
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    say("run_stream", name)
+    phi0, st0, _ = pg.run(ctx, case.V, case.F, case.label, case.mode)
+    item = dict(V=case.V, F=case.F, label=case.label, mode=case.mode)
+    outs = list(pg.run_stream(ctx, [item] * 3))
+    assert len(outs) == 3
+    ref = phi0.cpu().numpy()
+    for phi, st, info in outs:
+        got = phi.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert st["n_flipped"] == st0["n_flipped"]
+        assert info["times"]["partition_overlapped"] > 0.0
