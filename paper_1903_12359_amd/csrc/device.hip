@@ -46,6 +46,12 @@
 
 namespace pgcp {
 
+static void free_workmap(WorkMap& W) {
+    for (DevBuf* b : {&W.d_wg_sub, &W.d_wg_rank, &W.d_wg_s0, &W.d_wg_s1, &W.d_sub_pbase, &W.d_sub_nwg, &W.d_wg_h0,
+                      &W.d_halo, &W.d_lcol, &W.d_lpn})
+        dev_free(*b);
+}
+
 void free_part_device(pgcp_part* P) {
     DevBuf* all[] = {&P->d_row_gv, &P->d_row_prev, &P->d_row_next, &P->d_row_kind, &P->d_slice_sub,
                      &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_sl_rev, &P->d_val64, &P->d_val32,
@@ -53,14 +59,12 @@ void free_part_device(pgcp_part* P) {
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
                      &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2,
                      &P->d_partial, &P->d_bar, &P->d_gen, &P->d_res, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
-                     &P->d_flags, &P->wmap32.d_wg_sub, &P->wmap32.d_wg_s0, &P->wmap32.d_wg_s1,
-                     &P->wmap32.d_sub_pbase, &P->wmap32.d_sub_nwg, &P->wmap32.d_wg_rank,
-                     &P->wmap64.d_wg_sub, &P->wmap64.d_wg_s0, &P->wmap64.d_wg_s1, &P->wmap64.d_wg_rank,
-                     &P->wmap64.d_sub_pbase, &P->wmap64.d_sub_nwg, 
-                     &P->d_row0, &P->d_slicepart,
+                     &P->d_flags, &P->d_row0, &P->d_slicepart,
                      &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
                      &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp};
     for (DevBuf* b : all) dev_free(*b);
+    free_workmap(P->wmap32);
+    free_workmap(P->wmap64);
     if (P->ev0) (void)hipEventDestroy(P->ev0);
     if (P->ev1) (void)hipEventDestroy(P->ev1);
     P->ev0 = P->ev1 = nullptr;
@@ -315,6 +319,11 @@ struct CGArgs {
     const int32_t* wg_s1;          // [G] end slice
     const int32_t* sub_pbase;      // [K] first partial record of the piece
     const int32_t* sub_nwg;        // [K] workgroups of the piece
+    const int32_t* wg_h0;          // [G+1] register kernel: first halo entry of each workgroup
+    const int32_t* halo;           // [*] register kernel: packed rows of the halo entries
+    const int32_t* lcol;           // [sell] register kernel: local column of every SELL slot
+    const int32_t* lpn;            // [2N] register kernel: local loop neighbours (prev, next) or -1
+    int lds_n;                     // register kernel: LDS entries of one vector (own rows + largest halo)
     const int32_t* active;         // [K]
     const double* target_rel2;     // [K*2] squared relative tolerance per piece and coordinate
     typename Vec2<T>::type* e;
@@ -529,19 +538,48 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
     return false;
 }
 
-// Register-resident batched PCG.  Thread t of a workgroup owns the rows
-// (s0 + wave + NW j) * 64 + lane, j < R, for the whole solve: e, r, z, p of its
-// rows live in registers.  Each iteration the workgroup stages p_new of its
-// own rows in LDS for the SpMV; columns owned by other workgroups of the piece
-// ("halo") are rebuilt as z + beta p_old from the values those workgroups
-// published through the coherent path.  Only rows with a neighbour in another
-// workgroup publish z and p.
+// Register-resident batched PCG with LDS-staged vectors.  Thread t of a
+// workgroup owns the rows (s0 + wave + NW j) * 64 + lane, j < R, for the whole
+// solve: r and z of its rows live in registers, e and p_old in LDS.  The
+// workgroup numbers its rows locally (own rows 0 .. nown-1, then the distinct
+// columns of other workgroups that its rows reference, the "halo"), and every
+// SELL slot carries its local column (lcol), so both sparse products read all
+// their operands from LDS.  Each product is preceded by one cooperative fill
+// of the halo (every thread loads its entries at once): p_new = z + beta p_old
+// (SpMV) or this iteration's residual r_old - alpha q (SPAI), rebuilt from
+// values the owning workgroups published before the last barrier.  Only rows
+// with a neighbour in another workgroup publish.
+
+// y_j = d_j x_j + sum_k v_jk x[lcol_jk] for the thread's R rows, operands in LDS.
+template <typename TV, typename T, typename V2, int R>
+__device__ __forceinline__ void lds_spmv(const int32_t* __restrict__ lcol, const TV* __restrict__ val,
+                                         const TV* __restrict__ diag, const int32_t (&rv)[R],
+                                         const int32_t (&base)[R], const int (&w)[R], const V2 (&x)[R],
+                                         const V2* lv, V2 (&y)[R]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const T d = (T)diag[rv[j]];
+        T yx = d * x[j].x, yy = d * x[j].y;
+        for (int t = 0; t < w[j]; ++t) {
+            const int32_t el = base[j] + t * 64;
+            const V2 c = lv[lcol[el]];
+            const T v = (T)val[el];
+            yx += v * c.x;
+            yy += v * c.y;
+        }
+        y[j].x = yx;
+        y[j].y = yy;
+    }
+}
+
 template <typename T, int BLK, int R>
 __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     using V2 = typename Vec2<T>::type;
     constexpr int NW = BLK / 64;
     extern __shared__ unsigned char smem_raw[];
-    V2* lds_p = reinterpret_cast<V2*>(smem_raw);
+    V2* lv = reinterpret_cast<V2*>(smem_raw);   // [lds_n] p: own rows, then the halo
+    V2* lrs = lv + a.lds_n;                     // [lds_n] SPAI operand r: own rows, then the halo
+    V2* le = lv + 2 * (int64_t)a.lds_n;         // [BLK R] e of the own rows
     __shared__ double lds[NW * 8 + 16];
     __shared__ int lds_flag[2];
     const int wg = blockIdx.x;
@@ -553,71 +591,85 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     const bool leader = rank == 0 && threadIdx.x == 0;
     const bool spai = a.pc != nullptr && a.pc[sub] != 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t lo = (int64_t)s0 * 64, hi = (int64_t)s1 * 64;
+    const int64_t lo = (int64_t)s0 * 64;
+    const int nown = (s1 - s0) * 64;
+    const int hb = a.wg_h0[wg], nh = a.wg_h0[wg + 1] - hb;
+    V2* lh = lv + nown;
+    V2* lrh = lrs + nown;
     unsigned* bar = a.bar + sub;
     unsigned nbar = 0;
     double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
 
-    int64_t rows[R];
+    int32_t rows[R], rv[R], base[R];   // row, a row safe to load (rows past the range: slice s0), slots
+    int w[R], lp[R], ln[R];
     bool valid[R], msk[R], expo[R];
-    V2 e[R], r[R], z[R], po[R];
-    T dg[R], dinv[R];
+    V2 r[R], z[R];   // e and p_old of the own rows live in LDS
+    T dinv[R];
     V2 zero;
     zero.x = (T)0;
     zero.y = (T)0;
+    // the thread's first two halo entries stay in registers (row lo when absent)
+    const bool h0ok = threadIdx.x < nh, h1ok = threadIdx.x + BLK < nh;
+    const int hc0 = h0ok ? a.halo[hb + threadIdx.x] : (int)lo;
+    const int hc1 = h1ok ? a.halo[hb + threadIdx.x + BLK] : (int)lo;
 
-    // ---- start: registers, export flags, z = D^-1 r, p_old = 0
+    // ---- start: registers, export flags, z = D^-1 r or M r, p_old = 0
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int s = s0 + wave + NW * j;
         valid[j] = s < s1;
-        rows[j] = (int64_t)s * 64 + lane;
-        e[j] = zero;
-        po[j] = zero;
+        const int sv = valid[j] ? s : s0;   // rows past the range read a valid slice, results discarded
+        rows[j] = s * 64 + lane;
+        rv[j] = sv * 64 + lane;
+        base[j] = (int32_t)a.sl_ptr[sv] + lane;
+        w[j] = a.sl_w[sv];
         r[j] = zero;
         z[j] = zero;
-        dg[j] = (T)0;
         dinv[j] = (T)0;
         msk[j] = true;
         expo[j] = false;
+        lp[j] = -1;
+        ln[j] = -1;
         if (!valid[j]) continue;
-        const int64_t rw = rows[j];
+        const int32_t rw = rows[j];
+        lv[rw - lo] = zero;
+        le[rw - lo] = zero;
         msk[j] = a.mask[rw] != 0;
-        dg[j] = a.diag[rw];
         if (!msk[j]) {
-            dinv[j] = (T)1 / dg[j];
+            dinv[j] = (T)1 / a.diag[rw];
             r[j] = a.r[rw];
             if (!spai) {
                 z[j].x = dinv[j] * r[j].x;
                 z[j].y = dinv[j] * r[j].y;
             }
         }
-        const int64_t base = a.sl_ptr[s] + lane;
-        const int w = a.sl_w[s];
         bool ex = false;
-        for (int k = 0; k < w; ++k) {
-            const int c = a.sl_col[base + (int64_t)k * 64];
-            ex |= (c < lo || c >= hi);
-        }
+        for (int k = 0; k < w[j]; ++k) ex |= a.lcol[base[j] + (int64_t)k * 64] >= nown;
         if (a.coupled) {
-            const int pv = a.rprev[rw];
-            if (pv >= 0) {
-                const int nx = a.rnext[rw];
-                ex |= (pv < lo || pv >= hi || nx < lo || nx >= hi);
-            }
+            lp[j] = a.lpn[2 * rw];
+            ln[j] = a.lpn[2 * rw + 1];
+            ex |= lp[j] >= nown || ln[j] >= nown;
         }
         expo[j] = ex;
     }
     if (spai) {
-        // z = M r: own rows' r through LDS, the rest from the input residual
+        // z = M r on the input residual (written by the previous kernel)
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            if (valid[j]) lds_p[rows[j] - lo] = r[j];
+            if (valid[j]) lrs[rows[j] - lo] = r[j];
+        {
+            const V2 v0 = a.r[hc0], v1 = a.r[hc1];
+            if (h0ok) lrh[threadIdx.x] = v0;
+            if (h1ok) lrh[threadIdx.x + BLK] = v1;
+            for (int h = threadIdx.x + 2 * BLK; h < nh; h += BLK) lrh[h] = a.r[a.halo[hb + h]];
+        }
         __syncthreads();
+        V2 mz[R];
+        lds_spmv<float, T, V2, R>(a.lcol, a.mval, a.mdiag, rv, base, w, r, lrs, mz);
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            if (valid[j] && !msk[j]) z[j] = spai_row<T, V2, KBR>(a, rows[j], r[j], lds_p, lo, hi, a.r);
+            if (valid[j] && !msk[j]) z[j] = mz[j];
         __syncthreads();
     }
 #pragma unroll
@@ -667,87 +719,61 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             stat = 2;
             break;
         }
-        // ---- phase A: p_new = z + beta p_old (registers, LDS, halo publish); q = A p_new; p.q
+        // ---- phase A: p_new = z + beta p_old (registers, LDS, publish); halo
+        // p_new rebuilt from the published z and p_old; q = A p_new; p.q
         const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
         V2 pn[R], q[R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
+            const V2 po = valid[j] ? lv[rows[j] - lo] : zero;
             V2 p;
-            p.x = done[0] ? (T)0 : z[j].x + bx * po[j].x;
-            p.y = done[1] ? (T)0 : z[j].y + by * po[j].y;
+            p.x = done[0] ? (T)0 : z[j].x + bx * po.x;
+            p.y = done[1] ? (T)0 : z[j].y + by * po.y;
             pn[j] = p;
             if (valid[j]) {
-                lds_p[rows[j] - lo] = p;
+                lv[rows[j] - lo] = p;
                 if (expo[j]) st_c(pnew + rows[j], p);
             }
         }
+        {
+            const V2 z0 = ld_c(a.z + hc0), o0 = ld_c(pold + hc0);
+            const V2 z1 = ld_c(a.z + hc1), o1 = ld_c(pold + hc1);
+            V2 v0, v1;
+            v0.x = done[0] ? (T)0 : z0.x + bx * o0.x;
+            v0.y = done[1] ? (T)0 : z0.y + by * o0.y;
+            v1.x = done[0] ? (T)0 : z1.x + bx * o1.x;
+            v1.y = done[1] ? (T)0 : z1.y + by * o1.y;
+            if (h0ok) lh[threadIdx.x] = v0;
+            if (h1ok) lh[threadIdx.x + BLK] = v1;
+            for (int h = threadIdx.x + 2 * BLK; h < nh; h += BLK) {
+                const int c = a.halo[hb + h];
+                const V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
+                V2 v;
+                v.x = done[0] ? (T)0 : zc.x + bx * oc.x;
+                v.y = done[1] ? (T)0 : zc.y + by * oc.y;
+                lh[h] = v;
+            }
+        }
         __syncthreads();
+        lds_spmv<T, T, V2, R>(a.lcol, a.val, a.diag, rv, base, w, pn, lv, q);
         double pq[2] = {0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            q[j] = zero;
-            if (!valid[j] || msk[j]) continue;
-            const int64_t rw = rows[j];
-            const int64_t s = rw >> 6;
-            const int64_t base = a.sl_ptr[s] + lane;
-            const int w = a.sl_w[s];
-            T qx = dg[j] * pn[j].x, qy = dg[j] * pn[j].y;
-            for (int k0 = 0; k0 < w; k0 += KBR) {
-                int cc[KBR];
-                T vv[KBR];
-#pragma unroll
-                for (int t = 0; t < KBR; ++t) {
-                    const int64_t el = base + (int64_t)(k0 + t) * 64;
-                    const bool in = k0 + t < w;
-                    cc[t] = in ? a.sl_col[el] : (int)rw;
-                    vv[t] = in ? a.val[el] : (T)0;
-                }
-                V2 pc[KBR];
-#pragma unroll
-                for (int t = 0; t < KBR; ++t) {
-                    const int c = cc[t];
-                    if (c >= lo && c < hi) {
-                        pc[t] = lds_p[c - lo];
-                    } else {
-                        const V2 zc = ld_c(a.z + c), oc = ld_c(pold + c);
-                        pc[t].x = zc.x + bx * oc.x;
-                        pc[t].y = zc.y + by * oc.y;
-                    }
-                }
-#pragma unroll
-                for (int t = 0; t < KBR; ++t) {
-                    qx += vv[t] * pc[t].x;
-                    qy += vv[t] * pc[t].y;
-                }
+            if (!valid[j] || msk[j]) {
+                // a Dirichlet row's A p is zero; neighbours rebuild its residual from it
+                q[j] = zero;
+                if (spai && valid[j] && expo[j]) st_c(a.q + rows[j], zero);
+                continue;
             }
-            if (a.coupled) {
-                const int pv = a.rprev[rw];
-                if (pv >= 0) {
-                    const int nx = a.rnext[rw];
-                    V2 pN, pP;
-                    if (nx >= lo && nx < hi) {
-                        pN = lds_p[nx - lo];
-                    } else {
-                        V2 zc = ld_c(a.z + nx), oc = ld_c(pold + nx);
-                        pN.x = zc.x + bx * oc.x;
-                        pN.y = zc.y + by * oc.y;
-                    }
-                    if (pv >= lo && pv < hi) {
-                        pP = lds_p[pv - lo];
-                    } else {
-                        V2 zc = ld_c(a.z + pv), oc = ld_c(pold + pv);
-                        pP.x = zc.x + bx * oc.x;
-                        pP.y = zc.y + by * oc.y;
-                    }
-                    qx -= (T)0.5 * (pN.y - pP.y);
-                    qy += (T)0.5 * (pN.x - pP.x);
-                }
+            if (a.coupled && lp[j] >= 0) {
+                // (L + L - M/2): the boundary term couples x and y along the loop
+                const V2 pN = lv[ln[j]], pP = lv[lp[j]];
+                q[j].x -= (T)0.5 * (pN.y - pP.y);
+                q[j].y += (T)0.5 * (pN.x - pP.x);
             }
-            q[j].x = qx;
-            q[j].y = qy;
-            if (spai && expo[j]) st_c(a.q + rw, q[j]);
-            pq[0] += (double)pn[j].x * (double)qx;
-            pq[1] += (double)pn[j].y * (double)qy;
+            if (spai && expo[j]) st_c(a.q + rows[j], q[j]);
+            pq[0] += (double)pn[j].x * (double)q[j].x;
+            pq[1] += (double)pn[j].y * (double)q[j].y;
         }
         bsum<BLK, 2>(pq, lds);
         if (threadIdx.x == 0) {
@@ -780,16 +806,18 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             }
             if (stat) break;
         }
-        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r (Jacobi) or, after
-        // one more barrier that publishes r, z = M r (learned SPAI); r.z, r.r
+        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r (Jacobi) or M r
+        // (learned SPAI, halo residual rebuilt as r_old - alpha q); r.z, r.r
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            po[j] = pn[j];
             if (!valid[j] || msk[j]) continue;
-            e[j].x += ax * pn[j].x;
-            e[j].y += ay * pn[j].y;
+            const V2 p = lv[rows[j] - lo];
+            V2 ev = le[rows[j] - lo];
+            ev.x += ax * p.x;
+            ev.y += ay * p.y;
+            le[rows[j] - lo] = ev;
             r[j].x -= ax * q[j].x;
             r[j].y -= ay * q[j].y;
             if (spai) continue;
@@ -805,14 +833,35 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (!valid[j]) continue;
-                lds_p[rows[j] - lo] = r[j];
+                lrs[rows[j] - lo] = r[j];
                 if (expo[j]) st_c(rnext + rows[j], r[j]);
             }
+            {
+                const V2 r0 = ld_c(rcur + hc0), q0 = ld_c(a.q + hc0);
+                const V2 r1 = ld_c(rcur + hc1), q1 = ld_c(a.q + hc1);
+                V2 v0, v1;
+                v0.x = r0.x - ax * q0.x;
+                v0.y = r0.y - ay * q0.y;
+                v1.x = r1.x - ax * q1.x;
+                v1.y = r1.y - ay * q1.y;
+                if (h0ok) lrh[threadIdx.x] = v0;
+                if (h1ok) lrh[threadIdx.x + BLK] = v1;
+                for (int h = threadIdx.x + 2 * BLK; h < nh; h += BLK) {
+                    const int c = a.halo[hb + h];
+                    const V2 rc = ld_c(rcur + c), qc = ld_c(a.q + c);
+                    V2 v;
+                    v.x = rc.x - ax * qc.x;
+                    v.y = rc.y - ay * qc.y;
+                    lrh[h] = v;
+                }
+            }
             __syncthreads();
+            V2 mz[R];
+            lds_spmv<float, T, V2, R>(a.lcol, a.mval, a.mdiag, rv, base, w, r, lrs, mz);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 if (!valid[j] || msk[j]) continue;
-                z[j] = spai_row<T, V2, KBR>(a, rows[j], r[j], lds_p, lo, hi, rcur, a.q, ax, ay);
+                z[j] = mz[j];
                 if (expo[j]) st_c(a.z + rows[j], z[j]);
                 acc2[0] += (double)r[j].x * (double)z[j].x;
                 acc2[1] += (double)r[j].y * (double)z[j].y;
@@ -865,7 +914,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     // the correction leaves through plain stores (read by the next kernel)
 #pragma unroll
     for (int j = 0; j < R; ++j)
-        if (valid[j]) a.e[rows[j]] = e[j];
+        if (valid[j]) a.e[rows[j]] = le[rows[j] - lo];
     if (leader) {
         a.iters[sub] = it;
         a.status[sub] = stat;
@@ -1550,6 +1599,47 @@ static const void* pcg_kernel(int blk, int R) {
     return reinterpret_cast<const void*>(&k_pcg<T, 1024, 2>);
 }
 
+// Local numbering of the register-resident kernel: for each workgroup range
+// [s0, s1) of 64-row slices, the sorted distinct columns outside it that its
+// rows reference (its halo), the local column of every SELL slot of its rows
+// (own row c -> c - 64 s0, halo column -> 64 (s1 - s0) + its halo position) and
+// the local loop neighbours of its boundary rows.  The ranges are disjoint, so
+// each writes its own slots and rows.
+static void local_numbering(const pgcp_part* P, const std::vector<std::pair<int32_t, int32_t>>& ranges,
+                            std::vector<std::vector<int32_t>>& halo, std::vector<int32_t>& lcol,
+                            std::vector<int32_t>& lpn) {
+    lcol.assign(P->sell_elems, 0);
+    lpn.assign(2 * P->N, -1);
+    halo.assign(ranges.size(), {});
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t g = 0; g < (int64_t)ranges.size(); ++g) {
+        const int64_t lo = (int64_t)ranges[g].first * 64, hi = (int64_t)ranges[g].second * 64;
+        const int32_t nown = (int32_t)(hi - lo);
+        const int64_t e0 = P->sl_ptr[ranges[g].first], e1 = P->sl_ptr[ranges[g].second];
+        std::vector<int32_t>& h = halo[g];
+        auto outside = [&](int64_t c) { return c < lo || c >= hi; };
+        for (int64_t el = e0; el < e1; ++el)
+            if (outside(P->sl_col[el])) h.push_back(P->sl_col[el]);
+        for (int64_t rw = lo; rw < hi; ++rw)
+            if (P->row_prev[rw] >= 0 && P->row_next[rw] >= 0) {
+                if (outside(P->row_prev[rw])) h.push_back(P->row_prev[rw]);
+                if (outside(P->row_next[rw])) h.push_back(P->row_next[rw]);
+            }
+        std::sort(h.begin(), h.end());
+        h.erase(std::unique(h.begin(), h.end()), h.end());
+        auto local = [&](int32_t c) -> int32_t {
+            if (!outside(c)) return (int32_t)(c - lo);
+            return nown + (int32_t)(std::lower_bound(h.begin(), h.end(), c) - h.begin());
+        };
+        for (int64_t el = e0; el < e1; ++el) lcol[el] = local(P->sl_col[el]);
+        for (int64_t rw = lo; rw < hi; ++rw)
+            if (P->row_prev[rw] >= 0 && P->row_next[rw] >= 0) {
+                lpn[2 * rw] = local(P->row_prev[rw]);
+                lpn[2 * rw + 1] = local(P->row_next[rw]);
+            }
+    }
+}
+
 // Workgroup map for one launch shape.  Pieces are placed on XCDs by
 // longest-processing-time first (workgroups g with g % n_xcd == x run on XCD x
 // under the hardware's round-robin dispatch), every piece on exactly one XCD,
@@ -1561,12 +1651,6 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     HIPCHK(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, ctx->device));
     if (!coop) return Error{PGCP_E_HIP, "device does not support cooperative launches"};
     const int n_xcd = (n_cu >= 64 && n_cu % 32 == 0) ? n_cu / 32 : 1;
-    int per_cu = 0;
-    const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
-                                  : (prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R));
-    const size_t lds_bytes = cfg.stream ? 0 : (size_t)cfg.blk * cfg.R * (prec == 0 ? 16 : 8);
-    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
-    const int64_t cap = (int64_t)per_cu * n_cu;
     const int64_t spw = (int64_t)(cfg.blk / 64) * cfg.R;   // slices per workgroup
     const int K = P->K;
     std::vector<int64_t> nw(K, 1);
@@ -1576,6 +1660,38 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
             int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
             nw[i] = std::max<int64_t>(1, (ns + spw - 1) / spw);
         }
+    // slice range of workgroup t of piece i (every map but the size-weighted
+    // one), and for the register-resident kernel the local numbering of each
+    // workgroup's rows and halo
+    std::vector<std::pair<int32_t, int32_t>> ranges;
+    std::vector<int64_t> range0(K + 1, 0);
+    std::vector<std::vector<int32_t>> halo;
+    std::vector<int32_t> lcol, lpn;
+    size_t lds_bytes = 0;
+    int64_t lds_n = 0;
+    if (spw > 0)
+        for (int i = 0; i < K; ++i) {
+            const int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
+            range0[i + 1] = range0[i] + nw[i];
+            for (int64_t t = 0; t < nw[i]; ++t)
+                ranges.emplace_back((int32_t)(sb + ns * t / nw[i]), (int32_t)(sb + ns * (t + 1) / nw[i]));
+        }
+    if (!cfg.stream) {
+        local_numbering(P, ranges, halo, lcol, lpn);
+        size_t max_nh = 0;
+        for (const auto& h : halo) max_nh = std::max(max_nh, h.size());
+        int lds_max = 0;
+        HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
+        // p and the SPAI operand (own rows + halo each), e (own rows)
+        lds_n = (int64_t)cfg.blk * cfg.R + (int64_t)max_nh;
+        lds_bytes = (size_t)(2 * lds_n + (int64_t)cfg.blk * cfg.R) * (prec == 0 ? 16 : 8);
+        if (lds_bytes + 4096 > (size_t)lds_max) return Error{PGCP_OK, ""};
+    }
+    int per_cu = 0;
+    const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
+                                  : (prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R));
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
+    const int64_t cap = (int64_t)per_cu * n_cu;
     if (cfg.stream && cfg.R <= 0) {
         // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
         // in proportion to ns_i^1.5 (its rows times its expected CG iterations,
@@ -1598,6 +1714,7 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         W->blk = cfg.blk;
         W->rows_per_thread = 0;
         W->stream = 1;
+        W->lds_bytes = 0;
         W->n_xcd = n_xcd;
         W->n_wg = (int)G;
         W->wg_sub.assign(G, -1);
@@ -1663,20 +1780,38 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         pb += (int32_t)nw[i];
     }
     W->n_partials = pb;
+    W->lds_bytes = lds_bytes;
+    W->lds_n = (int)lds_n;
     for (int x = 0; x < n_xcd; ++x) {
         int64_t slot = 0;
         for (int i : on[x]) {
-            int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
             for (int64_t t = 0; t < nw[i]; ++t, ++slot) {
                 int64_t g = slot * n_xcd + x;
                 W->wg_sub[g] = i;
                 W->wg_rank[g] = (int32_t)t;
-                W->wg_s0[g] = (int32_t)(sb + ns * t / nw[i]);
-                W->wg_s1[g] = (int32_t)(sb + ns * (t + 1) / nw[i]);
+                W->wg_s0[g] = ranges[range0[i] + t].first;
+                W->wg_s1[g] = ranges[range0[i] + t].second;
             }
         }
     }
+    // halo entries in workgroup order (register-resident kernel only)
+    std::vector<int32_t> wg_h0(G + 1, 0), hcat;
+    for (int64_t g = 0; g < G && !cfg.stream; ++g) {
+        if (W->wg_sub[g] >= 0) {
+            const auto& h = halo[range0[W->wg_sub[g]] + W->wg_rank[g]];
+            hcat.insert(hcat.end(), h.begin(), h.end());
+        }
+        if (hcat.size() > (size_t)INT32_MAX) return Error{PGCP_E_INVALID, "halo too large for int32 offsets"};
+        wg_h0[g + 1] = (int32_t)hcat.size();
+    }
+    if (hcat.empty()) hcat.push_back(0);
     Error e{PGCP_OK, ""};
+    if (!cfg.stream) {
+        if ((e = upload(W->d_wg_h0, wg_h0, ctx->stream)).code) return e;
+        if ((e = upload(W->d_halo, hcat, ctx->stream)).code) return e;
+        if ((e = upload(W->d_lcol, lcol, ctx->stream)).code) return e;
+        if ((e = upload(W->d_lpn, lpn, ctx->stream)).code) return e;
+    }
     if ((e = upload(W->d_wg_sub, W->wg_sub, ctx->stream)).code) return e;
     if ((e = upload(W->d_wg_rank, W->wg_rank, ctx->stream)).code) return e;
     if ((e = upload(W->d_wg_s0, W->wg_s0, ctx->stream)).code) return e;
@@ -1707,6 +1842,11 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.wg_s1 = (const int32_t*)W.d_wg_s1.p;
     a.sub_pbase = (const int32_t*)W.d_sub_pbase.p;
     a.sub_nwg = (const int32_t*)W.d_sub_nwg.p;
+    a.wg_h0 = (const int32_t*)W.d_wg_h0.p;
+    a.halo = (const int32_t*)W.d_halo.p;
+    a.lcol = (const int32_t*)W.d_lcol.p;
+    a.lpn = (const int32_t*)W.d_lpn.p;
+    a.lds_n = W.lds_n;
     a.active = (const int32_t*)P->d_active.p;
     a.target_rel2 = (const double*)P->d_target.p;
     a.e = (V2*)P->d_e.p;
@@ -1770,7 +1910,7 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<float>(W.blk), grid, block, args, 0, s));
         else
             HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
-                                              (size_t)W.blk * W.rows_per_thread * 8, s));
+                                              W.lds_bytes, s));
     } else {
         CGArgs<double> a = cg_args<double>(P, W, mask, coupled, max_iter, (const double*)P->d_val64.p,
                                            (const double*)P->d_diag64.p);
@@ -1785,7 +1925,7 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<double>(W.blk), grid, block, args, 0, s));
         else
             HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
-                                              (size_t)W.blk * W.rows_per_thread * 16, s));
+                                              W.lds_bytes, s));
     }
     return Error{PGCP_OK, ""};
 }
@@ -1798,8 +1938,7 @@ static Error stream_fit(pgcp_ctx* ctx, pgcp_part* P, int prec, int blk, int* R) 
         WorkMap T;
         bool fits;
         Error e = build_workmap(ctx, P, prec, PcgCfg{blk, r, 1}, &T, &fits);
-        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
-            dev_free(*b);
+        free_workmap(T);
         if (e.code) return e;
         if (fits) {
             *R = r;
@@ -1872,8 +2011,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
         WorkMap T;
         bool fits;
         Error e = build_workmap(ctx, P, prec, c, &T, &fits);
-        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
-            dev_free(*b);
+        free_workmap(T);
         if (e.code) return e;
         reg_fits |= fits;
     }
@@ -1914,8 +2052,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             best_ms = ms;
             best = c;
         }
-        for (DevBuf* b : {&T.d_wg_sub, &T.d_wg_rank, &T.d_wg_s0, &T.d_wg_s1, &T.d_sub_pbase, &T.d_sub_nwg})
-            dev_free(*b);
+        free_workmap(T);
     }
     if (best.blk == 0) return Error{PGCP_E_INVALID, "problem too large for one cooperative launch"};
     bool fits;

@@ -41,6 +41,10 @@ struct WorkMap {
     std::vector<int32_t> wg_sub, wg_rank, wg_s0, wg_s1;   // per workgroup
     std::vector<int32_t> sub_pbase, sub_nwg;              // per piece
     DevBuf d_wg_sub, d_wg_rank, d_wg_s0, d_wg_s1, d_sub_pbase, d_sub_nwg;
+    // register-resident kernel: local numbering of each workgroup's rows and halo
+    size_t lds_bytes = 0;        // dynamic LDS per workgroup
+    int lds_n = 0;               // LDS entries of one vector: own rows + largest halo
+    DevBuf d_wg_h0, d_halo, d_lcol, d_lpn;
 };
 
 }  // namespace pgcp
