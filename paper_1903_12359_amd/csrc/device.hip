@@ -321,7 +321,7 @@ struct CGArgs {
     const int32_t* sub_nwg;        // [K] workgroups of the piece
     const int32_t* wg_h0;          // [G+1] register kernel: first halo entry of each workgroup
     const int32_t* halo;           // [*] register kernel: packed rows of the halo entries
-    const int32_t* lcol;           // [sell] register kernel: local column of every SELL slot
+    const uint16_t* lcol;          // [sell] register kernel: local column of every SELL slot
     const int32_t* lpn;            // [2N] register kernel: local loop neighbours (prev, next) or -1
     int lds_n;                     // register kernel: LDS entries of one vector (own rows + largest halo)
     const int32_t* active;         // [K]
@@ -350,30 +350,30 @@ struct CGArgs {
     int stall;                     // stop after this many iterations without a 10% residual gain
 };
 
-// Fixed-order block sum of NV values per thread; result returned to every thread.
+// Fixed-order block sum of NV values per thread; result returned to every
+// thread.  The per-wave sums go to one of two LDS banks that alternate from
+// call to call (par), so one barrier per call suffices: a bank is written
+// again only two calls later, after every thread has passed the barrier of
+// the call in between and so has finished reading it.
 template <int BLK, int NV>
-__device__ __forceinline__ void bsum(double (&v)[NV], double* lds) {
+__device__ __forceinline__ void bsum(double (&v)[NV], double* lds, int& par) {
     constexpr int NW = BLK / 64;
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* bank = lds + par * (NW * 8);
+    par ^= 1;
     if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double s = 0.0;
-            for (int w = 0; w < NW; ++w) s += lds[w * NV + i];
-            lds[NW * NV + i] = s;
-        }
+        for (int i = 0; i < NV; ++i) bank[wave * NV + i] = v[i];
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = lds[NW * NV + i];
-    __syncthreads();
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += bank[w * NV + i];
+        v[i] = s;
+    }
 }
 
 // Cross-workgroup data (the z and p vectors that neighbours gather, and the
@@ -418,7 +418,7 @@ __device__ __forceinline__ void st_c(double* p, double v) {
 // Fixed-order sum of the piece's partial records (slots off .. off+NV-1).
 template <int BLK, int NV>
 __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int nwg, int off, double (&out)[NV],
-                                          double* lds) {
+                                          double* lds, int& par) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) out[i] = 0.0;
     for (int w = threadIdx.x; w < nwg; w += BLK) {
@@ -426,7 +426,7 @@ __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int 
 #pragma unroll
         for (int i = 0; i < NV; ++i) out[i] += ld_c(p + i);
     }
-    bsum<BLK, NV>(out, lds);
+    bsum<BLK, NV>(out, lds, par);
 }
 
 // z = M r for one row with the learned SPAI (M has the Laplacian's pattern):
@@ -493,7 +493,8 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
 template <int BLK, int NV>
 __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsigned nb, int nwg,
                                              const double* partial, int pbase, int off, double* res,
-                                             double (&out)[NV], int* abort_flag, int* lds_flag, double* lds) {
+                                             double (&out)[NV], int* abort_flag, int* lds_flag, double* lds,
+                                             int& par) {
     __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -502,7 +503,7 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
     }
     __syncthreads();
     if (lds_flag[1]) {
-        piece_sum<BLK, NV>(partial, pbase, nwg, off, out, lds);
+        piece_sum<BLK, NV>(partial, pbase, nwg, off, out, lds, par);
         if (threadIdx.x == 0) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) st_c(res + off + i, out[i]);
@@ -550,25 +551,63 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
 // values the owning workgroups published before the last barrier.  Only rows
 // with a neighbour in another workgroup publish.
 
-// y_j = d_j x_j + sum_k v_jk x[lcol_jk] for the thread's R rows, operands in LDS.
+// y_j = d_j x_j + sum_k v_jk x[lcol_jk] for the thread's R rows, operands in
+// LDS.  The first KS slots of RB rows are loaded together, without branches
+// (slots past a row's width are clamped to its last slot and masked), so that
+// one memory round trip serves them; a scheduling barrier between row groups
+// keeps the compiler from hoisting every group's loads at once (which would
+// spill registers).  Wider rows loop over the rest.
+constexpr int KS = 6;
+constexpr int RB = 2;
+
 template <typename TV, typename T, typename V2, int R>
-__device__ __forceinline__ void lds_spmv(const int32_t* __restrict__ lcol, const TV* __restrict__ val,
+__device__ __forceinline__ void lds_spmv(const uint16_t* __restrict__ lcol, const TV* __restrict__ val,
                                          const TV* __restrict__ diag, const int32_t (&rv)[R],
                                          const int32_t (&base)[R], const int (&w)[R], const V2 (&x)[R],
                                          const V2* lv, V2 (&y)[R]) {
+    // the slot loads do not depend on the iteration; an opaque zero keeps the
+    // compiler from hoisting them out of the CG loop into registers for good
+    int32_t opq = 0;
+    __asm__ volatile("" : "+v"(opq));
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-        const T d = (T)diag[rv[j]];
-        T yx = d * x[j].x, yy = d * x[j].y;
-        for (int t = 0; t < w[j]; ++t) {
-            const int32_t el = base[j] + t * 64;
-            const V2 c = lv[lcol[el]];
-            const T v = (T)val[el];
-            yx += v * c.x;
-            yy += v * c.y;
+    for (int j0 = 0; j0 < R; j0 += RB) {
+        __builtin_amdgcn_sched_barrier(0);
+        constexpr int G = RB < R ? RB : R;
+        int lc[G][KS];
+        TV vv[G][KS], dd[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int j = j0 + g < R ? j0 + g : R - 1;
+            dd[g] = diag[rv[j]];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int32_t el = base[j] + opq + min(t, w[j] - 1) * 64;
+                lc[g][t] = lcol[el];
+                vv[g][t] = val[el];
+            }
         }
-        y[j].x = yx;
-        y[j].y = yy;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int j = j0 + g;
+            if (j >= R) break;
+            T yx = (T)dd[g] * x[j].x, yy = (T)dd[g] * x[j].y;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const V2 c = lv[lc[g][t]];
+                const T v = t < w[j] ? (T)vv[g][t] : (T)0;
+                yx += v * c.x;
+                yy += v * c.y;
+            }
+            for (int t = KS; t < w[j]; ++t) {
+                const int32_t el = base[j] + t * 64;
+                const V2 c = lv[lcol[el]];
+                const T v = (T)val[el];
+                yx += v * c.x;
+                yy += v * c.y;
+            }
+            y[j].x = yx;
+            y[j].y = yy;
+        }
     }
 }
 
@@ -580,7 +619,8 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     V2* lv = reinterpret_cast<V2*>(smem_raw);   // [lds_n] p: own rows, then the halo
     V2* lrs = lv + a.lds_n;                     // [lds_n] SPAI operand r: own rows, then the halo
     V2* le = lv + 2 * (int64_t)a.lds_n;         // [BLK R] e of the own rows
-    __shared__ double lds[NW * 8 + 16];
+    __shared__ double lds[2 * NW * 8];
+    int bpar = 0;   // LDS bank of the next block sum
     __shared__ int lds_flag[2];
     const int wg = blockIdx.x;
     const int sub = a.wg_sub[wg];
@@ -590,7 +630,8 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
     const bool leader = rank == 0 && threadIdx.x == 0;
     const bool spai = a.pc != nullptr && a.pc[sub] != 0;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index is uniform: slice numbers, widths and offsets stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t lo = (int64_t)s0 * 64;
     const int nown = (s1 - s0) * 64;
     const int hb = a.wg_h0[wg], nh = a.wg_h0[wg + 1] - hb;
@@ -684,14 +725,14 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         acc[2] += (double)r[j].x * (double)r[j].x;
         acc[3] += (double)r[j].y * (double)r[j].y;
     }
-    bsum<BLK, 4>(acc, lds);
+    bsum<BLK, 4>(acc, lds, bpar);
     if (threadIdx.x == 0) {
         for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
     }
     nbar++;
     double st[4];
     if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
-                             a.abort_flag, lds_flag, lds)) {
+                             a.abort_flag, lds_flag, lds, bpar)) {
         if (leader) a.status[sub] = 3;
         return;
     }
@@ -775,7 +816,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
             pq[0] += (double)pn[j].x * (double)q[j].x;
             pq[1] += (double)pn[j].y * (double)q[j].y;
         }
-        bsum<BLK, 2>(pq, lds);
+        bsum<BLK, 2>(pq, lds, bpar);
         if (threadIdx.x == 0) {
             st_c(mypart + 0, pq[0]);
             st_c(mypart + 1, pq[1]);
@@ -783,7 +824,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         nbar++;
         double pqs[2];
         if (piece_reduce<BLK, 2>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, pqs,
-                                 a.abort_flag, lds_flag, lds)) {
+                                 a.abort_flag, lds_flag, lds, bpar)) {
             stat = 3;
             break;
         }
@@ -869,13 +910,13 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
                 acc2[3] += (double)r[j].y * (double)r[j].y;
             }
         }
-        bsum<BLK, 4>(acc2, lds);
+        bsum<BLK, 4>(acc2, lds, bpar);
         if (threadIdx.x == 0) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
         }
         nbar++;
         if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
-                                 a.abort_flag, lds_flag, lds)) {
+                                 a.abort_flag, lds_flag, lds, bpar)) {
             stat = 3;
             break;
         }
@@ -933,7 +974,8 @@ template <typename T, int BLK>
 __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
     using V2 = typename Vec2<T>::type;
     constexpr int NW = BLK / 64;
-    __shared__ double lds[NW * 8 + 16];
+    __shared__ double lds[2 * NW * 8];
+    int bpar = 0;   // LDS bank of the next block sum
     __shared__ int lds_flag[2];
     const int wg = blockIdx.x;
     const int sub = a.wg_sub[wg];
@@ -974,14 +1016,14 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         acc[2] += (double)r.x * (double)r.x;
         acc[3] += (double)r.y * (double)r.y;
     }
-    bsum<BLK, 4>(acc, lds);
+    bsum<BLK, 4>(acc, lds, bpar);
     if (threadIdx.x == 0) {
         for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
     }
     nbar++;
     double st[4];
     if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
-                             a.abort_flag, lds_flag, lds)) {
+                             a.abort_flag, lds_flag, lds, bpar)) {
         if (leader) a.status[sub] = 3;
         return;
     }
@@ -1073,7 +1115,7 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             else
                 a.q[rw] = q;
         }
-        bsum<BLK, 2>(pq, lds);
+        bsum<BLK, 2>(pq, lds, bpar);
         if (threadIdx.x == 0) {
             st_c(mypart + 0, pq[0]);
             st_c(mypart + 1, pq[1]);
@@ -1081,7 +1123,7 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         nbar++;
         double pqs[2];
         if (piece_reduce<BLK, 2>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, pqs,
-                                 a.abort_flag, lds_flag, lds)) {
+                                 a.abort_flag, lds_flag, lds, bpar)) {
             stat = 3;
             break;
         }
@@ -1139,13 +1181,13 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
             acc2[3] += (double)r.y * (double)r.y;
         }
 
-        bsum<BLK, 4>(acc2, lds);
+        bsum<BLK, 4>(acc2, lds, bpar);
         if (threadIdx.x == 0) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
         }
         nbar++;
         if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
-                                 a.abort_flag, lds_flag, lds)) {
+                                 a.abort_flag, lds_flag, lds, bpar)) {
             stat = 3;
             break;
         }
@@ -1602,11 +1644,12 @@ static const void* pcg_kernel(int blk, int R) {
 // Local numbering of the register-resident kernel: for each workgroup range
 // [s0, s1) of 64-row slices, the sorted distinct columns outside it that its
 // rows reference (its halo), the local column of every SELL slot of its rows
-// (own row c -> c - 64 s0, halo column -> 64 (s1 - s0) + its halo position) and
+// (own row c -> c - 64 s0, halo column -> 64 (s1 - s0) + its halo position;
+// 16-bit, shapes whose workgroups exceed 65536 entries are rejected) and
 // the local loop neighbours of its boundary rows.  The ranges are disjoint, so
 // each writes its own slots and rows.
 static void local_numbering(const pgcp_part* P, const std::vector<std::pair<int32_t, int32_t>>& ranges,
-                            std::vector<std::vector<int32_t>>& halo, std::vector<int32_t>& lcol,
+                            std::vector<std::vector<int32_t>>& halo, std::vector<uint16_t>& lcol,
                             std::vector<int32_t>& lpn) {
     lcol.assign(P->sell_elems, 0);
     lpn.assign(2 * P->N, -1);
@@ -1631,7 +1674,7 @@ static void local_numbering(const pgcp_part* P, const std::vector<std::pair<int3
             if (!outside(c)) return (int32_t)(c - lo);
             return nown + (int32_t)(std::lower_bound(h.begin(), h.end(), c) - h.begin());
         };
-        for (int64_t el = e0; el < e1; ++el) lcol[el] = local(P->sl_col[el]);
+        for (int64_t el = e0; el < e1; ++el) lcol[el] = (uint16_t)local(P->sl_col[el]);
         for (int64_t rw = lo; rw < hi; ++rw)
             if (P->row_prev[rw] >= 0 && P->row_next[rw] >= 0) {
                 lpn[2 * rw] = local(P->row_prev[rw]);
@@ -1666,7 +1709,8 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     std::vector<std::pair<int32_t, int32_t>> ranges;
     std::vector<int64_t> range0(K + 1, 0);
     std::vector<std::vector<int32_t>> halo;
-    std::vector<int32_t> lcol, lpn;
+    std::vector<uint16_t> lcol;
+    std::vector<int32_t> lpn;
     size_t lds_bytes = 0;
     int64_t lds_n = 0;
     if (spw > 0)
@@ -1685,7 +1729,8 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         // p and the SPAI operand (own rows + halo each), e (own rows)
         lds_n = (int64_t)cfg.blk * cfg.R + (int64_t)max_nh;
         lds_bytes = (size_t)(2 * lds_n + (int64_t)cfg.blk * cfg.R) * (prec == 0 ? 16 : 8);
-        if (lds_bytes + 4096 > (size_t)lds_max) return Error{PGCP_OK, ""};
+        // local columns are 16-bit; a shape whose workgroup has more entries does not fit
+        if (lds_n > 65536 || lds_bytes + 4096 > (size_t)lds_max) return Error{PGCP_OK, ""};
     }
     int per_cu = 0;
     const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
@@ -1844,7 +1889,7 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.sub_nwg = (const int32_t*)W.d_sub_nwg.p;
     a.wg_h0 = (const int32_t*)W.d_wg_h0.p;
     a.halo = (const int32_t*)W.d_halo.p;
-    a.lcol = (const int32_t*)W.d_lcol.p;
+    a.lcol = (const uint16_t*)W.d_lcol.p;
     a.lpn = (const int32_t*)W.d_lpn.p;
     a.lds_n = W.lds_n;
     a.active = (const int32_t*)P->d_active.p;

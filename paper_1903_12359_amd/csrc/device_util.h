@@ -65,10 +65,42 @@ __device__ __forceinline__ V axpy2(V x, S ax, S ay, V y) {   // y + a*x per comp
     return o;
 }
 
+// One DPP move of a double (both 32-bit halves) with a compile-time control.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    int lo, hi;
+    __builtin_memcpy(&lo, &v, 4);
+    __builtin_memcpy(&hi, reinterpret_cast<const char*>(&v) + 4, 4);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+    double r;
+    __builtin_memcpy(&r, &lo, 4);
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 4, &hi, 4);
+    return r;
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    int lo, hi;
+    __builtin_memcpy(&lo, &v, 4);
+    __builtin_memcpy(&hi, reinterpret_cast<const char*>(&v) + 4, 4);
+    lo = __builtin_amdgcn_readlane(lo, l);
+    hi = __builtin_amdgcn_readlane(hi, l);
+    double r;
+    __builtin_memcpy(&r, &lo, 4);
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 4, &hi, 4);
+    return r;
+}
+
+// Sum over the 64 lanes of a wave, the same bits in every lane: DPP exchanges
+// inside each row of 16 lanes (swap neighbours, swap pairs, mirror the
+// half-rows, mirror the row), after which every lane holds its row's sum, then
+// the four row sums in a fixed order.  All lanes must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_mov<0x141>(v);   // row_half_mirror
+    v += dpp_mov<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Fixed-order block sum of NV values per thread; result valid in thread 0.
