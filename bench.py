@@ -50,9 +50,9 @@ HBM_PEAK_GBS = 8000.0
 # summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
 TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "a8ff198a83b88bc458dc4c4d4dfc71c71065d02e35054c06cf41c438fe402fa4",
+           "source_sha256": "8e47207068a84aff863a70bf5d5b787e08470339b3727aa8027656433ff6e394",
            "pcg_shapes": {"dncp": "512,4,0", "harmonic": "256,4,0"},
-           "bytes_per_launch": 6.432e9},
+           "bytes_per_launch": 4.679e9},
 }
 
 
