@@ -248,7 +248,7 @@ def main():
                     "harmonic_max_relres": float(info["harmonic"].relres.max())},
     }
     def shape(rep):
-        return f"{rep.cg_block},{rep.rows_per_thread},{rep.cg_stream}"
+        return f"{rep.cg_block},{rep.rows_per_thread},{rep.cg_stream},{rep.cg_single}"
 
     for name, r in res.items():
         rec[name] = {"value": round(r["value"], 4), "ms_per_step": round(r["ms_per_step"], 3),

@@ -108,7 +108,10 @@ typedef struct {
                                  (rows beyond what registers of one cooperative grid hold) */
     int32_t n_fallback;       /* out: pieces finished with Jacobi after the learned
                                  preconditioner broke down or stagnated              */
-    int32_t reserved3;
+    int32_t cg_single;        /* out: 1 if the last batched-CG launch used the single-reduction
+                                 kernel (one per-piece barrier per iteration; opt-in with
+                                 PGCP_PCG_KERNEL=single in the environment), 0 if the
+                                 two-barrier or the streaming kernel                     */
 } pgcp_solve_stats;
 
 /* Distortion statistics over all 3|F| angles (Table 5 of the paper). */

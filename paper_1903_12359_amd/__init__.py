@@ -43,7 +43,7 @@ class SolveStats(ctypes.Structure):
                 ("status", ctypes.POINTER(ctypes.c_int32)), ("seconds", ctypes.c_double),
                 ("cg_kernel_ms", ctypes.c_double), ("cg_bytes", ctypes.c_double), ("cg_launches", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("cg_block", ctypes.c_int32),
-                ("cg_stream", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("reserved3", ctypes.c_int32)]
+                ("cg_stream", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("cg_single", ctypes.c_int32)]
 
 
 class DistStats(ctypes.Structure):
@@ -151,6 +151,7 @@ class SolveReport:
     cg_block: int = 0
     cg_stream: int = 0
     n_fallback: int = 0
+    cg_single: int = 0
 
 
 class Context:
@@ -338,7 +339,7 @@ def _report(st, keep):
     it, rr, ss = keep
     return SolveReport(st.n_sub, st.refine_steps, st.total_iters, it.copy(), rr.reshape(-1, 2).copy(),
                        ss.copy(), st.seconds, st.cg_kernel_ms, st.cg_bytes, st.cg_launches, st.rows_per_thread,
-                       st.cg_workgroups, st.cg_block, st.cg_stream, st.n_fallback)
+                       st.cg_workgroups, st.cg_block, st.cg_stream, st.n_fallback, st.cg_single)
 
 
 def assemble_cotan(ctx: Context, plan: Plan, V_dev):

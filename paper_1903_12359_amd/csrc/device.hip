@@ -48,7 +48,7 @@ namespace pgcp {
 
 static void free_workmap(WorkMap& W) {
     for (DevBuf* b : {&W.d_wg_sub, &W.d_wg_rank, &W.d_wg_s0, &W.d_wg_s1, &W.d_sub_pbase, &W.d_sub_nwg, &W.d_wg_h0,
-                      &W.d_halo, &W.d_lcol, &W.d_lpn})
+                      &W.d_halo, &W.d_lcol, &W.d_lpn, &W.d_wg_n1, &W.d_rcol, &W.d_expo})
         dev_free(*b);
 }
 
@@ -57,7 +57,7 @@ void free_part_device(pgcp_part* P) {
                      &P->d_sl_ptr, &P->d_sl_w, &P->d_sl_col, &P->d_sl_opp, &P->d_sl_rev, &P->d_val64, &P->d_val32,
                      &P->d_diag64, &P->d_diag32, &P->d_pin_row, &P->d_pin_x1, &P->d_loop_ptr,
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
-                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2,
+                     &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2, &P->d_s1,
                      &P->d_partial, &P->d_bar, &P->d_gen, &P->d_res, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
                      &P->d_flags, &P->d_row0, &P->d_slicepart,
                      &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
@@ -120,6 +120,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_p1, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_q, N * 16)).code) return e;
     if ((e = dev_alloc(P->d_r2, N * 16)).code) return e;
+    if ((e = dev_alloc(P->d_s1, N * 16)).code) return e;
     const size_t K = (size_t)P->K;
     if ((e = dev_alloc(P->d_rnorm, K * 2 * 8)).code) return e;
     if ((e = dev_alloc(P->d_scale, K * 2 * 8)).code) return e;
@@ -323,7 +324,12 @@ struct CGArgs {
     const int32_t* halo;           // [*] register kernel: packed rows of the halo entries
     const uint16_t* lcol;          // [sell] register kernel: local column of every SELL slot
     const int32_t* lpn;            // [2N] register kernel: local loop neighbours (prev, next) or -1
-    int lds_n;                     // register kernel: LDS entries of one vector (own rows + largest halo)
+    int lds_n;                     // register kernel: LDS entries of one vector (own rows + largest ring 1)
+    const int32_t* wg_n1;          // [G] register kernels: ring-1 entries of each workgroup's halo
+    const uint16_t* rcol;          // [halo * KR] single-reduction kernel: local columns of ring-1 rows
+    const uint8_t* expo;           // [N] bit 0: row in some ring 1, bit 1: in some ring 2
+    typename Vec2<T>::type* s1;    // single-reduction kernel: sixth published vector buffer
+    int lds_nr, lds_nu;            // single-reduction kernel: LDS entries of r and u
     const int32_t* active;         // [K]
     const double* target_rel2;     // [K*2] squared relative tolerance per piece and coordinate
     typename Vec2<T>::type* e;
@@ -559,6 +565,7 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
 // spill registers).  Wider rows loop over the rest.
 constexpr int KS = 6;
 constexpr int RB = 2;
+constexpr int KR = 8;   // slots per ring-1 row the single-reduction kernel applies M with
 
 template <typename TV, typename T, typename V2, int R>
 __device__ __forceinline__ void lds_spmv(const uint16_t* __restrict__ lcol, const TV* __restrict__ val,
@@ -634,7 +641,7 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t lo = (int64_t)s0 * 64;
     const int nown = (s1 - s0) * 64;
-    const int hb = a.wg_h0[wg], nh = a.wg_h0[wg + 1] - hb;
+    const int hb = a.wg_h0[wg], nh = a.wg_n1[wg];   // ring 1 only
     V2* lh = lv + nown;
     V2* lrh = lrs + nown;
     unsigned* bar = a.bar + sub;
@@ -951,6 +958,350 @@ __global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
         t = rcur;
         rcur = rnext;
         rnext = t;
+    }
+    // the correction leaves through plain stores (read by the next kernel)
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+        if (valid[j]) a.e[rows[j]] = le[rows[j] - lo];
+    if (leader) {
+        a.iters[sub] = it;
+        a.status[sub] = stat;
+        a.rr_out[2 * sub] = rr0[0] > 0.0 ? rrc[0] / rr0[0] : 0.0;
+        a.rr_out[2 * sub + 1] = rr0[1] > 0.0 ? rrc[1] / rr0[1] : 0.0;
+    }
+}
+
+// Single-reduction batched PCG (Chronopoulos and Gear's recurrences): one
+// per-piece barrier per iteration instead of two.  With u = M r and w = A u,
+// the scalars gamma = (r, u), delta = (w, u) and |r|^2 of an iteration are
+// reduced together; beta = gamma'/gamma, alpha = gamma' / (delta' - beta
+// gamma' / alpha), and p = u + beta p, s = w + beta s (= A p) follow by
+// recurrence, so that x += alpha p and r -= alpha s.  The next residual of a
+// neighbouring row, r - alpha (w + beta s_prev), is rebuilt from the three
+// vectors its owner published before the barrier (double-buffered by
+// iteration parity), on ring 1 and, when M is the learned SPAI, on ring 2 too:
+// the workgroup applies M on its own rows and on ring 1 itself, so w = A u
+// needs no second exchange.  Own rows' w, p, s live in registers; r (own rows
+// and rings), u (own rows and ring 1) and e in LDS.  Same work map, local
+// numbering, barriers and bounded polls as k_pcg.
+template <typename T, int BLK, int R>
+__global__ void __launch_bounds__(BLK) k_pcg1(CGArgs<T> a) {
+    using V2 = typename Vec2<T>::type;
+    constexpr int NW = BLK / 64;
+    extern __shared__ unsigned char smem_raw[];
+    V2* lr = reinterpret_cast<V2*>(smem_raw);   // [lds_nr] r: own rows, ring 1, ring 2
+    V2* lu = lr + a.lds_nr;                     // [lds_nu] u = M r: own rows, ring 1
+    V2* le = lu + a.lds_nu;                     // [BLK R] e of the own rows
+    __shared__ double lds[2 * NW * 8];
+    __shared__ int lds_flag[2];
+    int bpar = 0;
+    const int wg = blockIdx.x;
+    const int sub = a.wg_sub[wg];
+    if (sub < 0 || !a.active[sub]) return;
+    const int s0 = a.wg_s0[wg], s1 = a.wg_s1[wg];
+    const int rank = a.wg_rank[wg];
+    const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
+    const bool leader = rank == 0 && threadIdx.x == 0;
+    const bool spai = a.pc != nullptr && a.pc[sub] != 0;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t lo = (int64_t)s0 * 64;
+    const int nown = (s1 - s0) * 64;
+    const int hb = a.wg_h0[wg], nh = a.wg_h0[wg + 1] - hb, n1 = a.wg_n1[wg];
+    const int nfill = spai ? nh : n1;               // ring entries whose residual the products need
+    const uint8_t pubmask = spai ? 3 : 1;           // rows in some ring 1 (and ring 2) publish
+    unsigned* bar = a.bar + sub;
+    unsigned nbar = 0;
+    double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
+
+    int32_t rows[R], rv[R], base[R];
+    int w[R], lp[R], ln[R];
+    bool valid[R], msk[R], pub[R];
+    V2 wv[R], pv[R], sv[R];
+    T dinv[R];
+    V2 zero;
+    zero.x = (T)0;
+    zero.y = (T)0;
+    // the thread's first two ring entries stay in registers (row lo when absent)
+    const bool h0ok = threadIdx.x < nfill, h1ok = threadIdx.x + BLK < nfill;
+    const int hc0 = h0ok ? a.halo[hb + threadIdx.x] : (int)lo;
+    const int hc1 = h1ok ? a.halo[hb + threadIdx.x + BLK] : (int)lo;
+
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int s = s0 + wave + NW * j;
+        valid[j] = s < s1;
+        const int sv_ = valid[j] ? s : s0;
+        rows[j] = s * 64 + lane;
+        rv[j] = sv_ * 64 + lane;
+        base[j] = (int32_t)a.sl_ptr[sv_] + lane;
+        w[j] = a.sl_w[sv_];
+        wv[j] = zero;
+        pv[j] = zero;
+        sv[j] = zero;
+        dinv[j] = (T)0;
+        msk[j] = true;
+        pub[j] = false;
+        lp[j] = -1;
+        ln[j] = -1;
+        if (!valid[j]) continue;
+        const int32_t rw = rows[j];
+        msk[j] = a.mask[rw] != 0;
+        V2 r0 = zero;
+        if (!msk[j]) {
+            dinv[j] = (T)1 / a.diag[rw];
+            r0 = a.r[rw];
+        }
+        lr[rw - lo] = r0;
+        le[rw - lo] = zero;
+        pub[j] = (a.expo[rw] & pubmask) != 0;
+        if (a.coupled) {
+            lp[j] = a.lpn[2 * rw];
+            ln[j] = a.lpn[2 * rw + 1];
+        }
+    }
+    {
+        // ring residuals of the input (written by the previous kernel)
+        const V2 v0 = a.r[hc0], v1 = a.r[hc1];
+        if (h0ok) lr[nown + threadIdx.x] = v0;
+        if (h1ok) lr[nown + threadIdx.x + BLK] = v1;
+        for (int h = threadIdx.x + 2 * BLK; h < nfill; h += BLK) lr[nown + h] = a.r[a.halo[hb + h]];
+    }
+
+    // u = M r on the own rows and ring 1
+    auto apply_m = [&]() {
+        V2 rr[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) rr[j] = valid[j] ? lr[rows[j] - lo] : zero;
+        if (spai) {
+            V2 mz[R];
+            lds_spmv<float, T, V2, R>(a.lcol, a.mval, a.mdiag, rv, base, w, rr, lr, mz);
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (valid[j]) lu[rows[j] - lo] = msk[j] ? zero : mz[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+                if (valid[j]) {
+                    V2 u;
+                    u.x = dinv[j] * rr[j].x;
+                    u.y = dinv[j] * rr[j].y;
+                    lu[rows[j] - lo] = u;
+                }
+        }
+        for (int h = threadIdx.x; h < n1; h += BLK) {
+            const int c = h < BLK ? hc0 : (h < 2 * BLK ? hc1 : a.halo[hb + h]);
+            const V2 rc = lr[nown + h];
+            V2 u = zero;
+            if (!a.mask[c]) {
+                if (spai) {
+                    const int64_t sc = c >> 6;
+                    const int wc = a.sl_w[sc];
+                    const int64_t bc = a.sl_ptr[sc] + (c & 63);
+                    const T md = (T)a.mdiag[c];
+                    T ux = md * rc.x, uy = md * rc.y;
+#pragma unroll
+                    for (int t = 0; t < KR; ++t) {
+                        const int tt = min(t, wc - 1);
+                        const T m = t < wc ? (T)a.mval[bc + (int64_t)tt * 64] : (T)0;
+                        const V2 x = lr[a.rcol[(int64_t)(hb + h) * KR + tt]];
+                        ux += m * x.x;
+                        uy += m * x.y;
+                    }
+                    u.x = ux;
+                    u.y = uy;
+                } else {
+                    const T di = (T)1 / a.diag[c];
+                    u.x = di * rc.x;
+                    u.y = di * rc.y;
+                }
+            }
+            lu[nown + h] = u;
+        }
+    };
+    // w = A u on the own rows
+    auto apply_a = [&]() {
+        V2 uu[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) uu[j] = valid[j] ? lu[rows[j] - lo] : zero;
+        lds_spmv<T, T, V2, R>(a.lcol, a.val, a.diag, rv, base, w, uu, lu, wv);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (!valid[j] || msk[j]) {
+                wv[j] = zero;
+                continue;
+            }
+            if (a.coupled && lp[j] >= 0) {
+                // (L + L - M/2): the boundary term couples x and y along the loop
+                const V2 pN = lu[ln[j]], pP = lu[lp[j]];
+                wv[j].x -= (T)0.5 * (pN.y - pP.y);
+                wv[j].y += (T)0.5 * (pN.x - pP.x);
+            }
+        }
+    };
+    // (r, u), (w, u), (r, r) per coordinate; publish r, w and s_prev of the
+    // rows other workgroups rebuild, into the buffers of this parity
+    auto dots_publish = [&](int parity, double (&acc)[6]) {
+        V2* PR = parity ? a.z : a.r2;
+        V2* PW = parity ? a.pb : a.pa;
+        V2* PS = parity ? a.s1 : a.q;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (!valid[j]) continue;
+            const V2 r = lr[rows[j] - lo], u = lu[rows[j] - lo];
+            acc[0] += (double)r.x * (double)u.x;
+            acc[1] += (double)r.y * (double)u.y;
+            acc[2] += (double)wv[j].x * (double)u.x;
+            acc[3] += (double)wv[j].y * (double)u.y;
+            acc[4] += (double)r.x * (double)r.x;
+            acc[5] += (double)r.y * (double)r.y;
+            if (pub[j]) {
+                st_c(PR + rows[j], r);
+                st_c(PW + rows[j], wv[j]);
+                st_c(PS + rows[j], sv[j]);
+            }
+        }
+    };
+
+    __syncthreads();
+    apply_m();
+    __syncthreads();
+    apply_a();
+    double acc[6];
+    dots_publish(0, acc);
+    bsum<BLK, 6>(acc, lds, bpar);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 6; ++i) st_c(mypart + i, acc[i]);
+    }
+    nbar++;
+    double st[6];
+    if (piece_reduce<BLK, 6>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, st,
+                             a.abort_flag, lds_flag, lds, bpar)) {
+        if (leader) a.status[sub] = 3;
+        return;
+    }
+    double g[2] = {st[0], st[1]}, dl[2] = {st[2], st[3]}, rr0[2] = {st[4], st[5]};
+    if (a.coupled) {
+        g[0] = g[1] = st[0] + st[1];
+        dl[0] = dl[1] = st[2] + st[3];
+        rr0[0] = rr0[1] = st[4] + st[5];
+    }
+    const double tgt[2] = {a.target_rel2[2 * sub] * rr0[0], a.target_rel2[2 * sub + 1] * rr0[1]};
+    bool done[2] = {rr0[0] <= tgt[0] || !(g[0] > 0.0), rr0[1] <= tgt[1] || !(g[1] > 0.0)};
+    double rrc[2] = {rr0[0], rr0[1]};
+    double alpha[2] = {0.0, 0.0}, beta[2] = {0.0, 0.0};
+    int stat = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (done[c]) continue;
+        if (!(dl[c] > 0.0) || !isfinite(dl[c])) stat = 1;
+        else alpha[c] = g[c] / dl[c];
+    }
+    double best = (done[0] ? 0.0 : 1.0) + (done[1] ? 0.0 : 1.0);
+    int it_best = 0;
+    int it = 0;
+
+    while (stat == 0 && !(done[0] && done[1])) {
+        if (it >= a.max_iter) {
+            stat = 2;
+            break;
+        }
+        const T ax = done[0] ? (T)0 : (T)alpha[0], ay = done[1] ? (T)0 : (T)alpha[1];
+        const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
+        // own rows: p = u + beta p, s = w + beta s, e += alpha p, r -= alpha s
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            if (!valid[j] || msk[j]) continue;
+            const int32_t l = rows[j] - (int32_t)lo;
+            const V2 u = lu[l];
+            pv[j].x = u.x + bx * pv[j].x;
+            pv[j].y = u.y + by * pv[j].y;
+            sv[j].x = wv[j].x + bx * sv[j].x;
+            sv[j].y = wv[j].y + by * sv[j].y;
+            V2 ev = le[l], rv_ = lr[l];
+            ev.x += ax * pv[j].x;
+            ev.y += ay * pv[j].y;
+            rv_.x -= ax * sv[j].x;
+            rv_.y -= ay * sv[j].y;
+            le[l] = ev;
+            lr[l] = rv_;
+        }
+        // ring rows: r - alpha (w + beta s_prev) from this iteration's published vectors
+        {
+            const int par = it & 1;
+            const V2* PR = par ? a.z : a.r2;
+            const V2* PW = par ? a.pb : a.pa;
+            const V2* PS = par ? a.s1 : a.q;
+            const V2 r0 = ld_c(PR + hc0), w0 = ld_c(PW + hc0), q0 = ld_c(PS + hc0);
+            const V2 r1 = ld_c(PR + hc1), w1 = ld_c(PW + hc1), q1 = ld_c(PS + hc1);
+            V2 v0, v1;
+            v0.x = r0.x - ax * (w0.x + bx * q0.x);
+            v0.y = r0.y - ay * (w0.y + by * q0.y);
+            v1.x = r1.x - ax * (w1.x + bx * q1.x);
+            v1.y = r1.y - ay * (w1.y + by * q1.y);
+            if (h0ok) lr[nown + threadIdx.x] = v0;
+            if (h1ok) lr[nown + threadIdx.x + BLK] = v1;
+            for (int h = threadIdx.x + 2 * BLK; h < nfill; h += BLK) {
+                const int c = a.halo[hb + h];
+                const V2 rc = ld_c(PR + c), wc = ld_c(PW + c), qc = ld_c(PS + c);
+                V2 v;
+                v.x = rc.x - ax * (wc.x + bx * qc.x);
+                v.y = rc.y - ay * (wc.y + by * qc.y);
+                lr[nown + h] = v;
+            }
+        }
+        __syncthreads();
+        apply_m();
+        __syncthreads();
+        apply_a();
+        double acc2[6];
+        dots_publish((it + 1) & 1, acc2);
+        bsum<BLK, 6>(acc2, lds, bpar);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < 6; ++i) st_c(mypart + i, acc2[i]);
+        }
+        nbar++;
+        if (piece_reduce<BLK, 6>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 0, a.res + 8 * (int64_t)sub, st,
+                                 a.abort_flag, lds_flag, lds, bpar)) {
+            stat = 3;
+            break;
+        }
+        double gn[2] = {st[0], st[1]}, dn[2] = {st[2], st[3]}, rrn[2] = {st[4], st[5]};
+        if (a.coupled) {
+            gn[0] = gn[1] = st[0] + st[1];
+            dn[0] = dn[1] = st[2] + st[3];
+            rrn[0] = rrn[1] = st[4] + st[5];
+        }
+        ++it;
+        double prog = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            if (done[c]) continue;
+            rrc[c] = rrn[c];
+            if (rrn[c] <= tgt[c] || !(gn[c] > 0.0)) {
+                done[c] = true;
+                continue;
+            }
+            const double bn = gn[c] / g[c];
+            const double den = dn[c] - bn * gn[c] / alpha[c];
+            if (!(den > 0.0) || !isfinite(den)) {
+                stat = 1;
+                break;
+            }
+            beta[c] = bn;
+            alpha[c] = gn[c] / den;
+            g[c] = gn[c];
+            prog += rrn[c] / rr0[c];
+        }
+        if (stat) break;
+        if (a.coupled) done[1] = done[0];
+        // stagnation: no 10% gain of the relative residual in `stall` iterations
+        if (prog < 0.9 * best) {
+            best = prog;
+            it_best = it;
+        } else if (!(done[0] && done[1]) && it - it_best > a.stall) {
+            stat = 4;
+            break;
+        }
     }
     // the correction leaves through plain stores (read by the next kernel)
 #pragma unroll
@@ -1641,45 +1992,116 @@ static const void* pcg_kernel(int blk, int R) {
     return reinterpret_cast<const void*>(&k_pcg<T, 1024, 2>);
 }
 
-// Local numbering of the register-resident kernel: for each workgroup range
-// [s0, s1) of 64-row slices, the sorted distinct columns outside it that its
-// rows reference (its halo), the local column of every SELL slot of its rows
-// (own row c -> c - 64 s0, halo column -> 64 (s1 - s0) + its halo position;
-// 16-bit, shapes whose workgroups exceed 65536 entries are rejected) and
-// the local loop neighbours of its boundary rows.  The ranges are disjoint, so
-// each writes its own slots and rows.
+template <typename T>
+static const void* pcg1_kernel(int blk, int R) {
+    if (blk == 256) {
+        switch (R) {
+            case 1: return reinterpret_cast<const void*>(&k_pcg1<T, 256, 1>);
+            case 2: return reinterpret_cast<const void*>(&k_pcg1<T, 256, 2>);
+            case 4: return reinterpret_cast<const void*>(&k_pcg1<T, 256, 4>);
+            default: return reinterpret_cast<const void*>(&k_pcg1<T, 256, 8>);
+        }
+    }
+    if (blk == 512) {
+        switch (R) {
+            case 1: return reinterpret_cast<const void*>(&k_pcg1<T, 512, 1>);
+            case 2: return reinterpret_cast<const void*>(&k_pcg1<T, 512, 2>);
+            default: return reinterpret_cast<const void*>(&k_pcg1<T, 512, 4>);
+        }
+    }
+    if (R == 1) return reinterpret_cast<const void*>(&k_pcg1<T, 1024, 1>);
+    return reinterpret_cast<const void*>(&k_pcg1<T, 1024, 2>);
+}
+
+// Local numbering of the register-resident kernels.  For each workgroup range
+// [s0, s1) of 64-row slices: ring 1 = the sorted distinct columns outside it
+// that its rows reference (SELL slots and loop neighbours), ring 2 = the sorted
+// distinct columns of ring-1 rows outside the range and ring 1.  Local index:
+// own row c -> c - 64 s0, ring-1 entry i -> nown + i, ring-2 entry i ->
+// nown + n1 + i (16-bit; larger workgroups are rejected by the caller).
+// lcol: local column of every SELL slot of the range's rows; lpn: local loop
+// neighbours of its boundary rows; rcol: local columns of the slots of its
+// ring-1 rows (KR per row, for the single-reduction kernel, which applies M on
+// ring 1); expo: bit 0 if a row is in some workgroup's ring 1, bit 1 if in some
+// ring 2 (the rows whose values their owners publish).  The ranges are
+// disjoint, so each writes its own slots and rows.
+struct LocalNum {
+    std::vector<std::vector<int32_t>> halo;    // per range: ring 1, then ring 2
+    std::vector<int32_t> n1;                   // per range: ring-1 entries
+    std::vector<uint16_t> lcol;                // [sell]
+    std::vector<int32_t> lpn;                  // [2N]
+    std::vector<std::vector<uint16_t>> rcol;   // per range: [n1 * KR]
+    std::vector<uint8_t> expo;                 // [N]
+    bool rings_ok = true;                      // ring-1 rows have at most KR slots
+};
+
 static void local_numbering(const pgcp_part* P, const std::vector<std::pair<int32_t, int32_t>>& ranges,
-                            std::vector<std::vector<int32_t>>& halo, std::vector<uint16_t>& lcol,
-                            std::vector<int32_t>& lpn) {
-    lcol.assign(P->sell_elems, 0);
-    lpn.assign(2 * P->N, -1);
-    halo.assign(ranges.size(), {});
+                            LocalNum& L) {
+    const size_t G = ranges.size();
+    L.lcol.assign(P->sell_elems, 0);
+    L.lpn.assign(2 * P->N, -1);
+    L.halo.assign(G, {});
+    L.n1.assign(G, 0);
+    L.rcol.assign(G, {});
+    L.expo.assign(P->N, 0);
+    std::vector<uint8_t> ok(G, 1);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t g = 0; g < (int64_t)ranges.size(); ++g) {
+    for (int64_t g = 0; g < (int64_t)G; ++g) {
         const int64_t lo = (int64_t)ranges[g].first * 64, hi = (int64_t)ranges[g].second * 64;
         const int32_t nown = (int32_t)(hi - lo);
         const int64_t e0 = P->sl_ptr[ranges[g].first], e1 = P->sl_ptr[ranges[g].second];
-        std::vector<int32_t>& h = halo[g];
         auto outside = [&](int64_t c) { return c < lo || c >= hi; };
+        std::vector<int32_t> r1, r2;
         for (int64_t el = e0; el < e1; ++el)
-            if (outside(P->sl_col[el])) h.push_back(P->sl_col[el]);
+            if (outside(P->sl_col[el])) r1.push_back(P->sl_col[el]);
         for (int64_t rw = lo; rw < hi; ++rw)
             if (P->row_prev[rw] >= 0 && P->row_next[rw] >= 0) {
-                if (outside(P->row_prev[rw])) h.push_back(P->row_prev[rw]);
-                if (outside(P->row_next[rw])) h.push_back(P->row_next[rw]);
+                if (outside(P->row_prev[rw])) r1.push_back(P->row_prev[rw]);
+                if (outside(P->row_next[rw])) r1.push_back(P->row_next[rw]);
             }
-        std::sort(h.begin(), h.end());
-        h.erase(std::unique(h.begin(), h.end()), h.end());
+        std::sort(r1.begin(), r1.end());
+        r1.erase(std::unique(r1.begin(), r1.end()), r1.end());
+        auto in_r1 = [&](int32_t c) { return std::binary_search(r1.begin(), r1.end(), c); };
+        for (int32_t c : r1) {
+            const int64_t sc = c / 64, lane = c % 64;
+            for (int32_t k = 0; k < P->sl_w[sc]; ++k) {
+                const int32_t q = P->sl_col[P->sl_ptr[sc] + (int64_t)k * 64 + lane];
+                if (outside(q) && !in_r1(q)) r2.push_back(q);
+            }
+            if (P->sl_w[sc] > KR) ok[g] = 0;
+        }
+        std::sort(r2.begin(), r2.end());
+        r2.erase(std::unique(r2.begin(), r2.end()), r2.end());
+        const int32_t n1 = (int32_t)r1.size();
         auto local = [&](int32_t c) -> int32_t {
             if (!outside(c)) return (int32_t)(c - lo);
-            return nown + (int32_t)(std::lower_bound(h.begin(), h.end(), c) - h.begin());
+            auto it = std::lower_bound(r1.begin(), r1.end(), c);
+            if (it != r1.end() && *it == c) return nown + (int32_t)(it - r1.begin());
+            return nown + n1 + (int32_t)(std::lower_bound(r2.begin(), r2.end(), c) - r2.begin());
         };
-        for (int64_t el = e0; el < e1; ++el) lcol[el] = (uint16_t)local(P->sl_col[el]);
+        for (int64_t el = e0; el < e1; ++el) L.lcol[el] = (uint16_t)local(P->sl_col[el]);
         for (int64_t rw = lo; rw < hi; ++rw)
             if (P->row_prev[rw] >= 0 && P->row_next[rw] >= 0) {
-                lpn[2 * rw] = local(P->row_prev[rw]);
-                lpn[2 * rw + 1] = local(P->row_next[rw]);
+                L.lpn[2 * rw] = local(P->row_prev[rw]);
+                L.lpn[2 * rw + 1] = local(P->row_next[rw]);
             }
+        std::vector<uint16_t>& rc = L.rcol[g];
+        rc.assign((size_t)n1 * KR, 0);
+        for (int32_t i = 0; i < n1; ++i) {
+            const int32_t c = r1[i];
+            const int64_t sc = c / 64, lane = c % 64;
+            for (int32_t k = 0; k < std::min(P->sl_w[sc], KR); ++k)
+                rc[(size_t)i * KR + k] = (uint16_t)local(P->sl_col[P->sl_ptr[sc] + (int64_t)k * 64 + lane]);
+        }
+        L.n1[g] = n1;
+        std::vector<int32_t>& h = L.halo[g];
+        h = r1;
+        h.insert(h.end(), r2.begin(), r2.end());
+    }
+    for (size_t g = 0; g < G; ++g) {
+        L.rings_ok = L.rings_ok && ok[g];
+        for (int32_t i = 0; i < (int32_t)L.halo[g].size(); ++i)
+            L.expo[L.halo[g][i]] |= (i < L.n1[g]) ? 1 : 2;
     }
 }
 
@@ -1708,11 +2130,10 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     // workgroup's rows and halo
     std::vector<std::pair<int32_t, int32_t>> ranges;
     std::vector<int64_t> range0(K + 1, 0);
-    std::vector<std::vector<int32_t>> halo;
-    std::vector<uint16_t> lcol;
-    std::vector<int32_t> lpn;
-    size_t lds_bytes = 0;
-    int64_t lds_n = 0;
+    LocalNum L;
+    size_t lds_bytes = 0, lds1_bytes = 0;
+    int64_t lds_n = 0, lds_nr = 0, lds_nu = 0;
+    bool cg1 = false;
     if (spw > 0)
         for (int i = 0; i < K; ++i) {
             const int64_t sb = P->row0[i] / 64, ns = (P->row0[i + 1] - P->row0[i]) / 64;
@@ -1721,22 +2142,40 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
                 ranges.emplace_back((int32_t)(sb + ns * t / nw[i]), (int32_t)(sb + ns * (t + 1) / nw[i]));
         }
     if (!cfg.stream) {
-        local_numbering(P, ranges, halo, lcol, lpn);
-        size_t max_nh = 0;
-        for (const auto& h : halo) max_nh = std::max(max_nh, h.size());
+        local_numbering(P, ranges, L);
+        int64_t max_n1 = 0, max_nh = 0;
+        for (size_t g = 0; g < L.halo.size(); ++g) {
+            max_n1 = std::max<int64_t>(max_n1, L.n1[g]);
+            max_nh = std::max<int64_t>(max_nh, (int64_t)L.halo[g].size());
+        }
         int lds_max = 0;
         HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device));
-        // p and the SPAI operand (own rows + halo each), e (own rows)
-        lds_n = (int64_t)cfg.blk * cfg.R + (int64_t)max_nh;
-        lds_bytes = (size_t)(2 * lds_n + (int64_t)cfg.blk * cfg.R) * (prec == 0 ? 16 : 8);
+        const int64_t own = (int64_t)cfg.blk * cfg.R;
+        const size_t vsz = prec == 0 ? 16 : 8;
+        // two-barrier kernel: p and the SPAI operand (own rows + ring 1 each), e (own rows)
+        lds_n = own + max_n1;
+        lds_bytes = (size_t)(2 * lds_n + own) * vsz;
         // local columns are 16-bit; a shape whose workgroup has more entries does not fit
         if (lds_n > 65536 || lds_bytes + 4096 > (size_t)lds_max) return Error{PGCP_OK, ""};
+        // single-reduction kernel: r (own rows + both rings), u (own rows + ring 1), e
+        lds_nr = own + max_nh;
+        lds_nu = own + max_n1;
+        lds1_bytes = (size_t)(lds_nr + lds_nu + own) * vsz;
+        cg1 = L.rings_ok && lds_nr <= 65536 && lds1_bytes + 4096 <= (size_t)lds_max;
     }
     int per_cu = 0;
     const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
                                   : (prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
     const int64_t cap = (int64_t)per_cu * n_cu;
+    int64_t cap1 = 0;
+    if (cg1) {
+        int pc1 = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &pc1, prec == 0 ? pcg1_kernel<double>(cfg.blk, cfg.R) : pcg1_kernel<float>(cfg.blk, cfg.R), cfg.blk,
+            lds1_bytes));
+        cap1 = (int64_t)pc1 * n_cu;
+    }
     if (cfg.stream && cfg.R <= 0) {
         // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
         // in proportion to ns_i^1.5 (its rows times its expected CG iterations,
@@ -1827,6 +2266,10 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     W->n_partials = pb;
     W->lds_bytes = lds_bytes;
     W->lds_n = (int)lds_n;
+    W->cg1 = cg1 && G <= cap1;
+    W->lds1_bytes = lds1_bytes;
+    W->lds_nr = (int)lds_nr;
+    W->lds_nu = (int)lds_nu;
     for (int x = 0; x < n_xcd; ++x) {
         int64_t slot = 0;
         for (int i : on[x]) {
@@ -1840,22 +2283,32 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         }
     }
     // halo entries in workgroup order (register-resident kernel only)
-    std::vector<int32_t> wg_h0(G + 1, 0), hcat;
+    std::vector<int32_t> wg_h0(G + 1, 0), wg_n1(G, 0), hcat;
+    std::vector<uint16_t> rcat;
     for (int64_t g = 0; g < G && !cfg.stream; ++g) {
         if (W->wg_sub[g] >= 0) {
-            const auto& h = halo[range0[W->wg_sub[g]] + W->wg_rank[g]];
+            const int64_t rg = range0[W->wg_sub[g]] + W->wg_rank[g];
+            const auto& h = L.halo[rg];
             hcat.insert(hcat.end(), h.begin(), h.end());
+            wg_n1[g] = L.n1[rg];
+            // KR local columns per halo entry (ring-2 entries unused), indexed like the halo
+            rcat.insert(rcat.end(), L.rcol[rg].begin(), L.rcol[rg].end());
+            rcat.resize(hcat.size() * KR, 0);
         }
-        if (hcat.size() > (size_t)INT32_MAX) return Error{PGCP_E_INVALID, "halo too large for int32 offsets"};
+        if (hcat.size() * KR > (size_t)INT32_MAX) return Error{PGCP_E_INVALID, "halo too large for int32 offsets"};
         wg_h0[g + 1] = (int32_t)hcat.size();
     }
     if (hcat.empty()) hcat.push_back(0);
+    if (rcat.empty()) rcat.push_back(0);
     Error e{PGCP_OK, ""};
     if (!cfg.stream) {
         if ((e = upload(W->d_wg_h0, wg_h0, ctx->stream)).code) return e;
         if ((e = upload(W->d_halo, hcat, ctx->stream)).code) return e;
-        if ((e = upload(W->d_lcol, lcol, ctx->stream)).code) return e;
-        if ((e = upload(W->d_lpn, lpn, ctx->stream)).code) return e;
+        if ((e = upload(W->d_wg_n1, wg_n1, ctx->stream)).code) return e;
+        if ((e = upload(W->d_lcol, L.lcol, ctx->stream)).code) return e;
+        if ((e = upload(W->d_lpn, L.lpn, ctx->stream)).code) return e;
+        if ((e = upload(W->d_rcol, rcat, ctx->stream)).code) return e;
+        if ((e = upload(W->d_expo, L.expo, ctx->stream)).code) return e;
     }
     if ((e = upload(W->d_wg_sub, W->wg_sub, ctx->stream)).code) return e;
     if ((e = upload(W->d_wg_rank, W->wg_rank, ctx->stream)).code) return e;
@@ -1892,6 +2345,12 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.lcol = (const uint16_t*)W.d_lcol.p;
     a.lpn = (const int32_t*)W.d_lpn.p;
     a.lds_n = W.lds_n;
+    a.wg_n1 = (const int32_t*)W.d_wg_n1.p;
+    a.rcol = (const uint16_t*)W.d_rcol.p;
+    a.expo = (const uint8_t*)W.d_expo.p;
+    a.s1 = (V2*)P->d_s1.p;
+    a.lds_nr = W.lds_nr;
+    a.lds_nu = W.lds_nu;
     a.active = (const int32_t*)P->d_active.p;
     a.target_rel2 = (const double*)P->d_target.p;
     a.e = (V2*)P->d_e.p;
@@ -1939,7 +2398,8 @@ static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
 }
 
 static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t* mask, int coupled, int max_iter,
-                        int stall, hipStream_t s, const int32_t* pc = nullptr) {
+                        int stall, hipStream_t s, const int32_t* pc = nullptr, bool single = false) {
+    single = single && W.cg1 && !W.stream;
     dim3 grid(W.n_wg), block(W.blk);
     if (prec) {
         CGArgs<float> a = cg_args<float>(P, W, mask, coupled, max_iter, (const float*)P->d_val32.p,
@@ -1953,6 +2413,9 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
         void* args[] = {&a};
         if (W.stream)
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<float>(W.blk), grid, block, args, 0, s));
+        else if (single)
+            HIPCHK(hipLaunchCooperativeKernel(pcg1_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
+                                              W.lds1_bytes, s));
         else
             HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<float>(W.blk, W.rows_per_thread), grid, block, args,
                                               W.lds_bytes, s));
@@ -1968,6 +2431,9 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
         void* args[] = {&a};
         if (W.stream)
             HIPCHK(hipLaunchCooperativeKernel(pcg_stream_kernel<double>(W.blk), grid, block, args, 0, s));
+        else if (single)
+            HIPCHK(hipLaunchCooperativeKernel(pcg1_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
+                                              W.lds1_bytes, s));
         else
             HIPCHK(hipLaunchCooperativeKernel(pcg_kernel<double>(W.blk, W.rows_per_thread), grid, block, args,
                                               W.lds_bytes, s));
@@ -2145,6 +2611,12 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     }
     Error e{PGCP_OK, ""};
     const WorkMap& W = prec ? P->wmap32 : P->wmap64;
+    // two-barrier kernel unless PGCP_PCG_KERNEL=single (the single-reduction
+    // kernel measured slower on C2 and drifts at tight tolerances); a pass whose
+    // pieces break down or stagnate with it is repeated with the two-barrier kernel
+    const char* kv = getenv("PGCP_PCG_KERNEL");
+    bool single = kv && std::strcmp(kv, "single") == 0;
+    bool used_single = false;
 
     std::vector<double> bnorm(2 * K, 0.0), rnorm(2 * K, 0.0), scale(2 * K, 0.0), target(2 * K, 0.0);
     std::vector<int32_t> active(K, 0), iters(K, 0), status(K, 0), it_total(K, 0), fail(K, 0);
@@ -2224,9 +2696,11 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         if ((e = prep_inner(P, prec, s)).code) return e;
         HIPCHK(hipEventRecord(P->ev0, s));
         if (learned) HIPCHK(hipMemcpyAsync(P->d_pc.p, pc.data(), K * 4, hipMemcpyHostToDevice, s));
+        const bool this_single = single && W.cg1 && !W.stream;
         if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s,
-                            learned ? (const int32_t*)P->d_pc.p : nullptr)).code)
+                            learned ? (const int32_t*)P->d_pc.p : nullptr, this_single)).code)
             return e;
+        used_single = this_single;
         HIPCHK(hipEventRecord(P->ev1, s));
         if (prec) {
             k_apply_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
@@ -2259,6 +2733,20 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
                 }
             fprintf(stderr, "[pgcp]   cg launch %.2f ms, max iters %d, status ok/brk/maxit/abort/stall %d/%d/%d/%d/%d\n",
                     ms, mx, nst[0], nst[1], nst[2], nst[3], nst[4]);
+        }
+        bool bad = false;
+        for (int i = 0; i < K; ++i)
+            if (active[i] && (status[i] == 1 || status[i] == 4)) bad = true;
+        if (this_single && bad) {
+            // repeat with the two-barrier kernel (the residual is recomputed first)
+            single = false;
+            for (int i = 0; i < K; ++i) {
+                if (!active[i]) continue;
+                it_total[i] += iters[i];
+                total += iters[i];
+                cg_bytes += iters[i] * iter_bytes(i);
+            }
+            continue;
         }
         for (int i = 0; i < K; ++i) {
             if (!active[i]) continue;
@@ -2299,6 +2787,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         st->cg_block = W.blk;
         st->cg_stream = W.stream;
         st->n_fallback = n_fallback;
+        st->cg_single = used_single ? 1 : 0;
     }
     if (noconv) return Error{PGCP_E_NOCONV, "some piece missed the residual tolerance"};
     return Error{PGCP_OK, ""};

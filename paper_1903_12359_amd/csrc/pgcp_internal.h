@@ -43,8 +43,12 @@ struct WorkMap {
     DevBuf d_wg_sub, d_wg_rank, d_wg_s0, d_wg_s1, d_sub_pbase, d_sub_nwg;
     // register-resident kernel: local numbering of each workgroup's rows and halo
     size_t lds_bytes = 0;        // dynamic LDS per workgroup
-    int lds_n = 0;               // LDS entries of one vector: own rows + largest halo
-    DevBuf d_wg_h0, d_halo, d_lcol, d_lpn;
+    int lds_n = 0;               // LDS entries of one vector: own rows + largest ring 1
+    DevBuf d_wg_h0, d_halo, d_lcol, d_lpn, d_wg_n1, d_rcol, d_expo;
+    // single-reduction kernel (both rings): usable, its LDS and vector sizes
+    bool cg1 = false;
+    size_t lds1_bytes = 0;
+    int lds_nr = 0, lds_nu = 0;
 };
 
 }  // namespace pgcp
@@ -98,7 +102,7 @@ struct pgcp_part {
     pgcp::DevBuf d_chart;                     // [3K] doubles: sphere chart centre (re, im, is-infinity)
 
     // ---------------- solver work space
-    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q, d_r2;
+    pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q, d_r2, d_s1;
     pgcp::DevBuf d_partial, d_bar, d_gen, d_res, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;

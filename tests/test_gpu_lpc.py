@@ -212,11 +212,15 @@ def test_learned_solves_reach_the_oracle(ctx, prec, tol, bound):
     assert err <= bound
 
 
-@pytest.mark.parametrize("cfg", ["256,2", "256,2,1"])
-def test_learned_solve_both_kernels(ctx, cfg, monkeypatch):
-    """The SPAI apply in the register-resident and in the streaming kernel, pieces over several workgroups."""
+@pytest.mark.parametrize("cfg,kernel", [("256,2", "single"), ("256,2", "two"), ("256,2,1", "stream")])
+def test_learned_solve_both_kernels(ctx, cfg, kernel, monkeypatch):
+    """The SPAI apply in the single-reduction kernel (M applied on the own rows
+    and ring 1 from residuals rebuilt on two rings), the two-barrier kernel and
+    the streaming kernel, pieces over several workgroups."""
     import paper_1903_12359_amd as pg
     monkeypatch.setenv("PGCP_PCG_CFG", cfg)
+    if kernel == "single":
+        monkeypatch.setenv("PGCP_PCG_KERNEL", "single")
     case = small_grid_case(96, 2, 2, seed=8, jitter=0.3)
     part, subs = prepare(case.V, case.F, case.label)
     ob = np.concatenate(local_params(subs))
@@ -225,9 +229,10 @@ def test_learned_solve_both_kernels(ctx, cfg, monkeypatch):
     net = pg.LPC(ctx, random_params(4) * 0.5)
     b, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13, lpc=net)
     assert rep.cg_workgroups > plan.K
+    assert rep.cg_single == (1 if kernel == "single" else 0)
     g = b.cpu().numpy()
     err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
-    say("kernel", cfg, "err", err, "iters", rep.total_iters)
+    say("kernel", cfg, kernel, "err", err, "iters", rep.total_iters)
     assert err <= 1e-9
 
 

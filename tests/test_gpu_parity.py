@@ -223,6 +223,41 @@ def test_forced_launch_shapes(ctx, cfg, monkeypatch):
     assert np.array_equal(b2.cpu().numpy(), g)
 
 
+@pytest.mark.parametrize("kernel", ["single", "two"])
+@pytest.mark.parametrize("system", ["dncp", "harmonic"])
+def test_pcg_kernels_match_oracle(ctx, kernel, system, monkeypatch):
+    """The single-reduction kernel (one per-piece barrier per iteration, rings
+    of rebuilt residuals) and the two-barrier kernel, on pieces spread over
+    several workgroups, give the oracle's answer; which one ran is reported."""
+    import paper_1903_12359_amd as pg
+    if kernel == "single":
+        monkeypatch.setenv("PGCP_PCG_KERNEL", "single")
+    monkeypatch.setenv("PGCP_PCG_CFG", "256,1")
+    case = case_c2(n=160)
+    say("pcg kernel", kernel, system)
+    part, subs, bdy_o, welded = _oracle_stages(case)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    if system == "dncp":
+        b, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13)
+        g = b.cpu().numpy()
+        ob = np.concatenate(bdy_o)
+        err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+    else:
+        seam = plan.export()["seam_gv"]
+        wz = np.array([welded[int(v)] for v in seam])
+        phi, rep = pg.harmonic_solve(ctx, plan, _dev(np.column_stack([wz.real, wz.imag])), precision="fp64",
+                                     tol=1e-13)
+        vals, _ = harmonic_all(subs, welded, case.mode)
+        from oracle.pipeline import assemble
+        phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+        err = np.abs(phi.cpu().numpy() - phi_o).max() / np.abs(phi_o).max()
+    say("  workgroups", rep.cg_workgroups, "single", rep.cg_single, "iters", int(rep.iters.max()), "err", err)
+    assert rep.cg_workgroups > plan.K          # pieces span several workgroups
+    assert rep.cg_single == (1 if kernel == "single" else 0)
+    assert err <= 1e-9
+
+
 def test_c2_full_size_stagewise(ctx):
     """C2 at full size (512^2 vertices, 16 pieces): DNCP and harmonic against the oracle."""
     import paper_1903_12359_amd as pg
