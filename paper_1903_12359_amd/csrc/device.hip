@@ -618,8 +618,15 @@ __device__ __forceinline__ void lds_spmv(const uint16_t* __restrict__ lcol, cons
     }
 }
 
+// 256-thread workgroups are asked to fit two per CU (two waves per SIMD): the
+// register budget that lets a 1024-row workgroup shape hold C2-sized batches
+// in one cooperative grid.
+template <int BLK>
+constexpr int pcg_waves_per_eu() { return BLK == 256 ? 2 : BLK / 256; }
+
 template <typename T, int BLK, int R>
-__global__ void __launch_bounds__(BLK) k_pcg(CGArgs<T> a) {
+__global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(pcg_waves_per_eu<BLK>())))
+k_pcg(CGArgs<T> a) {
     using V2 = typename Vec2<T>::type;
     constexpr int NW = BLK / 64;
     extern __shared__ unsigned char smem_raw[];

@@ -17,6 +17,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -379,6 +382,14 @@ Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double*
     auto release = [&]() {
         for (DevBuf* b : {&zt, &ztmp, &recb, &descb, &ptsb, &sslot, &sval}) dev_free(*b);
     };
+    const char* vb = getenv("PGCP_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
+    auto now = [] { return std::chrono::steady_clock::now(); };
+    auto ms = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const auto t_start = now();
+    double t_arcs = 0.0;
     try {
         std::vector<int32_t> slot_of(P->nv, -1);
         for (int64_t t = 0; t < ns; ++t) slot_of[P->seam_gv[t]] = (int32_t)t;
@@ -410,6 +421,7 @@ Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double*
             const bool closed = P->mode == PGCP_SPHERE && r == nrounds - 1;
             std::vector<Job> jobs(rnd.size());
             std::vector<Error> errs(rnd.size(), Error{PGCP_OK, ""});
+            const auto t_r0 = now();
 #pragma omp parallel for schedule(dynamic) if (rnd.size() > 1)
             for (size_t t = 0; t < rnd.size(); ++t) {
                 try {
@@ -420,6 +432,13 @@ Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double*
             }
             for (auto& er : errs)
                 if (er.code != PGCP_OK) throw er;
+            t_arcs += ms(t_r0, now());
+            if (verbose) {
+                size_t kmax = 0;
+                for (const Job& J : jobs) kmax = std::max(kmax, J.arc_slot.size());
+                fprintf(stderr, "[pgcp] weld round %d: %zu pairs, longest arc %zu points, arcs %.2f ms\n", r,
+                        rnd.size(), kmax, ms(t_r0, now()));
+            }
             // pack the records and the point list of the round
             std::vector<double> rec;
             std::vector<PairDesc> desc(rnd.size());
@@ -552,7 +571,11 @@ Error weld_all_device(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv, double*
         HIPTHROW(hipMemcpyAsync(welded_uv, zt.p, (size_t)ns * 16, hipMemcpyDeviceToHost, s));
         HIPTHROW(hipStreamSynchronize(s));
         P->welded = true;
+        const auto t_rel = now();
         release();
+        if (verbose)
+            fprintf(stderr, "[pgcp] weld total %.2f ms (host arcs %.2f ms, buffer release %.2f ms)\n",
+                    ms(t_start, now()), t_arcs, ms(t_rel, now()));
         return Error{PGCP_OK, ""};
     } catch (const Error& er) {
         release();
