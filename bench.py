@@ -50,9 +50,9 @@ HBM_PEAK_GBS = 8000.0
 # summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
 TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "8e47207068a84aff863a70bf5d5b787e08470339b3727aa8027656433ff6e394",
-           "pcg_shapes": {"dncp": "512,4,0", "harmonic": "256,4,0"},
-           "bytes_per_launch": 4.679e9},
+           "source_sha256": "186c907551bd01abc4d1e65c64590847588414c2b8ee778771b1c0c07b0662d8",
+           "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "512,4,0,0"},
+           "bytes_per_launch": 8.691e9},
 }
 
 
