@@ -1,7 +1,7 @@
 """PGCP hot-path benchmark on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--precision fp32|fp64] [--workload c2|c1|c3|c5]
-                    [--precond both|jacobi|learned] [--lpc-steps S] [--no-pipeline]
+                    [--precond both|jacobi|learned] [--lpc-steps S] [--lanes N] [--no-pipeline]
 
 One step is Algorithm 3 end to end on one synthetic mesh already resident in
 device memory (V, F; labels and the host copy of the connectivity for the
@@ -11,11 +11,14 @@ partition): partition + plan upload, cotangent assembly, DNCP of every piece
 reaches an FP64 relative residual of 1e-10 (per piece; per coordinate for the
 harmonic solve).  Prints one JSON line.
 
-The steps run as a stream (pg.run_stream): while the device works on one step,
-a host thread partitions the mesh of the next one, as a service that processes
-a stream of meshes would.  Every step still runs every stage; `value` is the
-throughput of the stream, and "sequential" reports a few steps run one after
-the other (the latency of a single mesh).  --no-pipeline times the latter only.
+The steps run as a stream (pg.run_stream), as a service that processes a
+stream of meshes would: --lanes N meshes are in flight, each on a host thread
+with its own context and stream, so that the host stages of one (partition,
+weld) overlap the device solves of another; the batched solves themselves take
+the whole device and run one at a time.  Every step still runs every stage;
+`value` is the throughput of the stream, and "sequential" reports a few steps
+run one after the other on one context (the latency of a single mesh).
+--no-pipeline times the latter only.
 
 The step is timed twice on the same GPU: with Jacobi-PCG, and with the learned
 SPAI preconditioner (network inference inside the step).  The network is
@@ -114,9 +117,8 @@ def train_lpc(ctx, steps, seed=0):
 
 def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, steps=None, pipeline=True):
     """Time `steps` complete steps on the same mesh.  With pipeline=True the steps
-    run through pg.run_stream, which partitions the next mesh on the host while
-    the device works on the current one (every step still runs every stage);
-    otherwise one step after the other."""
+    run through pg.run_stream with --lanes meshes in flight (every step still
+    runs every stage); otherwise one step after the other on one context."""
     import torch
     steps = args.steps if steps is None else steps
     kw = dict(precision=args.precision, tol=args.tol, lpc=lpc)
@@ -124,7 +126,7 @@ def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, steps=None, pipeline=Tr
 
     def steps_iter(n):
         if pipeline:
-            yield from pg.run_stream(ctx, [item] * n, **kw)
+            yield from pg.run_stream(ctx, [item] * n, lanes=args.lanes, **kw)
         else:
             for _ in range(n):
                 times = {}
@@ -171,6 +173,8 @@ def main():
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
     ap.add_argument("--lpc-steps", type=int, default=400, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanes", type=int, default=2, help="meshes in flight in the stream (1: the host partition "
+                    "of the next mesh overlaps the current one only)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="run the steps one after the other (no host partition of the next step during device work)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -243,6 +247,7 @@ def main():
                      "cg_iterations_per_step": head["iters"]},
         "stages_ms": head["stage"],
         "pipelined": not args.no_pipeline,
+        "lanes": args.lanes if not args.no_pipeline else 1,
         "quality": {"mean_abs_d_deg": st["mean_abs_d"], "max_mu": st["max_mu"], "n_flipped": st["n_flipped"],
                     "dncp_max_relres": float(info["dncp"].relres.max()),
                     "harmonic_max_relres": float(info["harmonic"].relres.max())},

@@ -176,6 +176,9 @@ class Context:
             raise PGCPError(rc, msg.decode() if msg else "")
 
     def close(self):
+        for lc in getattr(self, "_lane_ctxs", []):
+            lc.close()
+        self._lane_ctxs = []
         if getattr(self, "h", None):
             self.lib.pgcp_ctx_destroy(self.h)
             self.h = None
@@ -411,19 +414,32 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
     return out, d, mu, flip
 
 
-def run_stream(ctx: Context, cases, **kw):
+def run_stream(ctx: Context, cases, lanes: int = 1, **kw):
     """Algorithm 3 over a sequence of meshes, overlapping host and device work.
 
     `cases` is an iterable of dicts with keys V, F, label and optionally mode,
-    V_dev, F_dev.  While the device runs the stages of one mesh, a worker
-    thread partitions the next one on the host (pgcp_partition releases the
-    interpreter lock; its plan upload is ordered on the context's stream), so
-    the host partition is hidden behind device work.  Every mesh still goes
-    through every stage.  Yields run()'s (phi_dev, dist_stats, reports) per
-    mesh; reports["times"]["partition"] is the time spent waiting for the
-    prefetched plan and ["partition_overlapped"] the worker's partition time.
-    Remaining keyword arguments go to run().
+    V_dev, F_dev (the device copies must be complete before the call).  Every
+    mesh goes through every stage; yields run()'s (phi_dev, dist_stats,
+    reports) per mesh, in input order.  Remaining keyword arguments go to run().
+
+    lanes=1: while the device runs the stages of one mesh, a worker thread
+    partitions the next one on the host (pgcp_partition releases the
+    interpreter lock; its plan upload is ordered on the context's stream).
+    reports["times"]["partition"] is the time spent waiting for the prefetched
+    plan and ["partition_overlapped"] the worker's partition time.
+
+    lanes=n>1: n meshes are in flight.  A worker thread partitions meshes (up
+    to n + 1 ahead) on a context of its own; each lane is a host thread with a
+    context of its own on a stream of its own (all kept on `ctx` for later
+    calls) that takes the next plan and runs the stages.  The library runs one
+    batched-CG kernel at a time on a device (they take the whole device); the
+    partition, a lane's weld and solve host steps, and its other kernels
+    overlap the solves of the other lanes.  phi_dev is on the lane's stream,
+    which has finished with it when it is yielded.
     """
+    if lanes > 1:
+        yield from _run_lanes(ctx, cases, lanes, kw)
+        return
     from concurrent.futures import ThreadPoolExecutor
 
     def build(c):
@@ -451,6 +467,78 @@ def run_stream(ctx: Context, cases, **kw):
             times["partition"] = wait
             times["partition_overlapped"] = t_build
             yield out
+
+
+def _run_lanes(ctx: Context, cases, lanes: int, kw):
+    import threading
+    from collections import deque
+
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    pool = getattr(ctx, "_lane_ctxs", None)
+    if pool is None:
+        pool = ctx._lane_ctxs = []
+    while len(pool) < lanes + 1:
+        pool.append(Context(ctx.device, torch.cuda.Stream(ctx.device)))
+    part_ctx = pool[lanes]            # the partition worker's context (plan uploads)
+    free = list(pool[:lanes])
+    free_lock = threading.Lock()
+    torch.cuda.current_stream(ctx.device).synchronize()   # inputs made on the caller's stream
+
+    def build(c):
+        t = time.perf_counter()
+        p = Plan(part_ctx, c["V"], c["F"], c["label"], c.get("mode", "free"))   # upload finished on return
+        return p, time.perf_counter() - t
+
+    def work(c, pf):
+        with free_lock:
+            lc = free.pop()
+        try:
+            t = time.perf_counter()
+            plan, t_build = pf.result()
+            wait = time.perf_counter() - t
+            with torch.cuda.stream(lc.stream):
+                times = {}
+                try:
+                    out = run(lc, c["V"], c["F"], c["label"], c.get("mode", "free"), V_dev=c.get("V_dev"),
+                              F_dev=c.get("F_dev"), plan=plan, times=times, **kw)
+                finally:
+                    plan.close()
+                times["partition"] = wait
+                times["partition_overlapped"] = t_build
+                return out
+        finally:
+            with free_lock:
+                free.append(lc)
+
+    it = iter(cases)
+    plans, running = deque(), deque()
+    with ThreadPoolExecutor(max_workers=1) as pex, ThreadPoolExecutor(max_workers=lanes) as lex:
+        def fill():
+            # partitions run up to lanes + 1 meshes ahead of the lanes
+            while len(plans) + len(running) < 2 * lanes + 1:
+                c = next(it, None)
+                if c is None:
+                    break
+                plans.append((c, pex.submit(build, c)))
+            while plans and len(running) < lanes:
+                c, pf = plans.popleft()
+                running.append(lex.submit(work, c, pf))
+
+        try:
+            fill()
+            while running:
+                out = running.popleft().result()
+                fill()
+                yield out
+        finally:
+            for _, pf in plans:   # plans built for meshes that were not run
+                if pf.cancel():
+                    continue
+                try:
+                    pf.result()[0].close()
+                except Exception:
+                    pass
 
 
 def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,

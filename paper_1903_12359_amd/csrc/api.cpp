@@ -37,6 +37,13 @@ pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream) {
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    // keep released pool memory for reuse instead of returning it at every
+    // synchronisation (plans of a stream of meshes reuse the same sizes)
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, hip_device) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
     *out = c;
     return PGCP_OK;
 }
@@ -64,12 +71,15 @@ pgcp_status pgcp_partition(pgcp_ctx* ctx, const double* V, int64_t nv, const int
         e = Error{PGCP_E_NOMEM, "out of host memory"};
     }
     if (e.code == PGCP_OK && ctx) {
+        P->stream = ctx->stream;
+        pgcp::AllocScope scope(ctx->stream);
         if (hipSetDevice(ctx->device) != hipSuccess) e = Error{PGCP_E_HIP, "hipSetDevice failed"};
         else e = pgcp::upload_plan(ctx, P);
         if (e.code == PGCP_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
             e = Error{PGCP_E_HIP, "plan upload failed"};
     }
     if (e.code != PGCP_OK) {
+        pgcp::AllocScope scope(P->stream);
         pgcp::free_part_device(P);
         delete P;
         if (!ctx) return e.code;
@@ -109,6 +119,7 @@ pgcp_status pgcp_part_export(const pgcp_part* P, int32_t* face_sub, int32_t* sub
 
 void pgcp_part_destroy(pgcp_part* P) {
     if (!P) return;
+    pgcp::AllocScope scope(P->stream);
     pgcp::free_part_device(P);
     delete P;
 }
@@ -116,6 +127,8 @@ void pgcp_part_destroy(pgcp_part* P) {
 pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev) {
     if (!ctx || !P || !V_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     return fail(ctx, pgcp::launch_assemble(ctx, P, V_dev));
 }
 
@@ -123,6 +136,8 @@ pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts*
                              pgcp_solve_stats* stats) {
     if (!ctx || !P || !bdy_uv_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     double t0 = now();
     if (!P->assembled) return bad(ctx, "pgcp_assemble_cotan has not run");
     Error e = pgcp::assembled_ok(ctx, P);
@@ -136,7 +151,11 @@ pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts*
 
 pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv_host, double* welded_uv_host) {
     if (!P || !bdy_uv_host || !welded_uv_host) return bad(ctx, "null argument");
-    if (ctx && !P->host_only) return fail(ctx, pgcp::weld_all_device(ctx, P, bdy_uv_host, welded_uv_host));
+    if (ctx && !P->host_only) {
+        pgcp::AllocScope scope(ctx->stream);
+        P->stream = ctx->stream;
+        return fail(ctx, pgcp::weld_all_device(ctx, P, bdy_uv_host, welded_uv_host));
+    }
     return fail(ctx, pgcp::weld_all(P, bdy_uv_host, welded_uv_host));
 }
 
@@ -145,6 +164,7 @@ pgcp_status pgcp_laplacian_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t pie
     if (!ctx || !P || !rowptr) return bad(ctx, "null argument");
     if (P->host_only || !P->assembled) return bad(ctx, "plan has no assembled device matrix");
     if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
+    pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::export_laplacian(ctx, P, piece, rowptr, col, val));
 }
 
@@ -152,6 +172,8 @@ pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* P, const double* welde
                                 const pgcp_solve_opts* opts, double* out_dev, pgcp_solve_stats* stats) {
     if (!ctx || !P || !welded_uv_dev || !out_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     double t0 = now();
     Error e = pgcp::run_harmonic(ctx, P, welded_uv_dev, opts, out_dev, stats);
     if (stats) {
@@ -167,6 +189,7 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, cons
     if (!ctx || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
     if (dim != 2 && dim != 3) return bad(ctx, "dim must be 2 or 3");
     if (nf <= 0 || nv <= 0) return bad(ctx, "empty mesh");
+    pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::run_distortion(ctx, V_dev, nv, F_dev, nf, param_dev, dim, d_dev, mu_dev, flip_dev,
                                           want_quantiles, stats));
 }
@@ -180,19 +203,28 @@ int64_t pgcp_lpc_num_params(void) { return pgcp::lpc_num_params(); }
 pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** out) {
     if (!ctx || !out) return bad(ctx, "null argument");
     *out = nullptr;
+    pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::lpc_create(ctx, params_host, out));
 }
 
 pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* params_host) {
     if (!ctx || !lpc || !params_host) return bad(ctx, "null argument");
+    pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::lpc_get_params(ctx, lpc, params_host));
 }
 
-void pgcp_lpc_destroy(pgcp_lpc* lpc) { pgcp::lpc_destroy(lpc); }
+void pgcp_lpc_destroy(pgcp_lpc* lpc) {
+    if (!lpc) return;
+    // the network may be read by several contexts' streams: let all of them finish
+    (void)hipDeviceSynchronize();
+    pgcp::lpc_destroy(lpc);
+}
 
 pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* lpc, int32_t system) {
     if (!ctx || !P || !lpc) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     return fail(ctx, pgcp::lpc_infer(ctx, P, lpc, system));
 }
 
@@ -201,6 +233,7 @@ pgcp_status pgcp_lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, do
     if (!ctx || !P) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
+    pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::lpc_export(ctx, P, piece, o_off, o_diag, m_off, m_diag));
 }
 
@@ -208,6 +241,8 @@ pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t sy
                           int32_t n_probes, double* loss, float* grad_host) {
     if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     return fail(ctx, pgcp::lpc_grad(ctx, P, lpc, system, probes_dev, n_probes, loss, grad_host, 0, 0.f));
 }
 
@@ -216,6 +251,8 @@ pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int3
     if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     if (!(lr > 0.f)) return bad(ctx, "learning rate must be positive");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
     return fail(ctx, pgcp::lpc_grad(ctx, P, lpc, system, probes_dev, n_probes, loss, nullptr, 1, lr));
 }
 

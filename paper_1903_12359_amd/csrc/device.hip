@@ -37,6 +37,8 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include <hipcub/hipcub.hpp>
@@ -2470,8 +2472,22 @@ static Error stream_fit(pgcp_ctx* ctx, pgcp_part* P, int prec, int blk, int* R) 
 // precision) or PGCP_PCG_CFG = "blk,R" (register-resident) or "blk,R,1"
 // (streaming; R = 0: size-weighted map) forces one; otherwise every shape that
 // fits is timed (best of two 40-iteration probes) on the real batch the first
-// time a context solves a batch of that shape, and the fastest is kept.  The streaming
-// kernel is tried with the fewest and twice the fewest slices per wave that fit.
+// time a batch of that shape is solved on the device, and the fastest is kept
+// for every context on that device (contexts that solve side by side share
+// it).  The streaming kernel is tried with the fewest and twice the fewest
+// slices per wave that fit.
+static std::mutex g_tuned_mu;
+
+// A batched-CG launch needs every workgroup resident at once and sized for
+// the whole device, so two of them must not share it: contexts that solve
+// side by side on their own streams take this lock from the launch to the
+// kernel's end (their other kernels run freely around it).
+static std::mutex& coop_mutex(int device) {
+    static std::mutex mu[16];
+    return mu[(unsigned)device % 16];
+}
+static std::map<std::string, std::array<int, 3>> g_tuned;   // {threads per workgroup, slices per wave, streaming}
+
 static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t* mask, int coupled) {
     WorkMap& W = prec ? P->wmap32 : P->wmap64;
     if (W.n_wg > 0) return Error{PGCP_OK, ""};
@@ -2487,12 +2503,22 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             if (fits) return Error{PGCP_OK, ""};
         }
     }
-    std::string key = std::to_string(prec) + ":" + std::to_string(coupled) + ":" + std::to_string(P->K);
+    std::string key = std::to_string(ctx->device) + "/" + std::to_string(prec) + ":" + std::to_string(coupled) +
+                      ":" + std::to_string(P->K);
     for (int i = 0; i < P->K; ++i) key += "," + std::to_string((P->row0[i + 1] - P->row0[i]) / 64);
-    auto hit = ctx->tuned.find(key);
-    if (hit != ctx->tuned.end()) {
+    bool known = false;
+    std::array<int, 3> shape{};
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        auto hit = g_tuned.find(key);
+        if (hit != g_tuned.end()) {
+            known = true;
+            shape = hit->second;
+        }
+    }
+    if (known) {
         bool fits;
-        Error e = build_workmap(ctx, P, prec, PcgCfg{hit->second[0], hit->second[1], hit->second[2]}, &W, &fits);
+        Error e = build_workmap(ctx, P, prec, PcgCfg{shape[0], shape[1], shape[2]}, &W, &fits);
         if (e.code) return e;
         if (fits) return Error{PGCP_OK, ""};
     }
@@ -2551,10 +2577,13 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
         float ms = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {   // best of two probes
             if ((e = prep_inner(P, prec, s)).code) return e;
-            HIPCHK(hipEventRecord(P->ev0, s));
-            if ((e = launch_pcg(P, T, prec, mask, coupled, probe_iters, 1 << 30, s)).code) return e;
-            HIPCHK(hipEventRecord(P->ev1, s));
-            HIPCHK(hipEventSynchronize(P->ev1));
+            {
+                std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
+                HIPCHK(hipEventRecord(P->ev0, s));
+                if ((e = launch_pcg(P, T, prec, mask, coupled, probe_iters, 1 << 30, s)).code) return e;
+                HIPCHK(hipEventRecord(P->ev1, s));
+                HIPCHK(hipEventSynchronize(P->ev1));
+            }
             float m1 = 0.f;
             HIPCHK(hipEventElapsedTime(&m1, P->ev0, P->ev1));
             int ab = 0;
@@ -2576,7 +2605,10 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     bool fits;
     Error e = build_workmap(ctx, P, prec, best, &W, &fits);
     if (e.code) return e;
-    ctx->tuned[key] = {best.blk, best.R, best.stream};
+    {
+        std::lock_guard<std::mutex> g(g_tuned_mu);
+        g_tuned[key] = {best.blk, best.R, best.stream};
+    }
     return Error{PGCP_OK, ""};
 }
 
@@ -2701,14 +2733,18 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         // launch shape: chosen once per plan and precision, on this residual
         if ((e = choose_workmap(ctx, P, prec, mask, coupled)).code) return e;
         if ((e = prep_inner(P, prec, s)).code) return e;
-        HIPCHK(hipEventRecord(P->ev0, s));
         if (learned) HIPCHK(hipMemcpyAsync(P->d_pc.p, pc.data(), K * 4, hipMemcpyHostToDevice, s));
         const bool this_single = single && W.cg1 && !W.stream;
-        if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s,
-                            learned ? (const int32_t*)P->d_pc.p : nullptr, this_single)).code)
-            return e;
+        {
+            std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
+            HIPCHK(hipEventRecord(P->ev0, s));
+            if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s,
+                                learned ? (const int32_t*)P->d_pc.p : nullptr, this_single)).code)
+                return e;
+            HIPCHK(hipEventRecord(P->ev1, s));
+            HIPCHK(hipEventSynchronize(P->ev1));
+        }
         used_single = this_single;
-        HIPCHK(hipEventRecord(P->ev1, s));
         if (prec) {
             k_apply_inner<float><<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const int32_t*)P->d_slice_sub.p,
                                                                    (const int32_t*)P->d_active.p,

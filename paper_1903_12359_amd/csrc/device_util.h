@@ -24,21 +24,29 @@ constexpr long long SPIN_MAX = 1ll << 24;
 
 // ----------------------------------------------------------------- buffers
 
-inline Error dev_alloc(DevBuf& b, size_t bytes) {
-    if (b.bytes >= bytes && b.p) return Error{PGCP_OK, ""};
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
-    if (bytes == 0) bytes = 16;
-    HIPCHK(hipMalloc(&b.p, bytes));
-    b.bytes = bytes;
-    return Error{PGCP_OK, ""};
+// Releases a buffer: pooled ones in the order of the calling scope's stream
+// (else the stream they were made on), others with hipFree.
+inline void dev_free(DevBuf& b) {
+    if (b.p) {
+        if (b.pooled) (void)hipFreeAsync(b.p, tls_alloc_set ? tls_alloc_stream : b.s);
+        else (void)hipFree(b.p);
+    }
+    b = DevBuf{};
 }
 
-inline void dev_free(DevBuf& b) {
-    if (b.p) (void)hipFree(b.p);
-    b.p = nullptr;
-    b.bytes = 0;
+inline Error dev_alloc(DevBuf& b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return Error{PGCP_OK, ""};
+    dev_free(b);
+    if (bytes == 0) bytes = 16;
+    if (tls_alloc_set) {
+        HIPCHK(hipMallocAsync(&b.p, bytes, tls_alloc_stream));
+        b.s = tls_alloc_stream;
+        b.pooled = true;
+    } else {
+        HIPCHK(hipMalloc(&b.p, bytes));
+    }
+    b.bytes = bytes;
+    return Error{PGCP_OK, ""};
 }
 
 template <typename T>

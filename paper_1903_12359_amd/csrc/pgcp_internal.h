@@ -23,10 +23,36 @@ struct Error {
     std::string msg;
 };
 
-// Device buffer owned by a plan or context.
+// Device buffer owned by a plan or context.  Buffers made inside a context's
+// call come from the device's stream-ordered pool (hipMallocAsync on the
+// context's stream) and go back to it with hipFreeAsync, so neither waits for
+// work on other streams: a plain hipFree waits for the whole device, which
+// would serialise contexts that run meshes side by side on their own streams.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    hipStream_t s = nullptr;   // stream of the allocation (pooled buffers)
+    bool pooled = false;
+};
+
+// Stream that the calling thread's allocations and releases are ordered on;
+// set for the duration of an entry point from the context (or plan) it works on.
+inline thread_local bool tls_alloc_set = false;
+inline thread_local hipStream_t tls_alloc_stream = nullptr;
+
+struct AllocScope {
+    bool prev_set;
+    hipStream_t prev;
+    explicit AllocScope(hipStream_t s) : prev_set(tls_alloc_set), prev(tls_alloc_stream) {
+        tls_alloc_set = true;
+        tls_alloc_stream = s;
+    }
+    ~AllocScope() {
+        tls_alloc_set = prev_set;
+        tls_alloc_stream = prev;
+    }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
 };
 
 // A device-side work assignment for the persistent batched CG: each workgroup
@@ -59,9 +85,6 @@ struct pgcp_ctx {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     std::string last_error;
-    // autotuned batched-CG launch shapes, keyed by precision, system kind and
-    // the per-piece slice counts of the plan: (threads per workgroup, slices per wave)
-    std::map<std::string, std::array<int, 3>> tuned;   // {threads per workgroup, slices per wave, streaming}
 };
 
 struct pgcp_part {
@@ -115,6 +138,7 @@ struct pgcp_part {
     pgcp::DevBuf d_lpc_av, d_lpc_R, d_lpc_sp, d_lpc_piece, d_lpc_c, d_lpc_goe, d_lpc_gov;
     pgcp::DevBuf d_lpc_dh, d_lpc_dhown, d_lpc_de0, d_lpc_de1, d_lpc_dx, d_pc;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t stream = nullptr;   // stream of the context that last worked on the plan
 
     bool assembled = false;
     bool welded = false;

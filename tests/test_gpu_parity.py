@@ -321,12 +321,17 @@ def _sigma(z):
     return np.column_stack([2 * z.real, -2 * z.imag, r2 - 1]) / (r2 + 1)[:, None]
 
 
+@pytest.mark.parametrize("zip_path", ["device", "lds", "host"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_device_weld_matches_oracle_and_host(ctx, name):
-    """The weld with the point replay on the GPU against the oracle's weld and the host-only weld."""
+def test_device_weld_matches_oracle_and_host(ctx, name, zip_path, monkeypatch):
+    """The weld with the point replay on the GPU against the oracle's weld and the
+    host-only weld: with the zipper and closing of the arcs on the device (points
+    in registers, or forced into LDS as for the longest arcs), or on the host."""
     import paper_1903_12359_amd as pg
+    if zip_path != "device":
+        monkeypatch.setenv("PGCP_ZIP", zip_path)
     case = CASES[name]()
-    say("device weld", name)
+    say("device weld", name, zip_path)
     part, subs = prepare(case.V, case.F, case.label)
     bdy = local_params(subs)
     wo = oracle_weld([s["loop"] for s in subs], bdy, case.mode, sizes=[len(s["T"]) for s in subs])
@@ -371,3 +376,31 @@ def test_run_stream_matches_run(ctx, name):
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
         assert st["n_flipped"] == st0["n_flipped"]
         assert info["times"]["partition_overlapped"] > 0.0
+
+
+@pytest.mark.parametrize("lanes", [2, 3])
+def test_run_stream_lanes_match_run(ctx, lanes):
+    """With several meshes in flight (one context and stream per lane, the
+    batched solves serialised), every mesh of a mixed stream gives what one run
+    of it gives, in input order, with and without the learned preconditioner."""
+    import torch
+    import paper_1903_12359_amd as pg
+    names = ["g33_3x3_jit", "S3_k6", "g33_3x3_jit", "S3_k6", "g33_3x3_jit"]
+    cases = {n: CASES[n]() for n in set(names)}
+    lpc = pg.LPC(ctx)
+    for use_lpc in (None, lpc):
+        say("run_stream lanes", lanes, "learned" if use_lpc else "jacobi")
+        ref = {}
+        for n, c in cases.items():
+            phi, st, _ = pg.run(ctx, c.V, c.F, c.label, c.mode, lpc=use_lpc, precision="fp32")
+            ref[n] = (phi.cpu().numpy(), st["n_flipped"])
+        items = [dict(V=cases[n].V, F=cases[n].F, label=cases[n].label, mode=cases[n].mode) for n in names]
+        outs = list(pg.run_stream(ctx, items, lanes=lanes, lpc=use_lpc, precision="fp32"))
+        assert len(outs) == len(names)
+        for n, (phi, st, info) in zip(names, outs):
+            got, (want, nfl) = phi.cpu().numpy(), ref[n]
+            assert got.shape == want.shape
+            assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max(), n
+            assert st["n_flipped"] == nfl == 0
+    torch.cuda.synchronize()
+    lpc.close()
