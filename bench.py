@@ -55,9 +55,9 @@ HBM_PEAK_GBS = 8000.0
 # summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
 TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "186c907551bd01abc4d1e65c64590847588414c2b8ee778771b1c0c07b0662d8",
-           "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "512,4,0,0"},
-           "bytes_per_launch": 8.691e9},
+           "source_sha256": "94119cdf7b8b496f2427510755b1ff72b75f8643c5fd5b8a266aa1fcd98d5957",
+           "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "256,4,0,0"},
+           "bytes_per_launch": 9.405e9},
 }
 
 

@@ -73,8 +73,15 @@ class WeldError(ValueError):
 # extended-plane helpers
 # ----------------------------------------------------------------------------
 
+def _ctype(x):
+    """Complex working type of the input: complex128, or a wider complex type
+    when the input carries one (an extended-precision run of the same steps,
+    used as a reference for the conditioning of long welds)."""
+    return np.result_type(np.asarray(x).dtype, np.complex128)
+
+
 def _csqrt(w):
-    return np.sqrt(w.astype(np.complex128))
+    return np.sqrt(w.astype(_ctype(w)))
 
 
 def _axis_sqrt_minus1(s):
@@ -114,7 +121,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
     Returns new (z, inf).  With squared_final=True this is the geodesic
     algorithm of Section 3.4 with the final map onto the upper half-plane.
     """
-    z = np.array(z, dtype=np.complex128)
+    z = np.array(z, dtype=_ctype(z))
     inf = np.array(inf, dtype=bool)
     N = z.size
     if k < 1 or k >= N:
@@ -125,7 +132,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
 
     # g_1
     z0, z1 = z[0], z[1]
-    out = np.empty(N, dtype=np.complex128)
+    out = np.empty(N, dtype=z.dtype)
     oinf = np.zeros(N, dtype=bool)
     gen = (idx >= 2) & ~inf
     out[gen] = _csqrt((z[gen] - z1) / (z[gen] - z0))
@@ -141,7 +148,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
         if inf[j] or xi.real <= 0.0:
             raise WeldError(f"zipper point {j} left the right half-plane")
         c, d = L_coeffs(xi)
-        Lz = np.empty(N, dtype=np.complex128)
+        Lz = np.empty(N, dtype=z.dtype)
         Linf = np.zeros(N, dtype=bool)
         fin = ~inf
         den = 1.0 + 1j * d * z[fin]
@@ -151,7 +158,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
             Lz[inf] = -1j * c / d
         else:
             Linf[inf] = True
-        out = np.empty(N, dtype=np.complex128)
+        out = np.empty(N, dtype=z.dtype)
         oinf = Linf.copy()
         zipped = (idx < j - 1) & ~Linf
         out[zipped] = _axis_sqrt_minus1(Lz[zipped].imag)
@@ -166,7 +173,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
     # final map g_{k+1}
     zeta_inf = bool(inf[0])
     zeta = z[0]
-    out = np.empty(N, dtype=np.complex128)
+    out = np.empty(N, dtype=z.dtype)
     oinf = np.zeros(N, dtype=bool)
     fin = ~inf
     if zeta_inf:
@@ -200,7 +207,7 @@ def intermediate_form(z, inf, k, branch, squared_final=False, check=True):
 def _close(z, inf, j, c0, c1, on_axis, glued_pair):
     """h_j applied to one point set."""
     N = z.size
-    Tz = np.empty(N, dtype=np.complex128)
+    Tz = np.empty(N, dtype=z.dtype)
     Tinf = np.zeros(N, dtype=bool)
     fin = ~inf
     den = c0 - 1j * c1 * z[fin]
@@ -210,12 +217,12 @@ def _close(z, inf, j, c0, c1, on_axis, glued_pair):
         Tz[inf] = 1j / c1
     else:
         Tinf[inf] = True
-    out = np.empty(N, dtype=np.complex128)
+    out = np.empty(N, dtype=z.dtype)
     oinf = Tinf.copy()
     ax = on_axis & ~Tinf
     t = Tz[ax].imag
     small = np.abs(t) <= 1.0
-    r = np.empty(t.size, dtype=np.complex128)
+    r = np.empty(t.size, dtype=z.dtype)
     r[small] = np.sqrt(1.0 - t[small] * t[small])
     r[~small] = 1j * np.sign(t[~small]) * np.sqrt(t[~small] * t[~small] - 1.0)
     out[ax] = r
@@ -246,7 +253,7 @@ def partial_weld(za, ia, zb, ib, k):
     eta = za[0]
 
     def h0(z, inf):
-        out = np.empty(z.size, dtype=np.complex128)
+        out = np.empty(z.size, dtype=z.dtype)
         oinf = np.zeros(z.size, dtype=bool)
         fin = ~inf
         if eta_inf:
@@ -282,7 +289,7 @@ def mobius3(z1, z2, z3):
 
 def apply_mobius(coef, z, inf):
     a, b, c, d = coef
-    out = np.empty(z.size, dtype=np.complex128)
+    out = np.empty(z.size, dtype=z.dtype)
     oinf = np.zeros(z.size, dtype=bool)
     fin = ~inf
     den = c * z[fin] + d
@@ -411,9 +418,11 @@ def weld_pair(ca, cb, closed=False):
     sa, sb = set(A), set(Bseq)
     seq_a = A + sorted(v for v in ca["z"] if v not in sa)
     seq_b = Bseq + sorted(v for v in cb["z"] if v not in sb)
-    za = np.array([ca["z"][v] for v in seq_a] + [0.0, 0.0], dtype=np.complex128)
+    va = [ca["z"][v] for v in seq_a]
+    za = np.array(va + [0.0, 0.0], dtype=_ctype(va))
     ia = np.array([ca["inf"][v] for v in seq_a] + [False, True])
-    zb = np.array([cb["z"][v] for v in seq_b] + [0.0, 0.0], dtype=np.complex128)
+    vb = [cb["z"][v] for v in seq_b]
+    zb = np.array(vb + [0.0, 0.0], dtype=_ctype(vb))
     ib = np.array([cb["inf"][v] for v in seq_b] + [False, True])
     za, ia = intermediate_form(za, ia, k, +1)
     zb, ib = intermediate_form(zb, ib, k, -1)
@@ -427,12 +436,12 @@ def weld_pair(ca, cb, closed=False):
     gap = np.abs(za[1:k] - zb[1:k])
     out = dict(z={}, inf={})
     for t, v in enumerate(seq_a):
-        out["z"][v] = complex(za[t])
+        out["z"][v] = za[t]
         out["inf"][v] = bool(ia[t])
     for t, v in enumerate(seq_b):
         if t <= k:
             continue
-        out["z"][v] = complex(zb[t])
+        out["z"][v] = zb[t]
         out["inf"][v] = bool(ib[t])
     out["outer"] = [] if closed else A[k:] + [A[0]] + Bseq[k + 1:][::-1]
     info = dict(k=k, glue_gap=float(gap.max()) if gap.size else 0.0,
@@ -448,13 +457,14 @@ def disk_step(comp):
     A = [outer[(s0 + s) % L] for s in range(L)]
     sa = set(A)
     seq = A + sorted(v for v in comp["z"] if v not in sa)
-    z = np.array([comp["z"][v] for v in seq], dtype=np.complex128)
+    vs = [comp["z"][v] for v in seq]
+    z = np.array(vs, dtype=_ctype(vs))
     zi = np.array([comp["inf"][v] for v in seq])
     z, zi = intermediate_form(z, zi, L - 1, +1, squared_final=True)
-    w = np.empty(z.size, dtype=np.complex128)
+    w = np.empty(z.size, dtype=z.dtype)
     w[~zi] = (z[~zi] - 1j) / (z[~zi] + 1j)
     w[zi] = 1.0
-    return dict(outer=outer, z={v: complex(w[t]) for t, v in enumerate(seq)},
+    return dict(outer=outer, z={v: w[t] for t, v in enumerate(seq)},
                 inf={v: False for v in seq})
 
 
@@ -475,7 +485,7 @@ def _weld(loops, coords, mode, sizes, return_steps):
         sizes = [len(l) for l in loops]
     comps = {}
     for i, (l, c) in enumerate(zip(loops, coords)):
-        comps[i] = dict(outer=list(l), z={v: complex(x) for v, x in zip(l, c)},
+        comps[i] = dict(outer=list(l), z={v: x for v, x in zip(l, c)},
                         inf={v: False for v in l})
     steps = []
     if len(loops) > 1:

@@ -2472,7 +2472,8 @@ static Error stream_fit(pgcp_ctx* ctx, pgcp_part* P, int prec, int blk, int* R) 
 // precision) or PGCP_PCG_CFG = "blk,R" (register-resident) or "blk,R,1"
 // (streaming; R = 0: size-weighted map) forces one; otherwise every shape that
 // fits is timed (best of two 40-iteration probes) on the real batch the first
-// time a batch of that shape is solved on the device, and the fastest is kept
+// time a batch of that shape is solved on the device, and the fastest (by more
+// than 3% over the earlier candidates) is kept
 // for every context on that device (contexts that solve side by side share
 // it).  The streaming kernel is tried with the fewest and twice the fewest
 // slices per wave that fit.
@@ -2595,7 +2596,9 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
         if (vb && vb[0] == '1')
             fprintf(stderr, "[pgcp] tune prec=%d coupled=%d shape %d,%d,%d: %d workgroups, %.3f ms / %d iterations\n",
                     prec, coupled, c.blk, c.R, c.stream, T.n_wg, ms, probe_iters);
-        if (ms < best_ms) {
+        // a later shape must be clearly faster: shapes within timing noise of
+        // each other keep the earlier one, so that the choice is repeatable
+        if (ms < 0.97f * best_ms) {
             best_ms = ms;
             best = c;
         }

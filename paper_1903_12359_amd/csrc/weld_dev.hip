@@ -899,10 +899,14 @@ void device_arcs(hipStream_t s, const std::vector<ArcTask>& tasks, DevBuf& bj, D
     double2* P = (double2*)bp.p;
     double* R = (double*)br.p;
     int* E = (int*)be.p;
+    // 256-thread workgroups up to 2048 points: four waves of at most 256
+    // registers fit beside a batched-CG workgroup of another context's solve
+    // (1024-thread ones were ~20% faster per step alone but waited for it)
     if (zip_mode() == 2) k_zip_arcs<1024, 8, true><<<g, 1024, 0, s>>>(J, P, R, E);
     else if (maxnp <= 256) k_zip_arcs<256, 1, false><<<g, 256, 0, s>>>(J, P, R, E);
     else if (maxnp <= 512) k_zip_arcs<256, 2, false><<<g, 256, 0, s>>>(J, P, R, E);
     else if (maxnp <= 1024) k_zip_arcs<256, 4, false><<<g, 256, 0, s>>>(J, P, R, E);
+    else if (maxnp <= 2048) k_zip_arcs<256, 8, false><<<g, 256, 0, s>>>(J, P, R, E);
     else if (maxnp <= 4096) k_zip_arcs<1024, 4, false><<<g, 1024, 0, s>>>(J, P, R, E);
     else k_zip_arcs<1024, 8, true><<<g, 1024, 0, s>>>(J, P, R, E);
     HIPTHROW(hipGetLastError());

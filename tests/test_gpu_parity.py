@@ -54,6 +54,18 @@ CASES = {
 }
 
 
+def _extended_weld(case, subs, bdy, seam):
+    """The oracle's weld of the same boundary coordinates in extended precision.
+
+    Long welds are ill-conditioned: the composed zipper maps amplify rounding
+    (at C3 size an FP64 evaluation lands ~2e-7 chordal from this one, at C2
+    ~7e-11), so at full size the GPU weld is held to the error of the FP64
+    oracle itself, both measured against this reference."""
+    wl = oracle_weld([s["loop"] for s in subs], [np.asarray(b).astype(np.clongdouble) for b in bdy], case.mode,
+                     sizes=[len(s["T"]) for s in subs])
+    return np.array([wl[int(v)] for v in seam])
+
+
 def _oracle_stages(case):
     part, subs = prepare(case.V, case.F, case.label)
     bdy = local_params(subs)
@@ -259,7 +271,8 @@ def test_pcg_kernels_match_oracle(ctx, kernel, system, monkeypatch):
 
 
 def test_c2_full_size_stagewise(ctx):
-    """C2 at full size (512^2 vertices, 16 pieces): DNCP and harmonic against the oracle."""
+    """C2 at full size (512^2 vertices, 16 pieces): DNCP, weld (the device zipper
+    on arcs of up to 512 points) and harmonic against the oracle."""
     import paper_1903_12359_amd as pg
     case = case_c2()
     say("C2 full: oracle")
@@ -270,6 +283,16 @@ def test_c2_full_size_stagewise(ctx):
     ob = np.concatenate(bdy)
     plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
     pg.assemble_cotan(ctx, plan, _dev(case.V))
+    seam = plan.export()["seam_gv"]
+    zo = np.array([welded[int(v)] for v in seam])
+    wg = pg.weld(ctx, plan, np.column_stack([ob.real, ob.imag]))
+    zg = wg[:, 0] + 1j * wg[:, 1]
+    zl = _extended_weld(case, subs, bdy, seam)
+    sc = float(np.abs(zl).max())
+    e_or = float(np.abs(zo - zl).max()) / sc
+    e_gpu = float(np.abs(zg - zl).max()) / sc
+    say("C2 full: weld err vs extended precision: gpu", e_gpu, "fp64 oracle", e_or)
+    assert e_gpu <= max(3.0 * e_or, 1e-12)
     # full-size pieces (16.6k vertices) are too ill-conditioned for CG to reach
     # 1e-13 in FP64; 1e-12 is the parity setting here
     for prec, tol, bound in (("fp64", 1e-12, 1e-9), ("fp32", 1e-11, 1e-6)):
@@ -288,7 +311,9 @@ def test_c2_full_size_stagewise(ctx):
 
 
 def test_c3_full_size_stagewise(ctx):
-    """C3 at full size (655,362 vertices, 64 k-means pieces, sphere): DNCP and harmonic against the oracle."""
+    """C3 at full size (655,362 vertices, 64 k-means pieces, sphere): DNCP, weld
+    (closed final weld of loops of ~1,400 points on the device) and harmonic
+    against the oracle."""
     import paper_1903_12359_amd as pg
     say("C3 full: generating")
     case = case_c3()
@@ -303,6 +328,15 @@ def test_c3_full_size_stagewise(ctx):
     seam = plan.export()["seam_gv"]
     w = np.array([welded[int(v)] for v in seam])
     wd = _dev(np.column_stack([w.real, w.imag]))
+    wg = pg.weld(ctx, plan, np.column_stack([ob.real, ob.imag]))
+    zg = wg[:, 0] + 1j * wg[:, 1]
+    io = ~np.isfinite(w)
+    assert np.array_equal(io, ~np.isfinite(zg))
+    sl = _sigma(_extended_weld(case, subs, bdy, seam)[~io])
+    e_or = float(np.abs(_sigma(w[~io]) - sl).max())
+    e_gpu = float(np.abs(_sigma(zg[~io]) - sl).max())
+    say("C3 full: weld chordal err vs extended precision: gpu", e_gpu, "fp64 oracle", e_or)
+    assert e_gpu <= max(3.0 * e_or, 1e-12)
     for prec, tol, bound in (("fp64", 1e-12, 1e-9), ("fp32", 1e-11, 1e-6)):
         say("C3 full:", prec)
         b, rep = pg.local_param(ctx, plan, precision=prec, tol=tol)

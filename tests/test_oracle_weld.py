@@ -127,6 +127,29 @@ def test_weld_glue_orientation_and_tiling(n, bx, by, seed):
             assert abs(_winding(outer_poly, c) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("mode", ["free", "disk"])
+def test_weld_extended_precision_run(mode):
+    """The weld evaluated in extended precision (the input's complex type is
+    carried through every step) agrees with the FP64 run to FP64 rounding, keeps
+    its type, and glues the arcs far more tightly: the reference that measures
+    the conditioning of long welds."""
+    if np.finfo(np.longdouble).nmant <= np.finfo(np.float64).nmant:
+        pytest.skip("long double is not wider than double here")
+    case = small_grid_case(25, 3, 3, seed=2, mode=mode)
+    part, subs = prepare(case.V, case.F, case.label)
+    bdy = local_params(subs)
+    loops = [s["loop"] for s in subs]
+    w64, st64, _ = weld(loops, bdy, mode, return_steps=True)
+    wl, stl, _ = weld(loops, [b.astype(np.clongdouble) for b in bdy], mode, return_steps=True)
+    assert all(np.asarray(c).dtype == np.clongdouble for c in wl.values())
+    z64 = np.array([w64[v] for v in sorted(w64)])
+    zl = np.array([wl[v] for v in sorted(wl)])
+    assert float(np.abs(z64 - zl).max()) <= 1e-12 * float(np.abs(zl).max())
+    gap64 = max(st["glue_gap"] for st in st64 if "glue_gap" in st)
+    gapl = max(st["glue_gap"] for st in stl if "glue_gap" in st)
+    assert gapl <= 1e-2 * gap64 or gapl <= 1e-16
+
+
 def test_weld_disk_constraint_unit_circle():
     case = small_grid_case(21, 2, 2, seed=3, mode="disk")
     part, subs = prepare(case.V, case.F, case.label)
