@@ -179,7 +179,7 @@ def main():
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
     ap.add_argument("--lpc-steps", type=int, default=400, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--lanes", type=int, default=2, help="meshes in flight in the stream (1: the host partition "
+    ap.add_argument("--lanes", type=int, default=3, help="meshes in flight in the stream (1: the host partition "
                     "of the next mesh overlaps the current one only)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="run the steps one after the other (no host partition of the next step during device work)")

@@ -2,6 +2,7 @@
 // host (partition, weld) and device (assembly, solves, distortion) stages.
 
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -9,7 +10,20 @@
 
 using pgcp::Error;
 
+extern "C" void kmp_set_defaults(char const* str);   // LLVM OpenMP runtime
+
 namespace {
+
+// Host stages run OpenMP regions from several threads at once (a partition
+// worker and the solve lanes of a stream, each with a team of its own): idle
+// team members must go to sleep soon instead of spinning for the runtime's
+// default 200 ms, or they take the cores the other teams need.  An explicit
+// KMP_BLOCKTIME in the environment wins.
+struct OmpDefaults {
+    OmpDefaults() {
+        if (!getenv("KMP_BLOCKTIME")) kmp_set_defaults("KMP_BLOCKTIME=1");
+    }
+} omp_defaults;
 
 pgcp_status fail(pgcp_ctx* ctx, const Error& e) {
     if (ctx && e.code != PGCP_OK) ctx->last_error = e.msg;

@@ -2648,8 +2648,11 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     const char* vb = getenv("PGCP_VERBOSE");
     const bool verbose = vb && vb[0] == '1';
     if (!P->ev0) {
+        // the host waits for the end of each batched-CG launch on ev1: a
+        // blocking wait leaves the core to other host work meanwhile (the
+        // partition of the next mesh, another lane's weld)
         HIPCHK(hipEventCreate(&P->ev0));
-        HIPCHK(hipEventCreate(&P->ev1));
+        HIPCHK(hipEventCreateWithFlags(&P->ev1, hipEventBlockingSync));
     }
     Error e{PGCP_OK, ""};
     const WorkMap& W = prec ? P->wmap32 : P->wmap64;

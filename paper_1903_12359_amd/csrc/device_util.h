@@ -49,8 +49,8 @@ inline Error dev_alloc(DevBuf& b, size_t bytes) {
     return Error{PGCP_OK, ""};
 }
 
-template <typename T>
-inline Error upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+template <typename T, typename A>
+inline Error upload(DevBuf& b, const std::vector<T, A>& v, hipStream_t s) {
     Error e = dev_alloc(b, v.size() * sizeof(T));
     if (e.code != PGCP_OK) return e;
     if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));

@@ -72,15 +72,22 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     // then the twin of a->b is the b->a entry in b's list.
     const int64_t nh = 3 * nf;
     auto he_b = [&](int64_t h) { return F[(h / 3) * 3 + (h % 3 + 1) % 3]; };
+    // (the order inside a vertex's list is not fixed; only membership is used)
     std::vector<int64_t> cnt(nv + 1, 0);
-    for (int64_t h = 0; h < nh; ++h) cnt[F[h] + 1]++;
+#pragma omp parallel for schedule(static)
+    for (int64_t h = 0; h < nh; ++h) __atomic_fetch_add(&cnt[F[h] + 1], (int64_t)1, __ATOMIC_RELAXED);
     for (int64_t v = 0; v < nv; ++v) cnt[v + 1] += cnt[v];
-    std::vector<int32_t> out_h(nh);
+    bigvec<int32_t> out_h(nh), out_b(nh);   // half-edge and its target, grouped by source
     {
         std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
-        for (int64_t h = 0; h < nh; ++h) out_h[fill[F[h]]++] = (int32_t)h;
+#pragma omp parallel for schedule(static)
+        for (int64_t h = 0; h < nh; ++h) {
+            const int64_t q = __atomic_fetch_add(&fill[F[h]], (int64_t)1, __ATOMIC_RELAXED);
+            out_h[q] = (int32_t)h;
+            out_b[q] = he_b(h);
+        }
     }
-    std::vector<int32_t> twin(nh, -1);
+    bigvec<int32_t> twin(nh);
     int bad_nm = 0, bad_or = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad_nm, bad_or)
     for (int64_t h = 0; h < nh; ++h) {
@@ -88,16 +95,16 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         int found = 0;
         int32_t t = -1;
         for (int64_t q = cnt[b]; q < cnt[b + 1]; ++q)
-            if (he_b(out_h[q]) == a) {
+            if (out_b[q] == a) {
                 found++;
                 t = out_h[q];
             }
         int same = 0;
         for (int64_t q = cnt[a]; q < cnt[a + 1]; ++q)
-            if (he_b(out_h[q]) == b) same++;
+            if (out_b[q] == b) same++;
         if (same > 1) bad_or++;              // two half-edges a->b: faces disagree on orientation
         if (found > 1 || found + same > 2) bad_nm++;
-        if (found == 1) twin[h] = t;
+        twin[h] = found == 1 ? t : -1;
     }
     if (bad_or) return topo("inconsistently oriented faces");
     if (bad_nm) return topo("non-manifold edge (more than two faces)");
@@ -135,14 +142,24 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     // vertices of each piece (sorted), packed rows padded to 64
     std::vector<std::vector<int32_t>> verts(K);
     Error err{PGCP_OK, ""};
-#pragma omp parallel for schedule(dynamic)
-    for (int i = 0; i < K; ++i) {
-        auto& vv = verts[i];
-        vv.reserve(3 * (fptr[i + 1] - fptr[i]));
-        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t)
-            for (int c = 0; c < 3; ++c) vv.push_back(F[3 * (int64_t)faces[t] + c]);
-        std::sort(vv.begin(), vv.end());
-        vv.erase(std::unique(vv.begin(), vv.end()), vv.end());
+#pragma omp parallel
+    {
+        // a thread's vertex stamps: the piece (+1) that last collected it
+        std::vector<int32_t> seen(nv, 0);
+#pragma omp for schedule(dynamic)
+        for (int i = 0; i < K; ++i) {
+            auto& vv = verts[i];
+            vv.reserve(fptr[i + 1] - fptr[i]);
+            for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t)
+                for (int c = 0; c < 3; ++c) {
+                    const int32_t g = F[3 * (int64_t)faces[t] + c];
+                    if (seen[g] != i + 1) {
+                        seen[g] = i + 1;
+                        vv.push_back(g);
+                    }
+                }
+            std::sort(vv.begin(), vv.end());
+        }
     }
     P->sub_nv.resize(K);
     P->row0.assign(K + 1, 0);
@@ -169,17 +186,18 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     }
 
     lap("pieces");
-    // corner -> packed row
-    std::vector<int32_t> corner_row(nh);
-#pragma omp parallel for schedule(dynamic)
-    for (int i = 0; i < K; ++i) {
-        const auto& vv = verts[i];
-        for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
-            int64_t f = faces[t];
-            for (int c = 0; c < 3; ++c) {
-                int32_t g = F[3 * f + c];
-                auto it = std::lower_bound(vv.begin(), vv.end(), g);
-                corner_row[3 * f + c] = P->row0[i] + (int32_t)(it - vv.begin());
+    // corner -> packed row (a thread's global-vertex -> row map, refilled per piece)
+    bigvec<int32_t> corner_row(nh);
+#pragma omp parallel
+    {
+        bigvec<int32_t> row_of(nv);
+#pragma omp for schedule(dynamic)
+        for (int i = 0; i < K; ++i) {
+            const auto& vv = verts[i];
+            for (size_t l = 0; l < vv.size(); ++l) row_of[vv[l]] = P->row0[i] + (int32_t)l;
+            for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
+                const int64_t f = faces[t];
+                for (int c = 0; c < 3; ++c) corner_row[3 * f + c] = row_of[F[3 * f + c]];
             }
         }
     }
@@ -294,7 +312,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
             for (int c = 0; c < 3; ++c) deg_raw[corner_row[3 * (int64_t)faces[t] + c]] += 2;
     std::vector<int64_t> rptr(N + 1, 0);
     for (int64_t r = 0; r < N; ++r) rptr[r + 1] = rptr[r] + deg_raw[r];
-    std::vector<int32_t> ent_col(rptr[N]), ent_opp(rptr[N]);
+    bigvec<int32_t> ent_col(rptr[N]), ent_opp(rptr[N]);
     {
         std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
         // rows of different pieces are disjoint: fill piece by piece in parallel
@@ -316,7 +334,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     }
     // merge duplicates: unique columns ascending, up to two opposite vertices
     std::vector<int32_t> deg(N, 0);
-    std::vector<int32_t> u_col(rptr[N]), u_o1(rptr[N]), u_o2(rptr[N]);
+    bigvec<int32_t> u_col(rptr[N]), u_o1(rptr[N]), u_o2(rptr[N]);
     std::vector<std::string> derr(1);
     bool bad_edge = false;
 #pragma omp parallel for schedule(static)

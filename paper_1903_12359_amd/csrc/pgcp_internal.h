@@ -6,6 +6,8 @@
 #include <map>
 #include <cstdint>
 #include <string>
+#include <memory>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -16,6 +18,30 @@
 namespace pgcp {
 
 using cplx = std::complex<double>;
+
+// Allocator whose new elements are default-initialised (no zero fill): the
+// plan's large arrays are written in parallel right after they are sized, and
+// a serial zero fill of tens of MB would cost more than writing them.
+template <class T>
+struct NoFillAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoFillAlloc<U>;
+    };
+    NoFillAlloc() = default;
+    template <class U>
+    NoFillAlloc(const NoFillAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using bigvec = std::vector<T, NoFillAlloc<T>>;
 
 // Error carried from internal code to the C ABI.
 struct Error {
@@ -106,9 +132,9 @@ struct pgcp_part {
     std::vector<int32_t> slice_sub;           // [nslices]
     std::vector<int64_t> sl_ptr;              // [nslices+1] first element of each slice
     std::vector<int32_t> sl_w;                // [nslices] slice width (max off-diagonals per row)
-    std::vector<int32_t> sl_col;              // [sell_elems] packed column; padding = own row
-    std::vector<int32_t> sl_opp;              // [2*sell_elems] opposite vertices (global ids) or -1
-    std::vector<int32_t> sl_rev;              // [sell_elems] slot of the reverse entry, -1 for padding
+    pgcp::bigvec<int32_t> sl_col;                 // [sell_elems] packed column; padding = own row
+    pgcp::bigvec<int32_t> sl_opp;                 // [2*sell_elems] opposite vertices (global ids) or -1
+    pgcp::bigvec<int32_t> sl_rev;                 // [sell_elems] slot of the reverse entry, -1 for padding
     std::vector<int32_t> pin_row;             // [2K] DNCP pins p0, p1 (packed rows)
     std::vector<double> pin_x1;               // [K] x coordinate of p1 (|v_p1 - v_p0|)
     std::vector<int32_t> loop_ptr;            // [K+1]

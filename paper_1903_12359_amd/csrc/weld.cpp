@@ -195,8 +195,51 @@ int shared_arc(const std::vector<int>& la, const std::vector<int>& lb, int* star
     return k;
 }
 
+namespace {
+
+// shared_arc with a dense position table: pos[v] is -1 for every vertex on entry
+// and again on return.
+int shared_arc_pos(const std::vector<int>& la, const std::vector<int>& lb, std::vector<int>& pos, int* start) {
+    const int La = (int)la.size(), Lb = (int)lb.size();
+    for (int i = 0; i < Lb; ++i) pos[lb[i]] = i;
+    auto done = [&](int r) {
+        for (int i = 0; i < Lb; ++i) pos[lb[i]] = -1;
+        return r;
+    };
+    std::vector<char> in(La, 0);
+    int m = 0;
+    for (int i = 0; i < La; ++i)
+        if (pos[la[i]] >= 0) {
+            in[i] = 1;
+            m++;
+        }
+    if (m < 3) return done(-1);
+    if (m == La && m == Lb) return done(-2);
+    if (m == La) return done(-1);
+    int runs = 0, s0 = -1;
+    for (int i = 0; i < La; ++i)
+        if (in[i] && !in[(i + La - 1) % La]) {
+            runs++;
+            s0 = i;
+        }
+    if (runs != 1) return done(-1);
+    const int k = m - 1;
+    for (int s = 0; s < k; ++s) {
+        const int pa = pos[la[(s0 + s) % La]], pb = pos[la[(s0 + s + 1) % La]];
+        if (((pa - pb) % Lb + Lb) % Lb != 1) return done(-1);
+    }
+    *start = s0;
+    return done(k);
+}
+
+}  // namespace
+
 Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<int64_t>& sizes,
                  int mode, std::vector<std::vector<std::pair<int, int>>>* rounds) {
+    int maxv = 0;
+    for (const auto& l : loops)
+        for (int v : l) maxv = std::max(maxv, v);
+    std::vector<int> pos(maxv + 1, -1);
     std::unordered_map<int, std::vector<int>> comps;   // id -> outer loop
     std::unordered_map<int, int64_t> size;
     for (size_t i = 0; i < loops.size(); ++i) {
@@ -205,19 +248,19 @@ Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<i
     }
     const size_t target = mode == PGCP_SPHERE ? 2 : 1;
     while (comps.size() > target) {
-        // candidate pairs from shared vertices
-        std::unordered_map<int, std::vector<int>> owners;
-        std::vector<int> ids;
-        for (auto& kv : comps) ids.push_back(kv.first);
-        std::sort(ids.begin(), ids.end());
-        for (int id : ids)
-            for (int v : comps[id]) owners[v].push_back(id);
+        // candidate pairs from shared vertices: (vertex, component) sorted by vertex
+        std::vector<std::pair<int, int>> vo;
+        for (auto& kv : comps)
+            for (int v : kv.second) vo.emplace_back(v, kv.first);
+        std::sort(vo.begin(), vo.end());
         std::vector<std::pair<int, int>> pairs;
-        for (auto& kv : owners) {
-            auto& o = kv.second;
-            for (size_t x = 0; x < o.size(); ++x)
-                for (size_t y = x + 1; y < o.size(); ++y)
-                    pairs.emplace_back(std::min(o[x], o[y]), std::max(o[x], o[y]));
+        for (size_t a = 0; a < vo.size();) {
+            size_t b = a;
+            while (b < vo.size() && vo[b].first == vo[a].first) b++;
+            for (size_t x = a; x < b; ++x)
+                for (size_t y = x + 1; y < b; ++y)
+                    pairs.emplace_back(std::min(vo[x].second, vo[y].second), std::max(vo[x].second, vo[y].second));
+            a = b;
         }
         std::sort(pairs.begin(), pairs.end());
         pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
@@ -232,7 +275,7 @@ Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<i
         std::vector<Cand> cands;
         for (auto& pr : pairs) {
             int st;
-            int k = shared_arc(comps[pr.first], comps[pr.second], &st);
+            int k = shared_arc_pos(comps[pr.first], comps[pr.second], pos, &st);
             if (k >= 2) {
                 int64_t m = (int64_t)std::min(comps[pr.first].size(), comps[pr.second].size());
                 cands.push_back(Cand{k, m, size[pr.first] + size[pr.second], pr.first, pr.second});
@@ -258,7 +301,7 @@ Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<i
             auto& la = comps[pr.first];
             auto& lb = comps[pr.second];
             int st;
-            int k = shared_arc(la, lb, &st);
+            int k = shared_arc_pos(la, lb, pos, &st);
             const int La = (int)la.size(), Lb = (int)lb.size();
             std::vector<int> A(La);
             for (int s = 0; s < La; ++s) A[s] = la[(st + s) % La];
