@@ -55,9 +55,9 @@ HBM_PEAK_GBS = 8000.0
 # summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
 TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "94119cdf7b8b496f2427510755b1ff72b75f8643c5fd5b8a266aa1fcd98d5957",
+           "source_sha256": "d51a100c91b72cc6aaa36c723909bc120c7fd91d9ce6a2c32c32f2aa97aee9b3",
            "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "256,4,0,0"},
-           "bytes_per_launch": 9.405e9},
+           "bytes_per_launch": 9.888e9},
 }
 
 
