@@ -22,6 +22,17 @@
  *  - Device work is enqueued on the context's stream.  Calls that return host
  *    results (partition, query/export, weld, and any call given a non-NULL stats
  *    pointer) synchronise that stream before returning.
+ *  - Device memory the library allocates inside a context's call comes from the
+ *    device's stream-ordered pool (hipMallocAsync) on that context's stream and
+ *    goes back to it in the order of the stream of the context that last worked
+ *    on the object (pgcp_part_destroy included), so no call waits for work on
+ *    other streams.  A plan is meant for one context at a time: a caller that
+ *    moves a plan to another context's stream orders the two streams itself.
+ *  - Several contexts (threads, streams) may work on one device at once.  A
+ *    batched-CG launch needs every workgroup of the device resident, so the
+ *    library runs one such launch per device at a time (a lock held from launch
+ *    to completion); all other work of the contexts overlaps.  Autotuned launch
+ *    shapes are shared by the contexts of a device.
  *  - Coordinates are float64.  Indices are int32.  Planar coordinates are stored
  *    as interleaved (x, y) pairs; spherical ones as (x, y, z) triples.
  *  - Boundary arrays ("bdy") list every piece's boundary loop, piece by piece
@@ -141,7 +152,8 @@ typedef struct {
 pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream);
 void pgcp_ctx_destroy(pgcp_ctx* ctx);
 const char* pgcp_last_error(const pgcp_ctx* ctx);
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on (work already enqueued on the old
+ * stream must be ordered before the new stream's by the caller). */
 pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream);
 
 /* Section 4.1.  Cut edges are interior edges whose two faces carry different
@@ -163,6 +175,8 @@ pgcp_status pgcp_part_query(const pgcp_part* part, pgcp_part_info* info);
  * loop_gv [n_bdy] (boundary loops), seam_gv [n_seam]. */
 pgcp_status pgcp_part_export(const pgcp_part* part, int32_t* face_sub, int32_t* sub_nv,
                              int32_t* loop_ptr, int32_t* loop_gv, int32_t* seam_gv);
+/* Release a plan.  Its device memory returns to the pool in the order of the
+ * stream of the context that last worked on it; the stream must still exist. */
 void pgcp_part_destroy(pgcp_part* part);
 
 /* Copy the assembled FP64 cotangent Laplacian of one piece to host CSR arrays
@@ -240,6 +254,8 @@ int64_t pgcp_lpc_num_params(void);
  * network lives on the context's device; release with pgcp_lpc_destroy. */
 pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** out);
 pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* params_host);
+/* Any context's solves may read the network; destroying it waits for the device
+ * to finish everything enqueued. */
 void pgcp_lpc_destroy(pgcp_lpc* lpc);
 /* Run the network on every piece of an assembled plan and store the SPAI
  * values for `system` in the plan.  Async. */
