@@ -412,6 +412,34 @@ def test_run_stream_matches_run(ctx, name):
         assert info["times"]["partition_overlapped"] > 0.0
 
 
+def test_run_stream_lanes_error_then_reuse(ctx):
+    """A mesh that cannot be partitioned (a ring-shaped piece) in the middle of
+    a stream with several meshes in flight raises the library's error to the
+    consumer without hanging, and the lanes' contexts run the next stream."""
+    import paper_1903_12359_amd as pg
+    from synth import block_labels, grid_mesh
+    n = 7
+    xy, F = grid_mesh(n)
+    V = np.column_stack([xy, np.zeros(n * n)])
+    ring = np.where(block_labels(n, 3, 3) == 4, 1, 0).astype(np.int32)
+    good = CASES["g17_2x2"]()
+    ok = dict(V=good.V, F=good.F, label=good.label, mode=good.mode)
+    bad = dict(V=V, F=F, label=ring, mode="free")
+    say("run_stream lanes: error in the stream")
+    got = []
+    with pytest.raises(pg.PGCPError) as ei:
+        for out in pg.run_stream(ctx, [ok, ok, bad, ok, ok], lanes=2):
+            got.append(out)
+    assert ei.value.status == "TOPOLOGY"
+    assert len(got) == 2
+    phi0, _, _ = pg.run(ctx, good.V, good.F, good.label, good.mode)
+    outs = list(pg.run_stream(ctx, [ok] * 3, lanes=2))
+    assert len(outs) == 3
+    ref = phi0.cpu().numpy()
+    for phi, st, _ in outs:
+        assert np.abs(phi.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("lanes", [2, 3])
 def test_run_stream_lanes_match_run(ctx, lanes):
     """With several meshes in flight (one context and stream per lane, the
