@@ -25,8 +25,10 @@ context (the latency of a single mesh).  --no-pipeline times the latter only.
 The step is timed twice on the same GPU: with Jacobi-PCG, and with the learned
 SPAI preconditioner (network inference inside the step).  The network is
 first trained on the GPU for --lpc-steps Adam steps on seeded training meshes
-disjoint from the workload; that time is reported separately and is not part
-of a step.  `value` is the learned-PCG throughput; both variants are listed.
+disjoint from the workload (--lpc-set c4: about 2,000 pieces of 1k-20k vertices
+from bump height fields and perturbed spheres, trained in windows of plans);
+that time is reported separately and is not part of a step.  `value` is the
+learned-PCG throughput; both variants are listed.
 
 The roofline object is for the dominant kernel, the batched persistent PCG
 (k_pcg): achieved = algorithmic bytes of all its launches in the timed steps /
@@ -100,18 +102,33 @@ def cpu_baseline(workload: str, timeout: float = 600.0):
     return rec
 
 
-def train_lpc(ctx, steps, seed=0):
-    """Train the learned preconditioner on the GPU (seeded training meshes, disjoint from the workloads)."""
+def train_lpc(ctx, steps, seed=0, which="c4"):
+    """Train the learned preconditioner on the GPU (seeded training meshes, disjoint from the workloads).
+
+    c4: the training recipe of the learned-preconditioner configuration (about
+    2,000 pieces of 1k-20k vertices from bump height fields and perturbed
+    spheres), in windows of plans; small: ten smaller meshes (107 pieces) held on
+    the device at once."""
     import paper_1903_12359_amd as pg
-    from paper_1903_12359_amd.lpc_train import TrainingSet, init_params, train, training_meshes
+    from paper_1903_12359_amd.lpc_train import TrainingSet, init_params, train, train_windows, training_meshes
     t0 = time.perf_counter()
-    tset = TrainingSet(ctx, training_meshes(seed=seed))
-    t1 = time.perf_counter()
     lpc = pg.LPC(ctx, init_params(seed))
-    hist = train(ctx, lpc, tset, steps, lr=2e-3, seed=seed)
+    if which == "c4":
+        from synth import c4_training_meshes
+        meshes = list(c4_training_meshes(seed=seed))
+        t1 = time.perf_counter()
+        hist, pieces, windows = train_windows(ctx, lpc, meshes, steps, lr=2e-3, seed=seed)
+        plans = len(meshes)
+    else:
+        tset = TrainingSet(ctx, training_meshes(seed=seed))
+        t1 = time.perf_counter()
+        hist = train(ctx, lpc, tset, steps, lr=2e-3, seed=seed)
+        plans, pieces, windows = len(tset.items), int(sum(p.K for p, _, _ in tset.items)), 1
+        for p, _, _ in tset.items:
+            p.close()
     t2 = time.perf_counter()
-    info = {"steps": steps, "train_s": round(t2 - t1, 3), "set_up_s": round(t1 - t0, 3),
-            "plans": len(tset.items), "pieces": int(sum(p.K for p, _, _ in tset.items)),
+    info = {"set": which, "steps": len(hist), "train_s": round(t2 - t1, 3), "set_up_s": round(t1 - t0, 3),
+            "plans": plans, "pieces": int(pieces), "windows": windows,
             "loss_first": round(float(np.mean(hist[:20])), 5), "loss_last": round(float(np.mean(hist[-20:])), 5),
             "n_params": lpc.n_params}
     return lpc, info
@@ -177,7 +194,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
-    ap.add_argument("--lpc-steps", type=int, default=400, help="GPU training steps of the learned preconditioner")
+    ap.add_argument("--lpc-steps", type=int, default=500, help="GPU training steps of the learned preconditioner")
+    ap.add_argument("--lpc-set", default="c4", choices=["c4", "small"],
+                    help="training set of the learned preconditioner (c4: ~2,000 pieces of 1k-20k vertices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lanes", type=int, default=3, help="meshes in flight in the stream (1: the host partition "
                     "of the next mesh overlaps the current one only)")
@@ -217,7 +236,7 @@ def main():
         res["jacobi"] = time_variant(pg, ctx, case, V_dev, F_dev, args, None, pipeline=not args.no_pipeline)
         print(f"[bench] jacobi: {res['jacobi']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)
     if args.precond in ("learned", "both"):
-        lpc, lpc_info = train_lpc(ctx, args.lpc_steps)
+        lpc, lpc_info = train_lpc(ctx, args.lpc_steps, which=args.lpc_set)
         print(f"[bench] learned preconditioner trained: {lpc_info}", file=sys.stderr, flush=True)
         res["learned"] = time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, pipeline=not args.no_pipeline)
         print(f"[bench] learned: {res['learned']['ms_per_step']:.1f} ms/step", file=sys.stderr, flush=True)

@@ -78,6 +78,40 @@ def train(ctx, lpc, tset: TrainingSet, steps: int, lr: float = 1e-3, n_probes: i
     return hist
 
 
+def train_windows(ctx, lpc, meshes, steps: int, window_rows: int = 1_500_000, lr: float = 1e-3,
+                  n_probes: int = 8, seed: int = 0, log=None):
+    """Training over a large set of meshes (the C4 recipe) in windows: the plans
+    of consecutive meshes up to `window_rows` vertices are assembled on the
+    device, trained on and released (a plan's training buffers hold ~10 kB per
+    row).  The `steps` Adam steps are shared among the windows in proportion to
+    their vertices.  Returns the loss history, the number of pieces seen and the
+    number of windows."""
+    meshes = list(meshes)
+    windows, cur, rows = [], [], 0
+    for c in meshes:
+        cur.append(c)
+        rows += c.V.shape[0]
+        if rows >= window_rows:
+            windows.append((cur, rows))
+            cur, rows = [], 0
+    if cur:
+        windows.append((cur, rows))
+    total = sum(r for _, r in windows)
+    hist, pieces, done = [], 0, 0
+    for w, (cases, rows) in enumerate(windows):
+        n = (steps * sum(r for _, r in windows[:w + 1])) // total - done   # cumulative rounding
+        done += n
+        tset = TrainingSet(ctx, cases)
+        pieces += sum(p.K for p, _, _ in tset.items)
+        hist.extend(train(ctx, lpc, tset, n, lr=lr, n_probes=n_probes, seed=seed + w))
+        for p, _, _ in tset.items:
+            p.close()
+        if log:
+            log(f"[lpc] window {w}: {len(cases)} meshes, {rows} vertices, {n} steps, "
+                f"loss {np.mean(hist[-20:]) if hist else float('nan'):.4f}")
+    return hist, pieces, len(windows)
+
+
 # layout of the flat parameter vector (the order pgcp_lpc_create expects)
 WIDTH = 64
 SHAPES = [("W_x", (3, WIDTH)), ("b_x", (WIDTH,)), ("W_y", (3, WIDTH)), ("b_y", (WIDTH,))]
@@ -105,9 +139,22 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--set", default="small", choices=["small", "c4"],
+                    help="small: 10 meshes held on the device; c4: ~2,000 pieces of 1k-20k vertices, trained "
+                         "in windows of plans")
     args = ap.parse_args()
     import paper_1903_12359_amd as pg
     ctx = pg.Context(0)
+    if args.set == "c4":
+        from synth import c4_training_meshes
+        lpc = pg.LPC(ctx, init_params(args.seed))
+        t = time.perf_counter()
+        hist, pieces, _ = train_windows(ctx, lpc, c4_training_meshes(seed=args.seed), args.steps, lr=args.lr,
+                                        seed=args.seed, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[lpc] {pieces} pieces, {len(hist)} steps in {time.perf_counter() - t:.1f}s", file=sys.stderr,
+              flush=True)
+        np.save(args.out, lpc.params())
+        return
     t = time.perf_counter()
     tset = TrainingSet(ctx, training_meshes(seed=args.seed))
     print(f"[lpc] training set: {len(tset.items)} plans, {sum(p.K for p, _, _ in tset.items)} pieces "

@@ -18,4 +18,5 @@ from .meshes import (  # noqa: F401
     small_sphere_case,
     icosphere,
     guillotine_labels,
+    c4_training_meshes,
 )

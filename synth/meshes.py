@@ -553,3 +553,41 @@ def case_c3(level: int = 8, k: int = 64) -> MeshCase:
     lab, ratio = sphere_labels(V, F, k, rng)
     return MeshCase("C3" if level == 8 else f"C3_l{level}", V, F, lab, "sphere",
                     dict(level=level, k=k, ratio=ratio))
+
+
+# ----------------------------------------------------------------------------
+# C4: training Laplacians
+# ----------------------------------------------------------------------------
+
+def c4_training_meshes(seed: int = 0, n_height: int = 1000, n_sphere: int = 1000):
+    """The learned-preconditioner training recipe: meshes whose pieces have about
+    1k-20k vertices, yielded one at a time until about n_height pieces of bump
+    height fields (grids 128^2-512^2, 8-32 bumps of C2's distribution, C2's
+    vertex jitter, block partitions) and n_sphere pieces of perturbed icospheres
+    (levels 6-7, C3's perturbation, k-means pieces) are reached.  Seeds are
+    disjoint from the benchmark cases."""
+    rng = np.random.default_rng(SEED_BASE + 4000 + seed)
+    count, t = 0, 0
+    while count < n_height:
+        n = int(rng.choice([128, 192, 256, 384, 512]))
+        size = float(np.exp(rng.uniform(np.log(1200.0), np.log(18000.0))))
+        blocks = max(1.0, n * n / size)
+        bx = max(1, int(round(np.sqrt(blocks * rng.uniform(0.5, 2.0)))))
+        by = max(1, int(round(blocks / bx)))
+        nb = int(rng.integers(8, 33))
+        count += bx * by
+        yield small_grid_case(n, bx, by, seed=40_000 + 1_000 * seed + t, jitter=1e-3 * (n - 1), nbumps=nb)
+        t += 1
+    count = 0
+    while count < n_sphere:
+        level = int(rng.choice([6, 7]))
+        nv = 10 * 4 ** level + 2
+        size = float(np.exp(rng.uniform(np.log(1200.0), np.log(18000.0))))
+        k = int(min(64, max(2, round(nv / size))))
+        srng = np.random.default_rng(SEED_BASE + 44_000 + 1_000 * seed + t)
+        V, F = icosphere(level)
+        V, _ = perturb_sphere(V, srng, lmax=8, scale=0.05)
+        lab, ratio = sphere_labels(V, F, k, srng)
+        count += int(lab.max()) + 1
+        yield MeshCase(f"c4sphere{level}_k{k}_s{t}", V, F, lab, "sphere", dict(level=level, k=k, ratio=ratio))
+        t += 1

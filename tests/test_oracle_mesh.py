@@ -208,3 +208,21 @@ def test_local_faces_roundtrip():
     for i, s in enumerate(p.subs):
         T = local_faces(p, case.F, i)
         assert np.array_equal(s.verts[T], case.F[s.faces])
+
+
+def test_c4_training_recipe_sizes_and_seeds():
+    """The training recipe yields height fields, then perturbed spheres, whose
+    pieces have about 1k-20k vertices, and the same meshes for the same seed."""
+    from itertools import islice
+    from synth import c4_training_meshes
+    first = list(islice(c4_training_meshes(seed=0, n_height=60, n_sphere=8), 12))
+    again = list(islice(c4_training_meshes(seed=0, n_height=60, n_sphere=8), 12))
+    assert [c.name for c in first] == [c.name for c in again]
+    assert all(np.array_equal(a.V, b.V) and np.array_equal(a.label, b.label) for a, b in zip(first, again))
+    modes = [c.mode for c in first]
+    assert "free" in modes and "sphere" in modes
+    assert modes == sorted(modes)   # all height fields before the spheres
+    for c in first:
+        part = partition(c.V, c.F, c.label)
+        sizes = np.array([s.verts.size for s in part.subs])
+        assert sizes.min() >= 500 and sizes.max() <= 30_000, (c.name, sizes.min(), sizes.max())
