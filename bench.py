@@ -59,7 +59,7 @@ TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
            "source_sha256": "d51a100c91b72cc6aaa36c723909bc120c7fd91d9ce6a2c32c32f2aa97aee9b3",
            "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "256,4,0,0"},
-           "bytes_per_launch": 9.888e9},
+           "bytes_per_launch": 9.980e9},
 }
 
 
