@@ -278,9 +278,14 @@ pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* part, pgcp_lpc* lpc, int32_t
 pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* part, pgcp_lpc* lpc, int32_t system,
                                 const float* probes_dev, int32_t n_probes, float lr, double* loss);
 /* Packed-row ranges of the pieces: piece i owns rows row0[i] .. row0[i+1]-1,
- * its local vertex j (ascending global index) on row row0[i] + j; rows past
- * sub_nv[i] are padding.  row0 [n_sub+1]. */
+ * its sub_nv[i] vertices on the first sub_nv[i] of them, the rest padding.
+ * row0 [n_sub+1]. */
 pgcp_status pgcp_part_rows(const pgcp_part* part, int64_t* row0);
+/* Global vertex of every packed row, -1 on padding rows: row_gv [row0[n_sub]].
+ * Within a piece the rows follow a reverse Cuthill-McKee order of the piece's
+ * vertex graph (a workgroup's consecutive rows form a compact patch), not the
+ * global order; probe vectors (pgcp_lpc_grad) are laid out by this map. */
+pgcp_status pgcp_part_row_vertices(const pgcp_part* part, int32_t* row_gv);
 
 #ifdef __cplusplus
 }

@@ -63,7 +63,8 @@ EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_s
            "pgcp_part_query", "pgcp_part_export", "pgcp_part_destroy", "pgcp_laplacian_export",
            "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion",
            "pgcp_lpc_num_params", "pgcp_lpc_create", "pgcp_lpc_get_params", "pgcp_lpc_destroy", "pgcp_lpc_infer",
-           "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows"]
+           "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows",
+           "pgcp_part_row_vertices"]
 PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
 SYSTEMS = {"dncp": 0, "harmonic": 1}
 
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "pgcp_lpc_grad": (I32, [P, P, P, I32, P, I32, ctypes.POINTER(D), P]),
         "pgcp_lpc_train_step": (I32, [P, P, P, I32, P, I32, ctypes.c_float, ctypes.POINTER(D)]),
         "pgcp_part_rows": (I32, [P, P]),
+        "pgcp_part_row_vertices": (I32, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -253,6 +255,12 @@ class Plan:
         row0 = np.empty(self.K + 1, np.int64)
         self.ctx.check(self.ctx.lib.pgcp_part_rows(self.h, _ptr(row0)))
         return row0
+
+    def row_vertices(self):
+        """Global vertex of every packed row ([row0[K]]), -1 on padding rows."""
+        gv = np.empty(int(self.rows()[-1]), np.int32)
+        self.ctx.check(self.ctx.lib.pgcp_part_row_vertices(self.h, _ptr(gv)))
+        return gv
 
     def close(self):
         if getattr(self, "h", None):

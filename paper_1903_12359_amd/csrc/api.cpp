@@ -276,4 +276,10 @@ pgcp_status pgcp_part_rows(const pgcp_part* P, int64_t* row0) {
     return PGCP_OK;
 }
 
+pgcp_status pgcp_part_row_vertices(const pgcp_part* P, int32_t* row_gv) {
+    if (!P || !row_gv) return PGCP_E_INVALID;
+    for (int64_t r = 0; r < P->N; ++r) row_gv[r] = P->row_gv[r];
+    return PGCP_OK;
+}
+
 }  // extern "C"

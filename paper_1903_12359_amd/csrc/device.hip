@@ -634,7 +634,11 @@ k_pcg(CGArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     V2* lv = reinterpret_cast<V2*>(smem_raw);   // [lds_n] p: own rows, then the halo
     V2* lrs = lv + a.lds_n;                     // [lds_n] SPAI operand r: own rows, then the halo
-    V2* le = lv + 2 * (int64_t)a.lds_n;         // [BLK R] e of the own rows
+    // e of the own rows: in LDS up to 1024 rows per workgroup; larger shapes
+    // keep it in memory (plain accesses, each thread its own rows) so that two
+    // workgroups still share a CU's LDS
+    constexpr bool ELDS = BLK * R <= 1024;
+    V2* le = lv + 2 * (int64_t)a.lds_n;         // [BLK R] (ELDS only)
     __shared__ double lds[2 * NW * 8];
     int bpar = 0;   // LDS bank of the next block sum
     __shared__ int lds_flag[2];
@@ -691,7 +695,8 @@ k_pcg(CGArgs<T> a) {
         if (!valid[j]) continue;
         const int32_t rw = rows[j];
         lv[rw - lo] = zero;
-        le[rw - lo] = zero;
+        if constexpr (ELDS) le[rw - lo] = zero;
+        else a.e[rw] = zero;
         msk[j] = a.mask[rw] != 0;
         if (!msk[j]) {
             dinv[j] = (T)1 / a.diag[rw];
@@ -871,10 +876,11 @@ k_pcg(CGArgs<T> a) {
         for (int j = 0; j < R; ++j) {
             if (!valid[j] || msk[j]) continue;
             const V2 p = lv[rows[j] - lo];
-            V2 ev = le[rows[j] - lo];
+            V2 ev = ELDS ? le[rows[j] - lo] : a.e[rows[j]];
             ev.x += ax * p.x;
             ev.y += ay * p.y;
-            le[rows[j] - lo] = ev;
+            if constexpr (ELDS) le[rows[j] - lo] = ev;
+            else a.e[rows[j]] = ev;
             r[j].x -= ax * q[j].x;
             r[j].y -= ay * q[j].y;
             if (spai) continue;
@@ -971,7 +977,7 @@ k_pcg(CGArgs<T> a) {
     // the correction leaves through plain stores (read by the next kernel)
 #pragma unroll
     for (int j = 0; j < R; ++j)
-        if (valid[j]) a.e[rows[j]] = le[rows[j] - lo];
+        if (ELDS && valid[j]) a.e[rows[j]] = le[rows[j] - lo];
     if (leader) {
         a.iters[sub] = it;
         a.status[sub] = stat;
@@ -1971,7 +1977,7 @@ Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
 struct PcgCfg {
     int blk, R, stream;
 };
-static const PcgCfg kPcgCfgs[] = {{256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 8, 0}, {512, 1, 0},
+static const PcgCfg kPcgCfgs[] = {{256, 1, 0}, {256, 2, 0}, {256, 4, 0}, {256, 6, 0}, {256, 8, 0}, {512, 1, 0},
                                   {512, 2, 0}, {512, 4, 0}, {1024, 1, 0}, {1024, 2, 0}};
 
 template <typename T>
@@ -1987,6 +1993,7 @@ static const void* pcg_kernel(int blk, int R) {
             case 1: return reinterpret_cast<const void*>(&k_pcg<T, 256, 1>);
             case 2: return reinterpret_cast<const void*>(&k_pcg<T, 256, 2>);
             case 4: return reinterpret_cast<const void*>(&k_pcg<T, 256, 4>);
+            case 6: return reinterpret_cast<const void*>(&k_pcg<T, 256, 6>);
             default: return reinterpret_cast<const void*>(&k_pcg<T, 256, 8>);
         }
     }
@@ -2163,14 +2170,14 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         const size_t vsz = prec == 0 ? 16 : 8;
         // two-barrier kernel: p and the SPAI operand (own rows + ring 1 each), e (own rows)
         lds_n = own + max_n1;
-        lds_bytes = (size_t)(2 * lds_n + own) * vsz;
+        lds_bytes = (size_t)(2 * lds_n + (own <= 1024 ? own : 0)) * vsz;   // e in LDS up to 1024 rows
         // local columns are 16-bit; a shape whose workgroup has more entries does not fit
         if (lds_n > 65536 || lds_bytes + 4096 > (size_t)lds_max) return Error{PGCP_OK, ""};
         // single-reduction kernel: r (own rows + both rings), u (own rows + ring 1), e
         lds_nr = own + max_nh;
         lds_nu = own + max_n1;
         lds1_bytes = (size_t)(lds_nr + lds_nu + own) * vsz;
-        cg1 = L.rings_ok && lds_nr <= 65536 && lds1_bytes + 4096 <= (size_t)lds_max;
+        cg1 = L.rings_ok && lds_nr <= 65536 && lds1_bytes + 4096 <= (size_t)lds_max && cfg.R != 6;
     }
     int per_cu = 0;
     const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
@@ -2975,7 +2982,8 @@ Error assembled_ok(pgcp_ctx* ctx, pgcp_part* P) {
 
 namespace pgcp {
 
-// Copy one piece's FP64 matrix back to host CSR (local indices, diagonal included).
+// Copy one piece's FP64 matrix back to host CSR (local indices = ranks of the
+// global vertices, diagonal included).
 Error export_laplacian(pgcp_ctx* ctx, const pgcp_part* P, int piece, int32_t* rowptr, int32_t* col, double* val) {
     const int32_t r0 = P->row0[piece];
     const int32_t n = P->sub_nv[piece];
@@ -2987,24 +2995,28 @@ Error export_laplacian(pgcp_ctx* ctx, const pgcp_part* P, int piece, int32_t* ro
     HIPCHK(hipMemcpyAsync(dg.data(), (const double*)P->d_diag64.p + r0, (size_t)n * 8, hipMemcpyDeviceToHost,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<int32_t> by_rank, rank_of;
+    piece_global_order(P, piece, by_rank, rank_of);
     rowptr[0] = 0;
-    for (int32_t l = 0; l < n; ++l) {
+    std::vector<std::pair<int32_t, double>> ent;
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t l = by_rank[t];
         const int64_t r = r0 + l, s = r / 64;
         const int lane = (int)(r & 63);
-        std::vector<std::pair<int32_t, double>> ent;
-        ent.emplace_back(l, dg[l]);
+        ent.clear();
+        ent.emplace_back(t, dg[l]);
         for (int k = 0; k < P->sl_w[s]; ++k) {
             const int64_t el = P->sl_ptr[s] + (int64_t)k * 64 + lane;
             const int32_t c = P->sl_col[el];
             if (c == r) continue;   // padding slot
-            ent.emplace_back(c - r0, v[el - e0]);
+            ent.emplace_back(rank_of[c - r0], v[el - e0]);
         }
         std::sort(ent.begin(), ent.end());
-        rowptr[l + 1] = rowptr[l] + (int32_t)ent.size();
+        rowptr[t + 1] = rowptr[t] + (int32_t)ent.size();
         if (col && val) {
-            for (size_t t = 0; t < ent.size(); ++t) {
-                col[rowptr[l] + t] = ent[t].first;
-                val[rowptr[l] + t] = ent[t].second;
+            for (size_t q = 0; q < ent.size(); ++q) {
+                col[rowptr[t] + q] = ent[q].first;
+                val[rowptr[t] + q] = ent[q].second;
             }
         }
     }

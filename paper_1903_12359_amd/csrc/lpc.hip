@@ -1013,18 +1013,27 @@ Error lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int piece, double* o_off, do
     HIPCHK(hipMemcpyAsync(mv.data(), (const double*)P->d_mval64.p + e0, (e1 - e0) * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(md.data(), (const double*)P->d_mdiag64.p + r0, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    // rows and, within a row, columns by ascending global vertex
+    std::vector<int32_t> by_rank, rank_of;
+    piece_global_order(P, piece, by_rank, rank_of);
+    std::vector<std::pair<int32_t, int64_t>> ent;
     int64_t o = 0;
-    for (int32_t l = 0; l < n; ++l) {
+    for (int32_t t = 0; t < n; ++t) {
+        const int32_t l = by_rank[t];
         const int64_t r = r0 + l, sl = r / 64;
         const int lane = (int)(r & 63);
-        if (o_diag) o_diag[l] = ov[l];
-        if (m_diag) m_diag[l] = md[l];
-        // columns of a row are ascending in its slots
+        if (o_diag) o_diag[t] = ov[l];
+        if (m_diag) m_diag[t] = md[l];
+        ent.clear();
         for (int k = 0; k < P->sl_w[sl]; ++k) {
             const int64_t el = P->sl_ptr[sl] + (int64_t)k * 64 + lane;
             if (P->sl_col[el] == r) continue;
-            if (o_off) o_off[o] = oe[el - e0];
-            if (m_off) m_off[o] = mv[el - e0];
+            ent.emplace_back(rank_of[P->sl_col[el] - r0], el);
+        }
+        std::sort(ent.begin(), ent.end());
+        for (const auto& q : ent) {
+            if (o_off) o_off[o] = oe[q.second - e0];
+            if (m_off) m_off[o] = mv[q.second - e0];
             ++o;
         }
     }

@@ -41,6 +41,74 @@ struct UnionFind {
 
 Error topo(const std::string& m) { return Error{PGCP_E_TOPOLOGY, m}; }
 
+// Reverse Cuthill-McKee order of a piece's vertices (local indices, adjacency
+// in CSR): from a pseudo-peripheral vertex (the end of a second breadth-first
+// sweep), breadth-first with neighbours by increasing degree (ties by index),
+// reversed.  Rows in this order give each workgroup's contiguous range of rows
+// a compact patch of the mesh, hence a small halo (a k-means piece of a sphere
+// in global vertex order scatters a workgroup's rows over the whole piece).
+void rcm_order(int32_t n, const std::vector<int32_t>& ptr, const std::vector<int32_t>& adj,
+               std::vector<int32_t>& order) {
+    order.clear();
+    order.reserve(n);
+    std::vector<int32_t> stamp(n, -1), q, nb;
+    std::vector<char> done(n, 0);
+    q.reserve(n);
+    int32_t sweep = 0;
+    auto deg = [&](int32_t v) { return ptr[v + 1] - ptr[v]; };
+    auto bfs = [&](int32_t s) -> size_t {   // plain sweep over unplaced vertices; start of its last level
+        q.clear();
+        q.push_back(s);
+        stamp[s] = ++sweep;
+        size_t head = 0, last = 0;
+        while (head < q.size()) {
+            const size_t end = q.size();
+            last = head;
+            for (; head < end; ++head) {
+                const int32_t v = q[head];
+                for (int32_t t = ptr[v]; t < ptr[v + 1]; ++t) {
+                    const int32_t u = adj[t];
+                    if (!done[u] && stamp[u] != sweep) {
+                        stamp[u] = sweep;
+                        q.push_back(u);
+                    }
+                }
+            }
+        }
+        return last;
+    };
+    auto pick = [&](size_t from) {   // smallest degree, then index, among q[from..]
+        int32_t best = q[from];
+        for (size_t t = from; t < q.size(); ++t) {
+            const int32_t v = q[t];
+            if (deg(v) < deg(best) || (deg(v) == deg(best) && v < best)) best = v;
+        }
+        return best;
+    };
+    for (int32_t s0 = 0; s0 < n; ++s0) {
+        if (done[s0]) continue;
+        int32_t s = pick(bfs(s0));
+        s = pick(bfs(s));
+        const size_t first = order.size();
+        order.push_back(s);
+        done[s] = 1;
+        for (size_t h = first; h < order.size(); ++h) {
+            const int32_t v = order[h];
+            nb.clear();
+            for (int32_t t = ptr[v]; t < ptr[v + 1]; ++t)
+                if (!done[adj[t]]) nb.push_back(adj[t]);
+            std::sort(nb.begin(), nb.end(),
+                      [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; });
+            for (int32_t u : nb)
+                if (!done[u]) {
+                    done[u] = 1;
+                    order.push_back(u);
+                }
+        }
+        std::reverse(order.begin() + (int64_t)first, order.end());
+    }
+}
+
 }  // namespace
 
 Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, int64_t nf,
@@ -139,13 +207,16 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     P->sub_nf.resize(K);
     for (int i = 0; i < K; ++i) P->sub_nf[i] = (int32_t)(fptr[i + 1] - fptr[i]);
 
-    // vertices of each piece (sorted), packed rows padded to 64
+    // vertices of each piece, in reverse Cuthill-McKee order (ties and
+    // starting sweeps by ascending global index), packed rows padded to 64
     std::vector<std::vector<int32_t>> verts(K);
     Error err{PGCP_OK, ""};
 #pragma omp parallel
     {
-        // a thread's vertex stamps: the piece (+1) that last collected it
-        std::vector<int32_t> seen(nv, 0);
+        // a thread's vertex stamps (the piece + 1 that last collected it) and
+        // global -> local map
+        std::vector<int32_t> seen(nv, 0), loc(nv);
+        std::vector<int32_t> ptr, adj, fill, order;
 #pragma omp for schedule(dynamic)
         for (int i = 0; i < K; ++i) {
             auto& vv = verts[i];
@@ -159,6 +230,38 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
                     }
                 }
             std::sort(vv.begin(), vv.end());
+            const int32_t n = (int32_t)vv.size();
+            for (int32_t l = 0; l < n; ++l) loc[vv[l]] = l;
+            // the piece's vertex graph (each face side once per direction), CSR
+            ptr.assign(n + 1, 0);
+            for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t)
+                for (int c = 0; c < 3; ++c) ptr[loc[F[3 * (int64_t)faces[t] + c]] + 1] += 2;
+            for (int32_t l = 0; l < n; ++l) ptr[l + 1] += ptr[l];
+            adj.resize(ptr[n]);
+            fill.assign(ptr.begin(), ptr.end() - 1);
+            for (int64_t t = fptr[i]; t < fptr[i + 1]; ++t) {
+                const int64_t f = faces[t];
+                for (int c = 0; c < 3; ++c) {
+                    const int32_t a = loc[F[3 * f + c]], b = loc[F[3 * f + (c + 1) % 3]];
+                    adj[fill[a]++] = b;
+                    adj[fill[b]++] = a;
+                }
+            }
+            // sort and drop repeated neighbours in place, then compact
+            int32_t w = 0;
+            for (int32_t l = 0; l < n; ++l) {
+                const int32_t b0 = ptr[l], b1 = ptr[l + 1];
+                std::sort(adj.begin() + b0, adj.begin() + b1);
+                const int32_t start = w;
+                for (int32_t t = b0; t < b1; ++t)
+                    if (t == b0 || adj[t] != adj[t - 1]) adj[w++] = adj[t];
+                ptr[l] = start;
+            }
+            ptr[n] = w;
+            rcm_order(n, ptr, adj, order);
+            std::vector<int32_t> ordered(n);
+            for (int32_t l = 0; l < n; ++l) ordered[l] = vv[order[l]];
+            vv.swap(ordered);
         }
     }
     P->sub_nv.resize(K);
@@ -233,8 +336,9 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
             emsg[i] = "piece " + std::to_string(i) + " has no boundary";
             continue;
         }
-        int32_t start = 0;
-        while (nxt[start] < 0) start++;   // smallest local index = smallest global index
+        int32_t start = -1;   // the boundary vertex of smallest global index
+        for (int32_t l = 0; l < n; ++l)
+            if (nxt[l] >= 0 && (start < 0 || verts[i][l] < verts[i][start])) start = l;
         std::vector<int32_t>& L = loops[i];
         int32_t v = start;
         do {

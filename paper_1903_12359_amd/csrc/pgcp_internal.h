@@ -1,6 +1,7 @@
 // Internal declarations shared by the host (C++) and device (HIP) parts of libpgcp.
 #pragma once
 
+#include <algorithm>
 #include <complex>
 #include <array>
 #include <map>
@@ -205,6 +206,20 @@ int shared_arc(const std::vector<int>& la, const std::vector<int>& lb, int* star
 Error merge_plan(const std::vector<std::vector<int>>& loops, const std::vector<int64_t>& sizes,
                  int mode, std::vector<std::vector<std::pair<int, int>>>* rounds);
 Error weld_all(pgcp_part* part, const double* bdy_uv, double* welded_uv);
+
+// A piece's packed rows by ascending global vertex: row row0 + by_rank[t]
+// holds the piece's t-th smallest global vertex, rank_of is the inverse.  The
+// exports list a piece in this order whatever order its rows are packed in.
+inline void piece_global_order(const pgcp_part* P, int piece, std::vector<int32_t>& by_rank,
+                               std::vector<int32_t>& rank_of) {
+    const int32_t r0 = P->row0[piece], n = P->sub_nv[piece];
+    by_rank.resize(n);
+    rank_of.resize(n);
+    for (int32_t l = 0; l < n; ++l) by_rank[l] = l;
+    std::sort(by_rank.begin(), by_rank.end(),
+              [&](int32_t a, int32_t b) { return P->row_gv[r0 + a] < P->row_gv[r0 + b]; });
+    for (int32_t t = 0; t < n; ++t) rank_of[by_rank[t]] = t;
+}
 
 // device side (device.hip)
 Error upload_plan(pgcp_ctx* ctx, pgcp_part* part);

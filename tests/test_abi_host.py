@@ -131,3 +131,55 @@ def test_single_piece_weld_is_identity_and_disk_circle():
     plan = pg.Plan(None, case.V, case.F, case.label, "disk")
     w = pg.weld(None, plan, bh)
     assert np.abs(np.hypot(w[:, 0], w[:, 1]) - 1).max() < 1e-12
+
+
+def _piece_graph(s):
+    """Vertex adjacency of one oracle piece (local = ascending global index) as CSR."""
+    import scipy.sparse as sp
+    T = np.asarray(s["T"])
+    n = len(s["verts"])
+    a = np.concatenate([T[:, 0], T[:, 1], T[:, 2], T[:, 1], T[:, 2], T[:, 0]])
+    b = np.concatenate([T[:, 1], T[:, 2], T[:, 0], T[:, 0], T[:, 1], T[:, 2]])
+    return sp.csr_matrix((np.ones(a.size), (a, b)), shape=(n, n))
+
+
+def _max_halo(order, G, block=1024):
+    """Largest number of distinct vertices outside a block of `block`
+    consecutive rows that the block's rows are adjacent to."""
+    pos = np.empty(len(order), np.int64)
+    pos[order] = np.arange(len(order))
+    worst = 0
+    for b0 in range(0, len(order), block):
+        rows = order[b0:b0 + block]
+        nb = np.unique(G[rows].indices)
+        worst = max(worst, int(np.count_nonzero((pos[nb] < b0) | (pos[nb] >= b0 + block))))
+    return worst
+
+
+@pytest.mark.parametrize("make", CASES + [lambda: small_sphere_case(6, 4, seed=3)])
+def test_row_order_is_reverse_breadth_first(make):
+    """A piece's packed rows hold exactly its vertices in reverse Cuthill-McKee
+    order: read backwards they list the piece's graph level by level from the
+    first one (breadth-first distances never decrease).  On k-means sphere
+    pieces a 1,024-row block's halo is smaller than in global order."""
+    import scipy.sparse.csgraph as csg
+    _lib()
+    case = make()
+    plan = pg.Plan(None, case.V, case.F, case.label, case.mode)
+    row0, gv = plan.rows(), plan.row_vertices()
+    part, subs = prepare(case.V, case.F, case.label)
+    assert gv.shape == (row0[-1],)
+    for i, s in enumerate(subs):
+        verts = np.asarray(s["verts"])
+        n = len(verts)
+        piece = gv[row0[i]:row0[i + 1]]
+        assert np.array_equal(np.sort(piece[:n]), np.sort(verts)), i
+        assert (piece[n:] == -1).all()
+        local = np.searchsorted(np.sort(verts), piece[:n])   # packed row -> oracle local index
+        G = _piece_graph(s)
+        d = csg.shortest_path(G, unweighted=True, indices=int(local[-1]))
+        assert np.isfinite(d).all(), i
+        assert (np.diff(d[local[::-1]]) >= 0).all(), i
+        if n >= 4096 and case.mode == "sphere":
+            h_rcm, h_glob = _max_halo(local, G), _max_halo(np.arange(n), G)
+            assert h_rcm < h_glob, (i, h_rcm, h_glob)

@@ -145,12 +145,14 @@ def _probes(plan, n_probes, seed):
 
 def _probe_batch(plan, V, case, system):
     """The oracle's batch for the same probes: per piece (G, A, V restricted to the piece's rows)."""
-    row0 = plan.rows()
+    row0, gv = plan.rows(), plan.row_vertices()
     Vh = V.cpu().numpy().astype(np.float64)
     batch = []
     for i, pm in enumerate(piece_masks(case)):
         n = pm["L"].shape[0]
-        Vi = Vh[:, row0[i]:row0[i] + n].T.copy()
+        # the oracle numbers a piece's vertices by ascending global index
+        rows = row0[i] + np.argsort(gv[row0[i]:row0[i] + n], kind="stable")
+        Vi = Vh[:, rows].T.copy()
         Vi[pm[system]] = 0.0
         batch.append((olpc.graph(pm["L"], pm[system]), olpc.system(pm["L"], pm[system]), Vi))
     return batch

@@ -89,6 +89,39 @@ def test_assembly_matches_oracle(ctx, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_row_order_is_reverse_breadth_first(ctx, name):
+    """Each piece's packed rows hold exactly its vertices (padding rows -1), in
+    reverse Cuthill-McKee order: read backwards, the rows list the piece's
+    vertex graph level by level from the first one (breadth-first distances
+    never decrease), so a workgroup's consecutive rows form a compact patch."""
+    import scipy.sparse.csgraph as csg
+    import paper_1903_12359_amd as pg
+    case = CASES[name]()
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    part, subs = prepare(case.V, case.F, case.label)
+    row0, gv = plan.rows(), plan.row_vertices()
+    assert gv.shape == (row0[-1],)
+    for i, s in enumerate(subs):
+        n = len(s["verts"])
+        piece = gv[row0[i]:row0[i + 1]]
+        assert np.array_equal(np.sort(piece[:n]), np.sort(np.asarray(s["verts"]))), (name, i)
+        assert (piece[n:] == -1).all()
+        L = plan.laplacian(i).tocsr()            # ascending global order
+        G = L.copy()
+        G.data = np.ones_like(G.data)            # the pattern (cotangent weights may be 0)
+        rank = np.searchsorted(np.sort(piece[:n]), piece[:n][::-1])
+        d = csg.shortest_path(G, unweighted=True, indices=int(rank[0]))
+        assert np.isfinite(d).all(), (name, i)
+        assert (np.diff(d[rank]) >= 0).all(), (name, i)
+        coo = L.tocoo()
+        pos = np.empty(n, np.int64)
+        pos[np.argsort(piece[:n], kind="stable")] = np.arange(n)
+        say("row order", name, i, "bandwidth global", int(np.abs(coo.row - coo.col).max()),
+            "packed", int(np.abs(pos[coo.row] - pos[coo.col]).max()))
+
+
+@pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
 def test_dncp_matches_oracle(ctx, name, prec, tol, bound):
     import paper_1903_12359_amd as pg
@@ -210,7 +243,7 @@ def test_call_order_errors(ctx):
     assert ei.value.status == "INVALID"
 
 
-@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,8", "256,1,1", "256,4,1", "512,2,1",
+@pytest.mark.parametrize("cfg", ["256,1", "256,2", "512,1", "1024,1", "256,6", "256,8", "512,4", "256,1,1", "256,4,1", "512,2,1",
                                  "256,0,1", "512,0,1"])
 def test_forced_launch_shapes(ctx, cfg, monkeypatch):
     """Every launch shape (register-resident, or streaming when the third field
