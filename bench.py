@@ -53,20 +53,25 @@ HBM_PEAK_GBS = 8000.0
 
 # Per-launch HBM traffic of k_pcg (FETCH_SIZE x2.0 + WRITE_SIZE x1.0 from
 # rocprofv3 counter passes over one timed step, scale factors from a 256 MiB
-# copy), for the kernel source and launch shapes it was measured with; the
-# summary and commands are in profiles/k_pcg_C2_512x512_16pieces.md.
+# copy), for the kernel and partition sources and launch shapes it was
+# measured with; the summary and commands are in
+# profiles/k_pcg_C2_512x512_16pieces.md.
 TRAFFIC = {
     "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "d51a100c91b72cc6aaa36c723909bc120c7fd91d9ce6a2c32c32f2aa97aee9b3",
+           "source_sha256": "fc5285c87699e94fd153a2ade192e4d71f9e85c42229fcb514ed8a8930d0b3c0",
            "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "256,4,0,0"},
-           "bytes_per_launch": 9.980e9},
+           "bytes_per_launch": 6.914e9},
 }
 
 
 def kernel_source_sha():
+    """SHA-256 over the CG kernel's source and the partition that lays out its rows."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_1903_12359_amd", "csrc", "device.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("device.hip", "partition.cpp"):
+        with open(os.path.join(ROOT, "paper_1903_12359_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def make_case(name):
