@@ -9,6 +9,7 @@
  *   pgcp_weld            Sections 4.3, 4.4   partial welding (+ disk / sphere step)
  *   pgcp_harmonic_solve  Section 4.5   Laplace equation with the welded boundary
  *   pgcp_distortion      Sections 3.5, 5   angle distortion, Beltrami |mu|, flips
+ *   pgcp_area_*          Section 6     area distortion and its Moebius post-optimisation
  *
  * Conventions
  *  - Plain C types only; no exceptions cross this boundary.  Every call returns
@@ -235,6 +236,39 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                             const int32_t* F_dev, int64_t nf, const double* param_dev,
                             int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats);
+
+/* Section 6, area distortion.  Per face
+ *   d_area(T) = log[(A(phi(T)) / sum A(phi)) / (A(T) / sum A)],
+ * A the area of the flat triangle through the face's points (in R^3 for the
+ * mesh and for spherical parameterizations).  V_dev [nv][3], F_dev [nf][3]
+ * (indices < nv, not checked), param_dev [nv][dim], dim 2 or 3; d_dev [nf]
+ * may be NULL; *mean_abs = mean of |d_area|.  A zero-area or non-finite
+ * triangle of the mesh is PGCP_E_DEGENERATE; one of the parameterization
+ * makes *mean_abs +inf.  Synchronous. */
+pgcp_status pgcp_area_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
+                                 const int32_t* F_dev, int64_t nf, const double* param_dev,
+                                 int32_t dim, double* d_dev, double* mean_abs);
+/* Section 6, area distortion: mean |d_area| of param composed with a Moebius
+ * map.  mode PGCP_FREE (dim 2): f(z) = (a z + b)/(c z + d), mobius[8] = Re a,
+ * Im a, Re b, Im b, Re c, Im c, Re d, Im d.  PGCP_DISK (dim 2): f(z) = (z -
+ * alpha)/(1 - conj(alpha) z), mobius[2] = Re alpha, Im alpha.  PGCP_SPHERE
+ * (dim 3): sigma^-1 o f o sigma with the eight-parameter f and sigma(p) =
+ * (x - i y)/(1 - z).  Parameters with ad - bc = 0 or |alpha| >= 1 give +inf.
+ * Synchronous. */
+pgcp_status pgcp_area_objective(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
+                                const int32_t* F_dev, int64_t nf, const double* param_dev,
+                                int32_t dim, int32_t mode, const double* mobius, double* value);
+/* Section 6, area distortion: the Moebius map of the mode (as in
+ * pgcp_area_objective) minimising mean |d_area|, by Nelder-Mead from the
+ * identity (initial simplex of step 0.1 per parameter) with at most max_evals
+ * evaluations on the device.  Writes the parameters to mobius[8] (mobius[2]
+ * for the disk), the objective at the identity and at the result, the number
+ * of evaluations (n_evals may be NULL) and, if out_dev is not NULL, the
+ * composed parameterization out_dev [nv][dim].  Synchronous. */
+pgcp_status pgcp_area_mobius_opt(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
+                                 const int32_t* F_dev, int64_t nf, const double* param_dev,
+                                 int32_t dim, int32_t mode, int32_t max_evals, double* mobius,
+                                 double* before, double* after, int32_t* n_evals, double* out_dev);
 
 /* ---------------------------------------------------------------------------
  * Learned sparse approximate inverse (the GPU path's preconditioner; the paper

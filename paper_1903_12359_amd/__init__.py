@@ -64,7 +64,7 @@ EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_s
            "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion",
            "pgcp_lpc_num_params", "pgcp_lpc_create", "pgcp_lpc_get_params", "pgcp_lpc_destroy", "pgcp_lpc_infer",
            "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows",
-           "pgcp_part_row_vertices"]
+           "pgcp_part_row_vertices", "pgcp_area_distortion", "pgcp_area_objective", "pgcp_area_mobius_opt"]
 PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
 SYSTEMS = {"dncp": 0, "harmonic": 1}
 
@@ -105,6 +105,9 @@ def load_library(path: str = LIB_PATH):
         "pgcp_lpc_train_step": (I32, [P, P, P, I32, P, I32, ctypes.c_float, ctypes.POINTER(D)]),
         "pgcp_part_rows": (I32, [P, P]),
         "pgcp_part_row_vertices": (I32, [P, P]),
+        "pgcp_area_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P]),
+        "pgcp_area_objective": (I32, [P, P, I64, P, I64, P, I32, I32, P, P]),
+        "pgcp_area_mobius_opt": (I32, [P, P, I64, P, I64, P, I32, I32, I32, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -420,6 +423,41 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
                                       ctypes.byref(st) if stats else None))
     out = {k: getattr(st, k) for k, _ in DistStats._fields_} if stats else None
     return out, d, mu, flip
+
+
+def area_distortion(ctx: Context, V_dev, F_dev, param_dev, want_d=False):
+    """Section 6: mean |d_area| of the parameterization (and d_area per face)."""
+    import torch
+    nf = F_dev.shape[0]
+    d = torch.empty(nf, dtype=torch.float64, device=f"cuda:{ctx.device}") if want_d else None
+    m = ctypes.c_double()
+    ctx.check(ctx.lib.pgcp_area_distortion(ctx.h, _ptr(V_dev), V_dev.shape[0], _ptr(F_dev), nf, _ptr(param_dev),
+                                           param_dev.shape[1], _ptr(d), ctypes.byref(m)))
+    return m.value, d
+
+
+def area_objective(ctx: Context, V_dev, F_dev, param_dev, mode, mobius):
+    """Section 6: mean |d_area| of the parameterization composed with a Moebius map."""
+    p = np.ascontiguousarray(mobius, dtype=np.float64)
+    v = ctypes.c_double()
+    ctx.check(ctx.lib.pgcp_area_objective(ctx.h, _ptr(V_dev), V_dev.shape[0], _ptr(F_dev), F_dev.shape[0],
+                                          _ptr(param_dev), param_dev.shape[1], MODES[mode], _ptr(p),
+                                          ctypes.byref(v)))
+    return v.value
+
+
+def area_mobius_opt(ctx: Context, V_dev, F_dev, param_dev, mode, max_evals=400, want_map=False):
+    """Section 6: the Moebius map minimising mean |d_area| (Nelder-Mead on the device's objective).
+
+    Returns (parameters, before, after, evaluations, composed map or None)."""
+    import torch
+    p = np.zeros(2 if mode == "disk" else 8, np.float64)
+    b, a, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    Y = torch.empty_like(param_dev) if want_map else None
+    ctx.check(ctx.lib.pgcp_area_mobius_opt(ctx.h, _ptr(V_dev), V_dev.shape[0], _ptr(F_dev), F_dev.shape[0],
+                                           _ptr(param_dev), param_dev.shape[1], MODES[mode], int(max_evals),
+                                           _ptr(p), ctypes.byref(b), ctypes.byref(a), ctypes.byref(n), _ptr(Y)))
+    return p, b.value, a.value, n.value, Y
 
 
 def run_stream(ctx: Context, cases, lanes: int = 1, **kw):

@@ -26,7 +26,7 @@ DEVICE_FLAGS = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang
 HOST_SOURCES = ["partition.cpp", "weld.cpp", "api.cpp"]
 HOST_EXTRA = {"weld.cpp": ["-fcx-limited-range"]}
 DEVICE_EXTRA = {"weld_dev.hip": ["-fcx-limited-range"]}
-DEVICE_SOURCES = ["device.hip", "lpc.hip", "weld_dev.hip"]
+DEVICE_SOURCES = ["device.hip", "lpc.hip", "weld_dev.hip", "area.hip"]
 
 
 def _hipcc():

@@ -208,6 +208,53 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, cons
                                           want_quantiles, stats));
 }
 
+static pgcp_status area_args(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
+                             const double* X, int32_t dim) {
+    if (!ctx || !V || !F || !X) return bad(ctx, "null argument");
+    if (dim != 2 && dim != 3) return bad(ctx, "dim must be 2 or 3");
+    if (nf <= 0 || nv <= 0) return bad(ctx, "empty mesh");
+    return PGCP_OK;
+}
+
+static pgcp_status area_mode(pgcp_ctx* ctx, int32_t mode, int32_t dim) {
+    if (mode != PGCP_FREE && mode != PGCP_DISK && mode != PGCP_SPHERE) return bad(ctx, "unknown mode");
+    if ((mode == PGCP_SPHERE) != (dim == 3)) return bad(ctx, "sphere mode takes dim 3, free and disk dim 2");
+    return PGCP_OK;
+}
+
+pgcp_status pgcp_area_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
+                                 const double* param_dev, int32_t dim, double* d_dev, double* mean_abs) {
+    pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
+    if (r != PGCP_OK) return r;
+    if (!mean_abs) return bad(ctx, "null argument");
+    pgcp::AllocScope scope(ctx->stream);
+    return fail(ctx, pgcp::run_area_distortion(ctx, V_dev, F_dev, nf, param_dev, dim, d_dev, mean_abs));
+}
+
+pgcp_status pgcp_area_objective(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
+                                const double* param_dev, int32_t dim, int32_t mode, const double* mobius,
+                                double* value) {
+    pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
+    if (r != PGCP_OK) return r;
+    if ((r = area_mode(ctx, mode, dim)) != PGCP_OK) return r;
+    if (!mobius || !value) return bad(ctx, "null argument");
+    pgcp::AllocScope scope(ctx->stream);
+    return fail(ctx, pgcp::run_area_objective(ctx, V_dev, F_dev, nf, param_dev, mode, mobius, value));
+}
+
+pgcp_status pgcp_area_mobius_opt(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
+                                 const double* param_dev, int32_t dim, int32_t mode, int32_t max_evals,
+                                 double* mobius, double* before, double* after, int32_t* n_evals, double* out_dev) {
+    pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
+    if (r != PGCP_OK) return r;
+    if ((r = area_mode(ctx, mode, dim)) != PGCP_OK) return r;
+    if (!mobius || !before || !after) return bad(ctx, "null argument");
+    if (max_evals < 1) return bad(ctx, "max_evals must be positive");
+    pgcp::AllocScope scope(ctx->stream);
+    return fail(ctx, pgcp::run_area_mobius_opt(ctx, V_dev, nv, F_dev, nf, param_dev, mode, max_evals, mobius, before,
+                                               after, n_evals, out_dev));
+}
+
 }  // extern "C"
 
 extern "C" {

@@ -236,4 +236,13 @@ Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* 
                      const double* X, int dim, double* d, double* mu, uint8_t* flip, int want_q,
                      pgcp_dist_stats* st);
 
+// area distortion (area.hip)
+Error run_area_distortion(pgcp_ctx* ctx, const double* V, const int32_t* F, int64_t nf, const double* X, int dim,
+                          double* d, double* mean_abs);
+Error run_area_objective(pgcp_ctx* ctx, const double* V, const int32_t* F, int64_t nf, const double* X, int mode,
+                         const double* params, double* value);
+Error run_area_mobius_opt(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, const double* X,
+                          int mode, int max_evals, double* params, double* before, double* after, int32_t* n_evals,
+                          double* Y);
+
 }  // namespace pgcp
