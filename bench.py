@@ -180,14 +180,33 @@ def time_variant(pg, ctx, case, V_dev, F_dev, args, lpc, steps=None, pipeline=Tr
             cg_launch += rep.cg_launches
             iters += rep.total_iters
             fallback += rep.n_fallback
-        last = (st, info)
+        last = (st, info, phi)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     ms_per_step = 1e3 * elapsed / steps
-    st, info = last
+    st, info, phi = last
     return dict(ms_per_step=ms_per_step, value=case.nv / (ms_per_step / 1e3) / 1e6, cg_ms=cg_ms,
                 cg_bytes=cg_bytes, cg_launch=cg_launch, iters=iters // steps, fallback=fallback,
-                stage={k: round(1e3 * v / steps, 3) for k, v in stage.items()}, st=st, info=info)
+                stage={k: round(1e3 * v / steps, 3) for k, v in stage.items()}, st=st, info=info, phi=phi)
+
+
+def area_record(pg, ctx, V_dev, F_dev, phi, mode, max_evals=400):
+    """Section 6 after the step: the Moebius map of the mode that minimises the
+    mean area distortion of the step's output (Nelder-Mead, one device
+    evaluation per step), timed apart from the steps.  Algorithmic bytes of one
+    evaluation: 36 per face (face indices, the log image area written and read
+    back, the log original area) + 8 per coordinate of each vertex read."""
+    import torch
+    nv, nf, dim = phi.shape[0], F_dev.shape[0], phi.shape[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p, before, after, evals, _ = pg.area_mobius_opt(ctx, V_dev, F_dev, phi.contiguous(), mode, max_evals=max_evals)
+    ms = 1e3 * (time.perf_counter() - t0)
+    per_eval = ms / max(evals, 1)
+    b = 36 * nf + 8 * dim * nv
+    return {"mean_abs_d_area_before": before, "mean_abs_d_area_after": after, "evals": evals,
+            "ms": round(ms, 3), "ms_per_eval": round(per_eval, 4), "algorithmic_bytes_per_eval": b,
+            "achieved_GBs": round(b / (per_eval / 1e3) / 1e9, 1), "parameters": [round(float(x), 6) for x in p]}
 
 
 def main():
@@ -307,6 +326,7 @@ def main():
                              "steps": min(args.steps, 4), "stages_ms": seq["stage"]}
     if lpc_info is not None:
         rec["lpc_training"] = lpc_info
+    rec["area_mobius"] = area_record(pg, ctx, V_dev, F_dev, head["phi"], case.mode)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle (one thread) on the same mesh", file=sys.stderr, flush=True)
         cb = cpu_baseline(args.workload)
