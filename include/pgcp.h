@@ -260,8 +260,9 @@ pgcp_status pgcp_area_objective(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                                 int32_t dim, int32_t mode, const double* mobius, double* value);
 /* Section 6, area distortion: the Moebius map of the mode (as in
  * pgcp_area_objective) minimising mean |d_area|, by Nelder-Mead from the
- * identity (initial simplex of step 0.1 per parameter) with at most max_evals
- * evaluations on the device.  Writes the parameters to mobius[8] (mobius[2]
+ * identity (initial simplex of step 0.1 per parameter), one evaluation on the
+ * device per objective value; no step starts once max_evals evaluations have
+ * been made (the last step adds at most n + 1, n = 8 or 2).  Writes the parameters to mobius[8] (mobius[2]
  * for the disk), the objective at the identity and at the result, the number
  * of evaluations (n_evals may be NULL) and, if out_dev is not NULL, the
  * composed parameterization out_dev [nv][dim].  Synchronous. */
