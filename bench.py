@@ -74,8 +74,12 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def make_case(name):
+def make_case(name, blocks=None):
     from synth import case_c1, case_c2, case_c3, case_c5
+    if blocks is not None:
+        if name != "c2":
+            raise SystemExit("--blocks applies to the c2 workload only")
+        return case_c2(blocks=blocks)
     return {"c1": case_c1, "c2": case_c2, "c3": case_c3, "c5": case_c5}[name]()
 
 
@@ -217,6 +221,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--blocks", type=int, default=None,
+                    help="c2 only: cut the height field into blocks x blocks pieces (default 4: 16 pieces)")
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
     ap.add_argument("--lpc-steps", type=int, default=500, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--lpc-set", default="c4", choices=["c4", "small"],
@@ -241,7 +247,7 @@ def main():
     pg.load_library()
     dev = "cuda:0"
     t0 = time.perf_counter()
-    case = make_case(args.workload)
+    case = make_case(args.workload, args.blocks)
     print(f"[bench] workload {case.name}: nv={case.nv} nf={case.nf} ({time.perf_counter() - t0:.1f}s to generate)",
           file=sys.stderr, flush=True)
     V_dev = torch.from_numpy(case.V).to(dev)
@@ -327,7 +333,7 @@ def main():
     if lpc_info is not None:
         rec["lpc_training"] = lpc_info
     rec["area_mobius"] = area_record(pg, ctx, V_dev, F_dev, head["phi"], case.mode)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.blocks is None:
         print("[bench] timing the CPU oracle (one thread) on the same mesh", file=sys.stderr, flush=True)
         cb = cpu_baseline(args.workload)
         if cb is not None:
