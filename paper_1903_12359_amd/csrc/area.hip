@@ -140,12 +140,14 @@ __global__ void __launch_bounds__(BLOCK) k_area_abs(int64_t nf, const double* __
     block_sum(v, part + blockIdx.x);
 }
 
-// out[0] = sum of part[0..n) in a fixed order (one workgroup)
+// out[0] = sum of part[0..n) in a fixed order (one workgroup); clears *clear
+// (the flag the next evaluation will set) when given
 __global__ void __launch_bounds__(BLOCK) k_area_sum(int64_t n, const double* __restrict__ part,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, int* __restrict__ clear) {
     double v = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += BLOCK) v += part[i];
     block_sum(v, out);
+    if (clear && threadIdx.x == 0) *clear = 0;
 }
 
 __global__ void __launch_bounds__(BLOCK) k_area_apply(int64_t nv, const double* __restrict__ X, int sphere, Mob m,
@@ -173,14 +175,22 @@ bool admissible(int mode, const double* p) {
     return dr != 0.0 || di != 0.0;
 }
 
-// Device state of one area computation on one mesh.
+// Device state of one area computation on one mesh.  stat holds the totals
+// (sum A, sum A(f), sum |d_area|) and two bad-area flags: evaluation k sets
+// flag k % 2 and its last kernel clears the other, so no evaluation needs a
+// separate clear, and one copy brings totals and flag back.
+struct Stat {
+    double tot[3];
+    int bad[2];
+};
+
 struct AreaWork {
     pgcp_ctx* ctx;
-    int64_t nf, nblk;
+    int64_t nf, nblk, k = 0;
     const double* X;
     const int32_t* F;
     int sphere;
-    DevBuf logA, logAf, part, tot, badb;
+    DevBuf logA, logAf, part, statb;
     Error init(pgcp_ctx* c, const double* V, const int32_t* Fd, int64_t n, const double* Xd, int sph) {
         ctx = c; nf = n; F = Fd; X = Xd; sphere = sph;
         nblk = (nf + BLOCK - 1) / BLOCK;
@@ -188,41 +198,42 @@ struct AreaWork {
         if ((e = dev_alloc(logA, nf * 8)).code) return e;
         if ((e = dev_alloc(logAf, nf * 8)).code) return e;
         if ((e = dev_alloc(part, nblk * 8)).code) return e;
-        if ((e = dev_alloc(tot, 3 * 8)).code) return e;
-        if ((e = dev_alloc(badb, 4)).code) return e;
+        if ((e = dev_alloc(statb, sizeof(Stat))).code) return e;
         hipStream_t s = ctx->stream;
-        HIPCHK(hipMemsetAsync(badb.p, 0, 4, s));
-        k_area_src<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, V, F, (double*)logA.p, (double*)part.p, (int*)badb.p);
-        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, (double*)tot.p);
+        Stat* st = (Stat*)statb.p;
+        HIPCHK(hipMemsetAsync(statb.p, 0, sizeof(Stat), s));
+        k_area_src<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, V, F, (double*)logA.p, (double*)part.p, &st->bad[0]);
+        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, &st->tot[0], &st->bad[1]);
         HIPCHK(hipGetLastError());
-        int bad = 0;
-        HIPCHK(hipMemcpyAsync(&bad, badb.p, 4, hipMemcpyDeviceToHost, s));
+        Stat h;
+        HIPCHK(hipMemcpyAsync(&h, statb.p, sizeof(Stat), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (bad) return Error{PGCP_E_DEGENERATE, "zero-area or non-finite triangle in the original mesh"};
+        k = 1;
+        if (h.bad[0]) return Error{PGCP_E_DEGENERATE, "zero-area or non-finite triangle in the original mesh"};
         return e;
     }
     // mean |d_area| of X composed with m (+inf when an image area is zero or not finite); d [nf] optional
     Error eval(const Mob& m, double* d, double* value) {
         hipStream_t s = ctx->stream;
-        HIPCHK(hipMemsetAsync(badb.p, 0, 4, s));
+        Stat* st = (Stat*)statb.p;
+        const int slot = (int)(k & 1);
         k_area_img<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, X, sphere, m, F, (double*)logAf.p, (double*)part.p,
-                                                    (int*)badb.p);
-        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, (double*)tot.p + 1);
+                                                    &st->bad[slot]);
+        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, &st->tot[1], nullptr);
         k_area_abs<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, (const double*)logAf.p, (const double*)logA.p,
-                                                    (const double*)tot.p, d, (double*)part.p);
-        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, (double*)tot.p + 2);
+                                                    st->tot, d, (double*)part.p);
+        k_area_sum<<<1, BLOCK, 0, s>>>(nblk, (const double*)part.p, &st->tot[2], &st->bad[slot ^ 1]);
         HIPCHK(hipGetLastError());
-        double h[3];
-        int bad = 0;
-        HIPCHK(hipMemcpyAsync(h, tot.p, 24, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(&bad, badb.p, 4, hipMemcpyDeviceToHost, s));
+        Stat h;
+        HIPCHK(hipMemcpyAsync(&h, statb.p, sizeof(Stat), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        const double v = h[2] / (double)nf;
-        *value = (bad || !std::isfinite(v)) ? std::numeric_limits<double>::infinity() : v;
+        ++k;
+        const double v = h.tot[2] / (double)nf;
+        *value = (h.bad[slot] || !std::isfinite(v)) ? std::numeric_limits<double>::infinity() : v;
         return Error{PGCP_OK, ""};
     }
     void release() {
-        for (DevBuf* b : {&logA, &logAf, &part, &tot, &badb}) dev_free(*b);
+        for (DevBuf* b : {&logA, &logAf, &part, &statb}) dev_free(*b);
     }
 };
 
