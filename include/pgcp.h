@@ -109,9 +109,11 @@ typedef struct {
     int32_t* status;          /* in/out [n_sub] 0 = converged                         */
     double seconds;           /* out: wall time of the call                          */
     double cg_kernel_ms;      /* out: summed duration of the batched-CG launches (HIP events) */
-    double cg_bytes;          /* out: algorithmic bytes those launches move: per CG iteration and
-                                 row, its matrix entries (value + column index), its diagonal
-                                 entry and ten passes over the interleaved (x, y) vectors       */
+    double cg_bytes;          /* out: minimal algorithmic bytes of those launches in FP32
+                                 accounting, summed over pieces and iterations: per row, 8 B per
+                                 matrix entry (FP32 value + int32 column, diagonal included), 4 B
+                                 of inverse diagonal and 76 B of (x, y) state vectors; the learned
+                                 SPAI adds 8 B per entry of M                                     */
     int32_t cg_launches;      /* out: number of batched-CG launches                    */
     int32_t rows_per_thread;  /* out: 64-row slices per wave of the batched-CG launch  */
     int32_t cg_workgroups;    /* out: workgroups of the batched-CG launch              */
@@ -124,6 +126,10 @@ typedef struct {
                                  kernel (one per-piece barrier per iteration; opt-in with
                                  PGCP_PCG_KERNEL=single in the environment), 0 if the
                                  two-barrier or the streaming kernel                     */
+    double cg_bytes_native;   /* out: the same launches' bytes at the precision their
+                                 recurrences ran in (8 B values and vectors for FP64 solves):
+                                 matrix value + column per entry, ten passes over the (x, y)
+                                 vectors, the diagonal and the mask twice per row             */
 } pgcp_solve_stats;
 
 /* Distortion statistics over all 3|F| angles (Table 5 of the paper). */
@@ -196,16 +202,26 @@ pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* part, const double* V_
 /* Section 4.2.  DNCP of every piece: solves (L (+) L - M/2) z = 0 with two
  * pinned boundary vertices (the loop's smallest global index at (0,0), the
  * loop vertex farthest from it in R^3 at (distance, 0)), by batched
- * Jacobi-preconditioned CG on all pieces at once; then translates each piece
- * so the mean of its boundary points is 0.  Writes bdy_uv_dev [n_bdy][2].
- * Requires pgcp_assemble_cotan. */
+ * preconditioned CG on all pieces at once (Jacobi, or the learned sparse
+ * approximate inverse when opts->precond is PGCP_PC_LEARNED; FP64 recurrences,
+ * or FP32 ones with FP64 residual refinement per opts->precision); then
+ * translates each piece so the mean of its boundary points is 0.  Writes
+ * bdy_uv_dev [n_bdy][2].  Requires pgcp_assemble_cotan.  opts may be NULL
+ * (defaults), stats may be NULL.  The refinement passes are decided on the
+ * host, so the call returns once the solve has finished; the boundary gather
+ * into bdy_uv_dev is enqueued on the stream. */
 pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* part, const pgcp_solve_opts* opts,
                              double* bdy_uv_dev, pgcp_solve_stats* stats);
 
 /* Sections 4.3-4.4.  Partial welding (Algorithms 1 and 2) of the boundary
  * coordinates along the plan's balanced merge tree; in disk mode followed by
  * the geodesic algorithm on the outer boundary and the Cayley map onto the unit
- * disk; in sphere mode the last two components are closed-welded.  Host code.
+ * disk; in sphere mode the last two components are closed-welded.  With a
+ * context the maps of every merge round run on the device (one workgroup per
+ * pair zips its two arcs; every other tracked point is replayed through its
+ * pair's recorded maps in parallel); the merge bookkeeping, the Moebius
+ * normalisation and arcs longer than 8,192 points run on the host.  ctx may be
+ * NULL for a host-only plan (everything on the host).
  * bdy_uv_host [n_bdy][2] in, welded_uv_host [n_seam][2] out (sphere mode: a
  * point at infinity is written as (+inf, +inf)).  Synchronous. */
 pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* part, const double* bdy_uv_host,
@@ -292,6 +308,21 @@ pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* param
 /* Any context's solves may read the network; destroying it waits for the device
  * to finish everything enqueued. */
 void pgcp_lpc_destroy(pgcp_lpc* lpc);
+/* Write the network's whole training state to `path`: the fp32 master
+ * parameters, Adam's first and second moments and its step count, in a small
+ * binary file (magic "PGCPLPC1", int64 parameter count, int64 step, three fp32
+ * arrays of num_params, a 64-bit FNV-1a hash of the preceding bytes; written
+ * to path.tmp and renamed).  Synchronous.  PGCP_E_INVALID if the file cannot
+ * be written. */
+pgcp_status pgcp_lpc_save(pgcp_ctx* ctx, const pgcp_lpc* lpc, const char* path);
+/* Create a network on the context's device from a file written by
+ * pgcp_lpc_save: parameters, Adam moments and step restored, so training
+ * resumes where it stopped and inference uses the saved weights.  A file of
+ * the wrong size, magic, parameter count or hash is PGCP_E_INVALID.  Release
+ * with pgcp_lpc_destroy.  Synchronous. */
+pgcp_status pgcp_lpc_load(pgcp_ctx* ctx, const char* path, pgcp_lpc** out);
+/* Number of Adam steps the network has taken (restored by pgcp_lpc_load). */
+pgcp_status pgcp_lpc_step(const pgcp_lpc* lpc, int64_t* step);
 /* Run the network on every piece of an assembled plan and store the SPAI
  * values for `system` in the plan.  Async. */
 pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* part, const pgcp_lpc* lpc, int32_t system);
@@ -316,6 +347,14 @@ pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* part, pgcp_lpc* lpc, i
  * its sub_nv[i] vertices on the first sub_nv[i] of them, the rest padding.
  * row0 [n_sub+1]. */
 pgcp_status pgcp_part_rows(const pgcp_part* part, int64_t* row0);
+/* Copy the packed-row iterate of the last DNCP or harmonic solve on the plan
+ * (interleaved (x, y) float64 per packed row, in pgcp_part_row_vertices
+ * order; masked rows hold their pinned or Dirichlet values; for the sphere the
+ * harmonic values are in each piece's chart) to out_dev [row0[n_sub]][2], and
+ * which system it was to *system (PGCP_SYS_*; may be NULL).  The training
+ * driver of the network builds its error probes from these.  Async.
+ * PGCP_E_INVALID if no solve has run on the plan. */
+pgcp_status pgcp_part_solution(pgcp_ctx* ctx, const pgcp_part* part, int32_t* system, double* out_dev);
 /* Global vertex of every packed row, -1 on padding rows: row_gv [row0[n_sub]].
  * Within a piece the rows follow a reverse Cuthill-McKee order of the piece's
  * vertex graph (a workgroup's consecutive rows form a compact patch), not the

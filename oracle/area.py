@@ -27,7 +27,11 @@ i y) / (1 - z) (north pole <-> infinity).  The paper uses a general
 constrained solver; reading: Nelder-Mead from the identity map with an
 initial simplex of step 0.1 along each parameter, a fixed evaluation budget,
 and +inf for parameters outside the admissible set (ad - bc = 0, |alpha| >= 1,
-or any non-finite image area).
+any zero or non-finite image area, or any face whose orientation the map
+reverses: a Moebius map keeps the orientation of every small triangle away
+from its pole, so a reversed face is one whose image wraps around the pole's
+image, i.e. the pole lies inside it and the map is not a bijection of the
+parameter domain).
 """
 from __future__ import annotations
 
@@ -47,6 +51,17 @@ def face_areas(P: np.ndarray, F: np.ndarray) -> np.ndarray:
         P = np.column_stack([P, np.zeros(P.shape[0])])
     a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
     return 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+
+
+def orientation(P: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """Signed orientation of each face: twice its signed area in the plane,
+    det[a, b, c] for points on the unit sphere (positive when counter-clockwise
+    seen from outside)."""
+    P = np.asarray(P, dtype=np.float64)
+    a, b, c = P[F[:, 0]], P[F[:, 1]], P[F[:, 2]]
+    if P.shape[1] == 2:
+        return (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+    return np.einsum("ij,ij->i", a, np.cross(b, c))
 
 
 def area_distortion(V: np.ndarray, F: np.ndarray, X: np.ndarray) -> np.ndarray:
@@ -113,6 +128,8 @@ def objective(V, F, X, mode: str, p: np.ndarray) -> float:
         Y = apply(X, mode, p)
         Af = face_areas(Y, F)
         if not np.all(np.isfinite(Af)) or not np.all(Af > 0):
+            return float("inf")
+        if not np.all(orientation(Y, F) * orientation(X, F) > 0):
             return float("inf")
         v = mean_abs(V, F, Y)
     return v if np.isfinite(v) else float("inf")

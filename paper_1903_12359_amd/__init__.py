@@ -43,7 +43,8 @@ class SolveStats(ctypes.Structure):
                 ("status", ctypes.POINTER(ctypes.c_int32)), ("seconds", ctypes.c_double),
                 ("cg_kernel_ms", ctypes.c_double), ("cg_bytes", ctypes.c_double), ("cg_launches", ctypes.c_int32),
                 ("rows_per_thread", ctypes.c_int32), ("cg_workgroups", ctypes.c_int32), ("cg_block", ctypes.c_int32),
-                ("cg_stream", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("cg_single", ctypes.c_int32)]
+                ("cg_stream", ctypes.c_int32), ("n_fallback", ctypes.c_int32), ("cg_single", ctypes.c_int32),
+                ("cg_bytes_native", ctypes.c_double)]
 
 
 class DistStats(ctypes.Structure):
@@ -64,7 +65,8 @@ EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_s
            "pgcp_assemble_cotan", "pgcp_local_param", "pgcp_weld", "pgcp_harmonic_solve", "pgcp_distortion",
            "pgcp_lpc_num_params", "pgcp_lpc_create", "pgcp_lpc_get_params", "pgcp_lpc_destroy", "pgcp_lpc_infer",
            "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows",
-           "pgcp_part_row_vertices", "pgcp_area_distortion", "pgcp_area_objective", "pgcp_area_mobius_opt"]
+           "pgcp_part_row_vertices", "pgcp_area_distortion", "pgcp_area_objective", "pgcp_area_mobius_opt",
+           "pgcp_lpc_save", "pgcp_lpc_load", "pgcp_lpc_step", "pgcp_part_solution"]
 PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
 SYSTEMS = {"dncp": 0, "harmonic": 1}
 
@@ -95,6 +97,10 @@ def load_library(path: str = LIB_PATH):
         "pgcp_weld": (I32, [P, P, P, P]),
         "pgcp_harmonic_solve": (I32, [P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
         "pgcp_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P, P, I32, ctypes.POINTER(DistStats)]),
+        "pgcp_lpc_save": (I32, [P, P, ctypes.c_char_p]),
+        "pgcp_lpc_load": (I32, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
+        "pgcp_lpc_step": (I32, [P, ctypes.POINTER(I64)]),
+        "pgcp_part_solution": (I32, [P, P, ctypes.POINTER(I32), P]),
         "pgcp_lpc_num_params": (I64, []),
         "pgcp_lpc_create": (I32, [P, P, ctypes.POINTER(P)]),
         "pgcp_lpc_get_params": (I32, [P, P, P]),
@@ -157,6 +163,7 @@ class SolveReport:
     cg_stream: int = 0
     n_fallback: int = 0
     cg_single: int = 0
+    cg_bytes_native: float = 0.0
 
 
 class Context:
@@ -265,6 +272,16 @@ class Plan:
         self.ctx.check(self.ctx.lib.pgcp_part_row_vertices(self.h, _ptr(gv)))
         return gv
 
+    def solution(self, out=None):
+        """Packed-row iterate of the last solve on this plan ([rows][2] float64
+        on the device) and which system it was ("dncp" or "harmonic")."""
+        import torch
+        if out is None:
+            out = torch.empty((int(self.rows()[-1]), 2), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        sysv = ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.pgcp_part_solution(self.ctx.h, self.h, ctypes.byref(sysv), _ptr(out)))
+        return out, ("dncp" if sysv.value == 0 else "harmonic")
+
     def close(self):
         if getattr(self, "h", None):
             self.ctx.lib.pgcp_part_destroy(self.h)
@@ -279,11 +296,17 @@ class Plan:
 
 
 class LPC:
-    """The learned SPAI preconditioner network (pgcp_lpc) on a context's device."""
+    """The learned SPAI preconditioner network (pgcp_lpc) on a context's device.
 
-    def __init__(self, ctx: Context, params: np.ndarray | None = None):
+    LPC(ctx, params) starts from a parameter vector (None: all zeros, i.e.
+    Jacobi); LPC.load(ctx, path) from a training-state file written by save()."""
+
+    def __init__(self, ctx: Context, params: np.ndarray | None = None, _handle=None):
         self.ctx = ctx
         self.n_params = int(ctx.lib.pgcp_lpc_num_params())
+        if _handle is not None:
+            self.h = _handle
+            return
         p = None
         if params is not None:
             p = np.ascontiguousarray(params, dtype=np.float32)
@@ -292,6 +315,22 @@ class LPC:
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.pgcp_lpc_create(ctx.h, _ptr(p), ctypes.byref(h)))
         self.h = h
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "LPC":
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.pgcp_lpc_load(ctx.h, os.fsencode(path), ctypes.byref(h)))
+        return cls(ctx, _handle=h)
+
+    def save(self, path: str):
+        """Parameters, Adam moments and step to `path` (pgcp_lpc_save)."""
+        self.ctx.check(self.ctx.lib.pgcp_lpc_save(self.ctx.h, self.h, os.fsencode(path)))
+
+    @property
+    def step(self) -> int:
+        v = ctypes.c_int64()
+        self.ctx.check(self.ctx.lib.pgcp_lpc_step(self.h, ctypes.byref(v)))
+        return int(v.value)
 
     def params(self) -> np.ndarray:
         out = np.empty(self.n_params, np.float32)
@@ -353,7 +392,8 @@ def _report(st, keep):
     it, rr, ss = keep
     return SolveReport(st.n_sub, st.refine_steps, st.total_iters, it.copy(), rr.reshape(-1, 2).copy(),
                        ss.copy(), st.seconds, st.cg_kernel_ms, st.cg_bytes, st.cg_launches, st.rows_per_thread,
-                       st.cg_workgroups, st.cg_block, st.cg_stream, st.n_fallback, st.cg_single)
+                       st.cg_workgroups, st.cg_block, st.cg_stream, st.n_fallback, st.cg_single,
+                       st.cg_bytes_native)
 
 
 def assemble_cotan(ctx: Context, plan: Plan, V_dev):

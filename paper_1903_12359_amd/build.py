@@ -42,17 +42,23 @@ def _run(cmd):
 
 
 def build(verbose: bool = True) -> str:
+    """Compile every source (in parallel, one compiler per source) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = _hipcc()
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in DEVICE_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([hipcc, *COMMON, *DEVICE_FLAGS, *DEVICE_EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append((obj, [hipcc, *COMMON, *DEVICE_FLAGS, *DEVICE_EXTRA.get(src, []), "-c",
+                           os.path.join(CSRC, src), "-o", obj]))
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
-        _run([hipcc, *COMMON, *HOST_EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+        jobs.append((obj, [hipcc, *COMMON, *HOST_EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(_run, cmd) for _, cmd in jobs]:
+            f.result()
+    objs = [obj for obj, _ in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "-shared", "-fopenmp", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -274,6 +274,34 @@ pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* param
     return fail(ctx, pgcp::lpc_get_params(ctx, lpc, params_host));
 }
 
+pgcp_status pgcp_part_solution(pgcp_ctx* ctx, const pgcp_part* P, int32_t* system, double* out_dev) {
+    if (!ctx || !P || !out_dev) return bad(ctx, "null argument");
+    if (P->host_only || P->solved < 0 || !P->d_u64.p) return bad(ctx, "no solve has run on this plan");
+    if (system) *system = P->solved;
+    if (hipMemcpyAsync(out_dev, P->d_u64.p, (size_t)P->N * 16, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+        return fail(ctx, Error{PGCP_E_HIP, "solution copy failed"});
+    return PGCP_OK;
+}
+
+pgcp_status pgcp_lpc_save(pgcp_ctx* ctx, const pgcp_lpc* lpc, const char* path) {
+    if (!ctx || !lpc || !path) return bad(ctx, "null argument");
+    pgcp::AllocScope scope(ctx->stream);
+    return fail(ctx, pgcp::lpc_save(ctx, lpc, path));
+}
+
+pgcp_status pgcp_lpc_load(pgcp_ctx* ctx, const char* path, pgcp_lpc** out) {
+    if (!ctx || !path || !out) return bad(ctx, "null argument");
+    *out = nullptr;
+    pgcp::AllocScope scope(ctx->stream);
+    return fail(ctx, pgcp::lpc_load(ctx, path, out));
+}
+
+pgcp_status pgcp_lpc_step(const pgcp_lpc* lpc, int64_t* step) {
+    if (!lpc || !step) return PGCP_E_INVALID;
+    *step = lpc->step;
+    return PGCP_OK;
+}
+
 void pgcp_lpc_destroy(pgcp_lpc* lpc) {
     if (!lpc) return;
     // the network may be read by several contexts' streams: let all of them finish

@@ -106,17 +106,37 @@ __global__ void __launch_bounds__(BLOCK) k_area_src(int64_t nf, const double* __
     block_sum(a, part + blockIdx.x);
 }
 
+// Orientation of a face's three points: the signed area (times 2) in the
+// plane, det[a, b, c] for points on the sphere (positive for a face seen
+// counter-clockwise from outside).
+__device__ __forceinline__ double orient(const double* p, int sphere) {
+    if (sphere)
+        return p[0] * (p[4] * p[8] - p[5] * p[7]) - p[1] * (p[3] * p[8] - p[5] * p[6]) +
+               p[2] * (p[3] * p[7] - p[4] * p[6]);
+    return (p[3] - p[0]) * (p[7] - p[1]) - (p[4] - p[1]) * (p[6] - p[0]);
+}
+
+// A face is inadmissible when its image area is zero or not finite, or when
+// the map reverses its orientation (a Moebius map preserves orientation where
+// it is finite, so a reversal means its pole lies inside the face).
 __global__ void __launch_bounds__(BLOCK) k_area_img(int64_t nf, const double* __restrict__ X, int sphere, Mob m,
                                                     const int32_t* __restrict__ F, double* __restrict__ logAf,
                                                     double* __restrict__ part, int* __restrict__ bad) {
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     double a = 0.0;
     if (t < nf) {
-        double p[9];
+        double p[9], q[9];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) image(X, F[3 * t + c], sphere, m, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+        for (int c = 0; c < 3; ++c) {
+            const int64_t v = F[3 * t + c];
+            image(X, v, sphere, m, p[3 * c], p[3 * c + 1], p[3 * c + 2]);
+            q[3 * c] = X[(sphere ? 3 : 2) * v];
+            q[3 * c + 1] = X[(sphere ? 3 : 2) * v + 1];
+            q[3 * c + 2] = sphere ? X[3 * v + 2] : 0.0;
+        }
         a = tri_area(p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], p[8]);
-        if (!(a > 0.0) || !isfinite(a)) {
+        const double turn = orient(p, sphere) * orient(q, sphere);
+        if (!(a > 0.0) || !isfinite(a) || !(turn > 0.0)) {
             atomicOr(bad, 1);
             a = 0.0;
         }
@@ -212,7 +232,8 @@ struct AreaWork {
         if (h.bad[0]) return Error{PGCP_E_DEGENERATE, "zero-area or non-finite triangle in the original mesh"};
         return e;
     }
-    // mean |d_area| of X composed with m (+inf when an image area is zero or not finite); d [nf] optional
+    // mean |d_area| of X composed with m (+inf when an image area is zero or not
+    // finite, or a face's orientation is reversed); d [nf] optional
     Error eval(const Mob& m, double* d, double* value) {
         hipStream_t s = ctx->stream;
         Stat* st = (Stat*)statb.p;

@@ -2676,11 +2676,24 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     int steps = 0;
     int64_t total = 0;
     bool all_conv = false;
-    double cg_ms = 0.0, cg_bytes = 0.0;
+    double cg_ms = 0.0, cg_bytes = 0.0, cg_bytes_native = 0.0;
     int cg_launches = 0;
-    // algorithmic bytes of one CG iteration of piece i: matrix values + column
-    // indices once, and per row z, p_old read, p_new written (phase A), e and r
-    // read+written, z written (phase B), the diagonal twice and the mask twice.
+    // Minimal bytes of one CG iteration of piece i, in the FP32 accounting of
+    // the method's cost model: per row its matrix entries with the diagonal
+    // (FP32 value + int32 index, 8 B each), the FP32 inverse diagonal (4 B),
+    // and the interleaved (x, y) state vectors x, r, p, q read and written once
+    // plus one gather of p and the preconditioner's diagonal (76 B); the learned
+    // SPAI adds its own value and index stream (8 B per entry with the diagonal).
+    auto iter_bytes_min = [&](int i) {
+        const double entries = (double)P->sub_nnz[i] + (double)P->sub_nv[i];
+        double b = 8.0 * entries + 80.0 * (double)P->sub_nv[i];
+        if (pc[i]) b += 8.0 * entries;
+        return b;
+    };
+    // The same iteration as this launch moves it, at the precision of its
+    // recurrences: matrix values + column indices once, and per row z, p_old
+    // read, p_new written (phase A), e and r read+written, z written (phase B),
+    // the diagonal twice and the mask twice.
     const double tsz = prec ? 4.0 : 8.0;
     auto iter_bytes = [&](int i) {
         double b = (double)P->sub_nnz[i] * (tsz + 4.0) + (double)P->sub_nv[i] * (8.0 * 2.0 * tsz + 2.0 * tsz + 2.0);
@@ -2800,7 +2813,8 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
                 if (!active[i]) continue;
                 it_total[i] += iters[i];
                 total += iters[i];
-                cg_bytes += iters[i] * iter_bytes(i);
+                cg_bytes += iters[i] * iter_bytes_min(i);
+                cg_bytes_native += iters[i] * iter_bytes(i);
             }
             continue;
         }
@@ -2808,7 +2822,8 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
             if (!active[i]) continue;
             it_total[i] += iters[i];
             total += iters[i];
-            cg_bytes += iters[i] * iter_bytes(i);
+            cg_bytes += iters[i] * iter_bytes_min(i);
+            cg_bytes_native += iters[i] * iter_bytes(i);
             if (pc[i] && (status[i] == 1 || status[i] == 4)) {
                 pc[i] = 0;   // learned SPAI broke down or stagnated: Jacobi from here on
                 n_fallback++;
@@ -2837,6 +2852,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         st->total_iters = total;
         st->cg_kernel_ms = cg_ms;
         st->cg_bytes = cg_bytes;
+        st->cg_bytes_native = cg_bytes_native;
         st->cg_launches = cg_launches;
         st->rows_per_thread = W.rows_per_thread;
         st->cg_workgroups = W.n_wg;
@@ -2859,6 +2875,7 @@ Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, dou
     HIPCHK(hipGetLastError());
     Error e = refine_solve(ctx, P, 1, (const uint8_t*)P->d_mask_dncp.p, o, st, 0);
     if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
+    P->solved = PGCP_SYS_DNCP;
     k_dncp_bdy<<<P->K, BLOCK, 0, s>>>((const int32_t*)P->d_loop_ptr.p, (const int32_t*)P->d_loop_row.p,
                                        (const double2*)P->d_u64.p, bdy);
     HIPCHK(hipGetLastError());
@@ -2882,6 +2899,7 @@ Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp
     HIPCHK(hipGetLastError());
     Error e = refine_solve(ctx, P, 0, (const uint8_t*)P->d_mask_harm.p, o, st, 1);
     if (e.code != PGCP_OK && e.code != PGCP_E_NOCONV) return e;
+    P->solved = PGCP_SYS_HARMONIC;
     k_harm_out<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p, (const int32_t*)P->d_row_gv.p,
                                                  (const int32_t*)P->d_slice_sub.p, (const double2*)P->d_u64.p,
                                                  (const double*)P->d_chart.p, sphere, out);

@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -925,6 +926,89 @@ Error lpc_create(pgcp_ctx* ctx, const float* params, pgcp_lpc** out) {
     if ((e = lpc_pack(L, s)).code) return fail(e);
     if (hipStreamSynchronize(s) != hipSuccess) return fail(Error{PGCP_E_HIP, "stream synchronise failed"});
     *out = L;
+    return Error{PGCP_OK, ""};
+}
+
+// Training-state file: the magic "PGCPLPC1", int64 parameter count, int64
+// Adam step, then the fp32 master parameters and Adam's first and second
+// moments (each [count]), then a 64-bit FNV-1a hash of everything before it.
+// Little-endian, as the device and host are.
+static constexpr char kLpcMagic[8] = {'P', 'G', 'C', 'P', 'L', 'P', 'C', '1'};
+
+static uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+Error lpc_save(pgcp_ctx* ctx, const pgcp_lpc* L, const char* path) {
+    std::vector<float> th(N_PARAMS), m(N_PARAMS), v(N_PARAMS);
+    hipStream_t s = ctx->stream;
+    HIPCHK(hipMemcpyAsync(th.data(), L->theta.p, N_PARAMS * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(m.data(), L->adam_m.p, N_PARAMS * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(v.data(), L->adam_v.p, N_PARAMS * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<unsigned char> buf;
+    auto put = [&](const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        buf.insert(buf.end(), c, c + n);
+    };
+    const int64_t n = N_PARAMS, step = L->step;
+    put(kLpcMagic, 8);
+    put(&n, 8);
+    put(&step, 8);
+    put(th.data(), N_PARAMS * 4);
+    put(m.data(), N_PARAMS * 4);
+    put(v.data(), N_PARAMS * 4);
+    const uint64_t h = fnv1a(buf.data(), buf.size());
+    put(&h, 8);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return Error{PGCP_E_INVALID, std::string("cannot open ") + tmp + " for writing"};
+    const bool ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+    const bool closed = std::fclose(f) == 0;
+    if (!ok || !closed || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return Error{PGCP_E_INVALID, std::string("cannot write ") + path};
+    }
+    return Error{PGCP_OK, ""};
+}
+
+Error lpc_load(pgcp_ctx* ctx, const char* path, pgcp_lpc** out) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return Error{PGCP_E_INVALID, std::string("cannot open ") + path};
+    std::vector<unsigned char> buf;
+    unsigned char tmp[1 << 16];
+    size_t got;
+    while ((got = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    std::fclose(f);
+    const size_t want = 24 + 3 * (size_t)N_PARAMS * 4 + 8;
+    if (buf.size() != want || std::memcmp(buf.data(), kLpcMagic, 8) != 0)
+        return Error{PGCP_E_INVALID, std::string(path) + " is not a training-state file of this network"};
+    int64_t n = 0, step = 0;
+    uint64_t h = 0;
+    std::memcpy(&n, buf.data() + 8, 8);
+    std::memcpy(&step, buf.data() + 16, 8);
+    std::memcpy(&h, buf.data() + want - 8, 8);
+    if (n != N_PARAMS || step < 0) return Error{PGCP_E_INVALID, std::string(path) + ": wrong parameter count"};
+    if (fnv1a(buf.data(), want - 8) != h) return Error{PGCP_E_INVALID, std::string(path) + ": checksum mismatch"};
+    const float* th = reinterpret_cast<const float*>(buf.data() + 24);
+    Error e = lpc_create(ctx, th, out);
+    if (e.code) return e;
+    pgcp_lpc* L = *out;
+    hipStream_t s = ctx->stream;
+    const bool ok = hipMemcpyAsync(L->adam_m.p, th + N_PARAMS, N_PARAMS * 4, hipMemcpyHostToDevice, s) == hipSuccess &&
+                    hipMemcpyAsync(L->adam_v.p, th + 2 * N_PARAMS, N_PARAMS * 4, hipMemcpyHostToDevice, s) ==
+                        hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        lpc_destroy(L);
+        *out = nullptr;
+        return Error{PGCP_E_HIP, "optimizer state upload failed"};
+    }
+    L->step = step;
     return Error{PGCP_OK, ""};
 }
 

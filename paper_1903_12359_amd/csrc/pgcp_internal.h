@@ -168,6 +168,7 @@ struct pgcp_part {
     hipStream_t stream = nullptr;   // stream of the context that last worked on the plan
 
     bool assembled = false;
+    int solved = -1;        // system of the last solve whose iterate d_u64 holds (-1: none)
     bool welded = false;
     bool host_only = false;
 };
@@ -190,6 +191,8 @@ int64_t lpc_num_params();
 Error lpc_create(pgcp_ctx* ctx, const float* params, pgcp_lpc** out);
 void lpc_destroy(pgcp_lpc* L);
 Error lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* L, float* out);
+Error lpc_save(pgcp_ctx* ctx, const pgcp_lpc* L, const char* path);
+Error lpc_load(pgcp_ctx* ctx, const char* path, pgcp_lpc** out);
 Error lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* L, int system);
 Error lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int piece, double* o_off, double* o_diag, double* m_off,
                  double* m_diag);

@@ -1,15 +1,29 @@
 """Training driver of the learned SPAI preconditioner (every step runs in libpgcp).
 
-    python -m paper_1903_12359_amd.lpc_train --out lpc_weights.npy [--steps 400]
+    python -m paper_1903_12359_amd.lpc_train --out lpc_state.bin [--steps 400] [--resume lpc_state.bin]
 
 The training set follows the recipe the network is meant for: subdomain
 Laplacians of seeded bump height fields (random block partitions) and of
 perturbed icospheres (k-means pieces), with both Dirichlet masks the method
 solves (DNCP pins, harmonic boundary).  Each step takes one plan (all of its
-pieces form the batch), draws Rademacher probe vectors on the device and calls
-pgcp_lpc_train_step: forward pass, loss, hand-written backward pass and Adam
-all run in the library's kernels.  This module only picks plans and draws the
-random probes.
+pieces form the batch) and one of its two systems and calls
+pgcp_lpc_train_step with a batch of probe vectors: forward pass, loss,
+hand-written backward pass and Adam all run in the library's kernels.
+
+Probes.  Half of each batch is Rademacher vectors (their loss averages to
+|MA - I|_F^2 / n, every mode alike); the other half are error vectors of the
+method's own solves: the plan is solved with Jacobi-PCG (DNCP from its pins;
+the harmonic system with the boundary values the method's own DNCP and weld
+produce), and e_k = x* - x_k after k = 16, 128 and 1,024 iterations (x and y
+components as separate probes) are the slow modes that CG leaves behind.  A
+piece that has converged by step k takes a Rademacher segment instead.
+
+Checkpoints.  Trainer.save writes the network's training state
+(pgcp_lpc_save: parameters, Adam moments and step) and, beside it, the
+driver's own random state (plan and system draws, probe generator) and step,
+so that Trainer.load continues with the same loss trajectory.
+
+This module only picks plans, draws the random probes and subtracts solutions.
 """
 from __future__ import annotations
 
@@ -57,29 +71,139 @@ def rademacher(n_rows: int, n_probes: int, gen, device):
             .to(torch.float32) * 2.0 - 1.0).contiguous()
 
 
-def train(ctx, lpc, tset: TrainingSet, steps: int, lr: float = 1e-3, n_probes: int = 8, seed: int = 0,
-          log_every: int = 0):
-    """Adam steps over random (plan, system) draws; returns the loss history."""
+ERROR_STEPS = (16, 128, 1024)
+
+
+def error_probes(ctx, plan, V_dev, ks=ERROR_STEPS, tol=1e-10, gen=None):
+    """Jacobi-PCG error snapshots of both systems of an assembled plan.
+
+    Returns {"dncp": E, "harmonic": E}, E a float32 tensor [2 len(ks)][rows]
+    in packed-row order: e_k = x* - x_k (x and y components) after k
+    iterations from the method's starting point, x* the solve to `tol`.  The
+    harmonic system takes the boundary values the method itself produces
+    (DNCP, then the weld).  Pieces whose error has vanished by step k (relative
+    to their solution) get a Rademacher segment drawn from `gen`."""
     import torch
+    import paper_1903_12359_amd as pg
     dev = f"cuda:{ctx.device}"
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(seed)
-    rng = np.random.default_rng(seed)
-    hist = []
-    for step in range(steps):
-        plan, _, n_rows = tset.items[int(rng.integers(len(tset.items)))]
-        system = "harmonic" if rng.random() < 0.5 else "dncp"
-        V = rademacher(n_rows, n_probes, gen, dev)
-        loss = lpc.train_step(plan, V, lr, system=system)
-        hist.append(loss)
-        if log_every and (step + 1) % log_every == 0:
-            print(f"[lpc] step {step + 1}/{steps} loss {np.mean(hist[-log_every:]):.4f}", file=sys.stderr,
-                  flush=True)
-    return hist
+    row0 = plan.rows()
+    out = {}
+    bdy, _ = pg.local_param(ctx, plan, precision="fp64", tol=tol)
+    welded = torch.from_numpy(pg.weld(ctx, plan, bdy.cpu().numpy())).to(dev)
+    for system in ("dncp", "harmonic"):
+        def solve(**kw):
+            if system == "dncp":
+                pg.local_param(ctx, plan, allow_noconv=True, **kw)
+            else:
+                pg.harmonic_solve(ctx, plan, welded, allow_noconv=True, **kw)
+            return plan.solution()[0].clone()
+        xs = solve(precision="fp64", tol=tol)
+        E = []
+        for k in ks:
+            xk = solve(precision="fp64", tol=tol, max_iter=int(k), max_refine=2)
+            E.append((xs - xk).T.to(torch.float32))
+        E = torch.cat(E, 0).contiguous()                       # [2 len(ks)][rows]
+        ref = xs.abs().amax()
+        for i in range(plan.K):
+            a, b = int(row0[i]), int(row0[i + 1])
+            seg = E[:, a:b]
+            dead = seg.abs().amax(dim=1) <= 1e-7 * float(ref)
+            if bool(dead.any()):
+                n = int(dead.sum())
+                seg[dead] = rademacher(b - a, n, gen, dev) if gen is not None else 1.0
+        out[system] = E
+    return out
+
+
+class Trainer:
+    """Adam steps over random (plan, system) draws with mixed probe batches.
+
+    Draws come from a numpy Generator (plan, system, which error probes) and a
+    torch Generator on the device (Rademacher probes), both seeded; save() and
+    load() carry them with the network's state, so a resumed run repeats the
+    uninterrupted run's losses."""
+
+    def __init__(self, ctx, lpc, tset: TrainingSet, lr: float = 1e-3, n_probes: int = 8, seed: int = 0,
+                 error_fraction: float = 0.5):
+        import torch
+        self.ctx, self.lpc, self.tset = ctx, lpc, tset
+        self.lr, self.n_probes, self.seed = lr, n_probes, seed
+        self.dev = f"cuda:{ctx.device}"
+        self.gen = torch.Generator(device=self.dev)
+        self.gen.manual_seed(seed)
+        self.rng = np.random.default_rng(seed)
+        self.step = 0
+        self.n_err = int(round(n_probes * error_fraction))
+        self.errors = None
+        if self.n_err > 0:
+            self.errors = [error_probes(ctx, plan, V, gen=self.gen) for plan, V, _ in tset.items]
+
+    def run(self, steps: int, log_every: int = 0):
+        import torch
+        hist = []
+        for _ in range(steps):
+            j = int(self.rng.integers(len(self.tset.items)))
+            plan, _, n_rows = self.tset.items[j]
+            system = "harmonic" if self.rng.random() < 0.5 else "dncp"
+            V = rademacher(n_rows, self.n_probes - self.n_err, self.gen, self.dev)
+            if self.n_err > 0:
+                E = self.errors[j][system]
+                pick = self.rng.choice(E.shape[0], size=self.n_err, replace=E.shape[0] < self.n_err)
+                V = torch.cat([V, E[torch.as_tensor(pick, device=self.dev)]], 0).contiguous()
+            hist.append(self.lpc.train_step(plan, V, self.lr, system=system))
+            self.step += 1
+            if log_every and self.step % log_every == 0:
+                print(f"[lpc] step {self.step} loss {np.mean(hist[-log_every:]):.4f}", file=sys.stderr, flush=True)
+        return hist
+
+    def save(self, path: str):
+        """The network's training state to `path`, the driver's random state to `path`.json."""
+        import json
+        self.lpc.save(path)
+        state = {"step": self.step, "seed": self.seed, "lr": self.lr, "n_probes": self.n_probes,
+                 "n_err": self.n_err, "numpy": self.rng.bit_generator.state,
+                 "torch": self.gen.get_state().tolist()}
+        with open(path + ".json", "w") as f:
+            json.dump(state, f)
+
+    @classmethod
+    def load(cls, ctx, tset: TrainingSet, path: str):
+        """Resume from save(): the network, Adam, the step and both random streams."""
+        import json
+        import torch
+        import paper_1903_12359_amd as pg
+        with open(path + ".json") as f:
+            state = json.load(f)
+        lpc = pg.LPC.load(ctx, path)
+        t = cls.__new__(cls)
+        t.ctx, t.lpc, t.tset = ctx, lpc, tset
+        t.lr, t.n_probes, t.seed, t.n_err = state["lr"], state["n_probes"], state["seed"], state["n_err"]
+        t.dev = f"cuda:{ctx.device}"
+        t.gen = torch.Generator(device=t.dev)
+        t.rng = np.random.default_rng(t.seed)
+        t.errors = None
+        if t.n_err > 0:
+            # the error probes are a function of the plans alone; their
+            # Rademacher fill-ins come from the generator's seeded start
+            t.gen.manual_seed(t.seed)
+            t.errors = [error_probes(ctx, plan, V, gen=t.gen) for plan, V, _ in tset.items]
+        t.rng.bit_generator.state = state["numpy"]
+        t.gen.set_state(torch.tensor(state["torch"], dtype=torch.uint8))
+        t.step = state["step"]
+        if lpc.step != t.step:
+            raise ValueError(f"{path}: network step {lpc.step} but driver step {t.step}")
+        return t
+
+
+def train(ctx, lpc, tset: TrainingSet, steps: int, lr: float = 1e-3, n_probes: int = 8, seed: int = 0,
+          log_every: int = 0, error_fraction: float = 0.5):
+    """Adam steps over random (plan, system) draws; returns the loss history."""
+    tr = Trainer(ctx, lpc, tset, lr=lr, n_probes=n_probes, seed=seed, error_fraction=error_fraction)
+    return tr.run(steps, log_every=log_every)
 
 
 def train_windows(ctx, lpc, meshes, steps: int, window_rows: int = 1_500_000, lr: float = 1e-3,
-                  n_probes: int = 8, seed: int = 0, log=None):
+                  n_probes: int = 8, seed: int = 0, log=None, error_fraction: float = 0.5):
     """Training over a large set of meshes (the C4 recipe) in windows: the plans
     of consecutive meshes up to `window_rows` vertices are assembled on the
     device, trained on and released (a plan's training buffers hold ~10 kB per
@@ -103,7 +227,8 @@ def train_windows(ctx, lpc, meshes, steps: int, window_rows: int = 1_500_000, lr
         done += n
         tset = TrainingSet(ctx, cases)
         pieces += sum(p.K for p, _, _ in tset.items)
-        hist.extend(train(ctx, lpc, tset, n, lr=lr, n_probes=n_probes, seed=seed + w))
+        hist.extend(train(ctx, lpc, tset, n, lr=lr, n_probes=n_probes, seed=seed + w,
+                          error_fraction=error_fraction))
         for p, _, _ in tset.items:
             p.close()
         if log:
@@ -135,35 +260,47 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", required=True, help="training-state file (pgcp_lpc_save format)")
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--resume", default=None, help="small set: continue from a state written by --out")
     ap.add_argument("--set", default="small", choices=["small", "c4"],
                     help="small: 10 meshes held on the device; c4: ~2,000 pieces of 1k-20k vertices, trained "
                          "in windows of plans")
     args = ap.parse_args()
     import paper_1903_12359_amd as pg
     ctx = pg.Context(0)
-    if args.set == "c4":
-        from synth import c4_training_meshes
-        lpc = pg.LPC(ctx, init_params(args.seed))
+    try:
+        if args.set == "c4":
+            from synth import c4_training_meshes
+            lpc = pg.LPC(ctx, init_params(args.seed))
+            t = time.perf_counter()
+            hist, pieces, _ = train_windows(ctx, lpc, c4_training_meshes(seed=args.seed), args.steps, lr=args.lr,
+                                            seed=args.seed, log=lambda m: print(m, file=sys.stderr, flush=True))
+            print(f"[lpc] {pieces} pieces, {len(hist)} steps in {time.perf_counter() - t:.1f}s", file=sys.stderr,
+                  flush=True)
+            lpc.save(args.out)
+            lpc.close()
+            return
         t = time.perf_counter()
-        hist, pieces, _ = train_windows(ctx, lpc, c4_training_meshes(seed=args.seed), args.steps, lr=args.lr,
-                                        seed=args.seed, log=lambda m: print(m, file=sys.stderr, flush=True))
-        print(f"[lpc] {pieces} pieces, {len(hist)} steps in {time.perf_counter() - t:.1f}s", file=sys.stderr,
+        tset = TrainingSet(ctx, training_meshes(seed=args.seed))
+        print(f"[lpc] training set: {len(tset.items)} plans, {sum(p.K for p, _, _ in tset.items)} pieces "
+              f"({time.perf_counter() - t:.1f}s)", file=sys.stderr, flush=True)
+        if args.resume:
+            tr = Trainer.load(ctx, tset, args.resume)
+        else:
+            tr = Trainer(ctx, pg.LPC(ctx, init_params(args.seed)), tset, lr=args.lr, seed=args.seed)
+        t = time.perf_counter()
+        tr.run(args.steps, log_every=50)
+        print(f"[lpc] {args.steps} steps in {time.perf_counter() - t:.1f}s (step {tr.step})", file=sys.stderr,
               flush=True)
-        np.save(args.out, lpc.params())
-        return
-    t = time.perf_counter()
-    tset = TrainingSet(ctx, training_meshes(seed=args.seed))
-    print(f"[lpc] training set: {len(tset.items)} plans, {sum(p.K for p, _, _ in tset.items)} pieces "
-          f"({time.perf_counter() - t:.1f}s)", file=sys.stderr, flush=True)
-    lpc = pg.LPC(ctx, init_params(args.seed))
-    t = time.perf_counter()
-    train(ctx, lpc, tset, args.steps, lr=args.lr, seed=args.seed, log_every=50)
-    print(f"[lpc] {args.steps} steps in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    np.save(args.out, lpc.params())
+        tr.save(args.out)
+        tr.lpc.close()
+        for p, _, _ in tset.items:
+            p.close()
+    finally:
+        ctx.close()
 
 
 if __name__ == "__main__":

@@ -110,6 +110,24 @@ def test_area_objective_matches_oracle(ctx, name):
     assert pg.area_objective(ctx, _dev(V), _dev(F), _dev(X), mode, bad) == float("inf")
 
 
+def test_pole_inside_the_domain_is_inadmissible(ctx):
+    # f(z) = 1/(z - z0) with z0 inside the parameter domain reverses the faces
+    # around z0 (their image areas stay finite): +inf on both sides; with the
+    # pole outside both give the same finite value
+    import paper_1903_12359_amd as pg
+    V, F, xy = _plane(n=16)
+    X = xy + 0.01 * np.column_stack([np.sin(3 * xy[:, 1]), np.cos(2 * xy[:, 0])])
+    inside = np.array([0.0, 0.0, 1.0, 0.0, 1.0, 0.0, -0.113, -0.057])
+    outside = np.array([0.0, 0.0, 1.0, 0.0, 1.0, 0.0, -2.0, 0.0])
+    Vd, Fd, Xd = _dev(V), _dev(F), _dev(X)
+    assert area.objective(V, F, X, "free", inside) == float("inf")
+    assert pg.area_objective(ctx, Vd, Fd, Xd, "free", inside) == float("inf")
+    o = area.objective(V, F, X, "free", outside)
+    g = pg.area_objective(ctx, Vd, Fd, Xd, "free", outside)
+    say("pole outside", g, o)
+    assert np.isfinite(o) and abs(g - o) <= 1e-12 * max(1.0, o)
+
+
 def _plane(n=24, lo=-0.5, hi=0.5):
     xy, F = grid_mesh(n)
     xy = lo + (hi - lo) * xy

@@ -109,3 +109,33 @@ def test_optimiser_inverts_a_spherical_moebius_map():
     p, before, after = area.optimise(P, F, X, "sphere", max_evals=4000)
     assert before > 0.1
     assert after < 1e-2 * before
+
+
+def test_pole_inside_the_domain_is_inadmissible():
+    # f(z) = 1 / (z - z0): holomorphic, so every small face away from z0 keeps
+    # its orientation; the faces around z0 are sent around the image of the
+    # pole (infinity) and come back reversed.  Unsigned areas alone stay
+    # finite there, so the objective must reject the map by orientation.
+    V, F, xy = _plane(n=16)
+    X = xy + 0.01 * np.column_stack([np.sin(3 * xy[:, 1]), np.cos(2 * xy[:, 0])])
+    inside = np.array([0.0, 0.0, 1.0, 0.0, 1.0, 0.0, -0.113, -0.057])    # pole at 0.113 + 0.057i
+    outside = np.array([0.0, 0.0, 1.0, 0.0, 1.0, 0.0, -2.0, 0.0])         # pole at 2
+    Y = area.apply(X, "free", inside)
+    turn = area.orientation(Y, F) * area.orientation(X, F)
+    assert (turn < 0).sum() >= 1 and (turn > 0).sum() > 0.9 * len(F)
+    assert np.isfinite(area.mean_abs(V, F, Y))              # areas alone do not see it
+    assert area.objective(V, F, X, "free", inside) == float("inf")
+    v = area.objective(V, F, X, "free", outside)
+    assert np.isfinite(v) and v == pytest.approx(area.mean_abs(V, F, area.apply(X, "free", outside)))
+    assert np.all(area.orientation(area.apply(X, "free", outside), F) > 0)
+
+
+def test_orientation_closed_forms():
+    # counter-clockwise unit right triangle: twice its area; reversed: negative
+    P2 = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    assert area.orientation(P2, np.array([[0, 1, 2]]))[0] == 1.0
+    assert area.orientation(P2, np.array([[0, 2, 1]]))[0] == -1.0
+    # the octant triangle (e_x, e_y, e_z) seen from outside is counter-clockwise: det = 1
+    P3 = np.eye(3)
+    assert area.orientation(P3, np.array([[0, 1, 2]]))[0] == 1.0
+    assert area.orientation(P3, np.array([[1, 0, 2]]))[0] == -1.0
