@@ -262,3 +262,38 @@ def test_training_lowers_loss_and_iterations(ctx):
     say("held-out harmonic iterations: jacobi", rj.total_iters, "learned", rl.total_iters)
     assert rl.relres.max() <= 1e-10
     assert rl.total_iters < 0.85 * rj.total_iters
+
+
+def test_checkpoint_resume_repeats_the_loss_trajectory(ctx, tmp_path):
+    """Trainer.save / Trainer.load (pgcp_lpc_save / pgcp_lpc_load: parameters,
+    Adam moments and step, plus the driver's random streams): a run resumed from
+    a checkpoint repeats the uninterrupted run's losses and parameters bitwise;
+    a corrupted file is refused."""
+    import paper_1903_12359_amd as pg
+    from paper_1903_12359_amd.lpc_train import Trainer, TrainingSet, init_params
+    cases = [small_grid_case(49, 2, 2, seed=50, jitter=0.15, nbumps=5), small_sphere_case(4, 6, seed=51)]
+    tset = TrainingSet(ctx, cases)
+    path = str(tmp_path / "lpc_state.bin")
+    try:
+        tr = Trainer(ctx, pg.LPC(ctx, init_params(1)), tset, lr=2e-3, seed=4, error_fraction=0.25)
+        h1 = tr.run(12)
+        tr.save(path)
+        h2 = tr.run(12)
+        p2 = tr.lpc.params()
+        tr2 = Trainer.load(ctx, tset, path)
+        assert tr2.step == 12 and tr2.lpc.step == 12
+        h2b = tr2.run(12)
+        say("losses", h1[-1], h2[-1], h2b[-1])
+        assert h2b == h2
+        assert np.array_equal(tr2.lpc.params(), p2)
+        tr.lpc.close()
+        tr2.lpc.close()
+        raw = bytearray(open(path, "rb").read())
+        raw[len(raw) // 2] ^= 0x40
+        bad = str(tmp_path / "bad.bin")
+        open(bad, "wb").write(bytes(raw))
+        with pytest.raises(pg.PGCPError):
+            pg.LPC.load(ctx, bad)
+    finally:
+        for p, _, _ in tset.items:
+            p.close()

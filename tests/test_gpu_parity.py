@@ -193,19 +193,71 @@ def test_distortion_flips_and_affine(ctx):
     assert st["n_flipped"] == case.nf and flip.cpu().numpy().all()
 
 
+_E2E = {}
+
+
+def _oracle_e2e(name):
+    if name not in _E2E:
+        case = CASES[name]()
+        _E2E[name] = (case, pgcp(case.V, case.F, case.label, case.mode))
+    return _E2E[name]
+
+
+def _e2e_err(phi, r):
+    """max_v |phi_v - phi_v^oracle| / max_v |phi_v^oracle| (Euclidean per vertex;
+    chordal on the sphere)."""
+    g = phi.cpu().numpy()
+    return float(np.linalg.norm(g - r["phi"], axis=1).max() / np.linalg.norm(r["phi"], axis=1).max())
+
+
 @pytest.mark.parametrize("name", ["g17_2x2", "C1", "C2_n128", "S3_k6", "S5_k12"])
 def test_end_to_end(ctx, name):
+    """Algorithm 3 on the FP64 path against the oracle's run, at the FP64 bound."""
     import paper_1903_12359_amd as pg
-    case = CASES[name]()
+    case, r = _oracle_e2e(name)
     say("end-to-end", name)
     phi, st, info = pg.run(ctx, case.V, case.F, case.label, case.mode, precision="fp64", tol=1e-13)
-    r = pgcp(case.V, case.F, case.label, case.mode)
-    g = phi.cpu().numpy()
-    err = np.abs(g - r["phi"]).max() / np.abs(r["phi"]).max()
+    err = _e2e_err(phi, r)
     say("  end-to-end rel err", err, st)
-    assert st["n_flipped"] == 0
-    assert err <= 1e-7
+    assert st["n_flipped"] == 0 and r["dist"]["stats"]["n_flipped"] == 0
+    assert err <= 1e-9
+    # a 1e-9 coordinate error moves an angle by ~1e-9 / (shortest edge) radians
     assert abs(st["mean_abs_d"] - r["dist"]["stats"]["mean_abs_d"]) <= 1e-6
+
+
+def _lpc_net(ctx):
+    """A network with random weights, biases and heads: its SPAI differs from
+    Jacobi on every entry (still symmetric positive definite by construction)."""
+    import paper_1903_12359_amd as pg
+    from oracle import lpc as olpc
+    rng = np.random.default_rng(11)
+    P = olpc.init_params(rng, zero_heads=False)
+    for k in P:
+        if k.startswith("b_") or k.startswith("c_"):
+            P[k] = rng.normal(0, 0.05, np.shape(P[k]))
+    return pg.LPC(ctx, 0.5 * olpc.flatten(P).astype(np.float32))
+
+
+@pytest.mark.parametrize("name", ["g17_2x2", "C1", "C2_n128", "S3_k6", "S5_k12"])
+@pytest.mark.parametrize("variant", ["fp32", "learned-fp32", "learned-fp64"])
+def test_end_to_end_mixed_and_learned(ctx, name, variant):
+    """Algorithm 3 with FP32 inner solves and FP64 refinement (both solves), and
+    with the learned SPAI preconditioner, against the same oracle run: the
+    mixed path at its bound (1e-6), the learned FP64 path at 1e-9; no flips."""
+    import paper_1903_12359_amd as pg
+    case, r = _oracle_e2e(name)
+    prec = "fp64" if variant == "learned-fp64" else "fp32"
+    net = _lpc_net(ctx) if variant.startswith("learned") else None
+    try:
+        phi, st, info = pg.run(ctx, case.V, case.F, case.label, case.mode, precision=prec, dncp_precision=prec,
+                               tol=1e-13 if prec == "fp64" else 1e-12, lpc=net)
+    finally:
+        if net is not None:
+            net.close()
+    err = _e2e_err(phi, r)
+    say("end-to-end", name, variant, "rel err", err, "iters", info["dncp"].total_iters, info["harmonic"].total_iters)
+    assert st["n_flipped"] == 0
+    assert err <= (1e-9 if prec == "fp64" else 1e-6)
 
 
 def test_run_twice_bitwise(ctx):
