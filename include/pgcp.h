@@ -158,6 +158,8 @@ typedef struct {
  * the null stream). */
 pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream);
 void pgcp_ctx_destroy(pgcp_ctx* ctx);
+/* Message of the last failed call on ctx; with ctx NULL, of the last failed
+ * pgcp_ctx_create on the calling thread. */
 const char* pgcp_last_error(const pgcp_ctx* ctx);
 /* Change the stream later calls enqueue on (work already enqueued on the old
  * stream must be ordered before the new stream's by the caller). */

@@ -80,6 +80,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libpgcp.so not built ({path}); run `python -m paper_1903_12359_amd.build`")
+    # torch's HIP runtime must enumerate the devices before the library's first
+    # HIP call: in the other order the library's runtime finds no device
+    import torch
+    torch.cuda.is_available()
     L = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
@@ -179,7 +183,8 @@ class Context:
         h = ctypes.c_void_p()
         rc = self.lib.pgcp_ctx_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
         if rc != 0:
-            raise PGCPError(rc, "context creation failed")
+            msg = self.lib.pgcp_last_error(None)
+            raise PGCPError(rc, "context creation failed: " + (msg.decode() if msg else ""))
         self.h = h
 
     def check(self, rc):

@@ -32,6 +32,15 @@ pgcp_status fail(pgcp_ctx* ctx, const Error& e) {
 
 pgcp_status bad(pgcp_ctx* ctx, const char* m) { return fail(ctx, Error{PGCP_E_INVALID, m}); }
 
+// message of the last failure of a call made without a context on this
+// thread (context creation), read by pgcp_last_error(NULL)
+thread_local std::string no_ctx_error = "no context";
+
+pgcp_status no_ctx_fail(pgcp_status code, const std::string& msg) {
+    no_ctx_error = msg;
+    return code;
+}
+
 double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -41,13 +50,17 @@ double now() {
 extern "C" {
 
 pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream) {
-    if (!out) return PGCP_E_INVALID;
+    if (!out) return no_ctx_fail(PGCP_E_INVALID, "null output pointer");
     *out = nullptr;
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return PGCP_E_HIP;
-    if (hipSetDevice(hip_device) != hipSuccess) return PGCP_E_HIP;
+    hipError_t rc = hipGetDeviceCount(&n);
+    if (rc != hipSuccess) return no_ctx_fail(PGCP_E_HIP, std::string("hipGetDeviceCount: ") + hipGetErrorString(rc));
+    if (hip_device < 0 || hip_device >= n)
+        return no_ctx_fail(PGCP_E_HIP, "device " + std::to_string(hip_device) + " of " + std::to_string(n));
+    rc = hipSetDevice(hip_device);
+    if (rc != hipSuccess) return no_ctx_fail(PGCP_E_HIP, std::string("hipSetDevice: ") + hipGetErrorString(rc));
     pgcp_ctx* c = new (std::nothrow) pgcp_ctx();
-    if (!c) return PGCP_E_NOMEM;
+    if (!c) return no_ctx_fail(PGCP_E_NOMEM, "out of host memory");
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
@@ -64,7 +77,7 @@ pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream) {
 
 void pgcp_ctx_destroy(pgcp_ctx* ctx) { delete ctx; }
 
-const char* pgcp_last_error(const pgcp_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+const char* pgcp_last_error(const pgcp_ctx* ctx) { return ctx ? ctx->last_error.c_str() : no_ctx_error.c_str(); }
 
 pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream) {
     if (!ctx) return PGCP_E_INVALID;
