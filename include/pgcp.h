@@ -255,6 +255,24 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                             int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * per-face outputs and statistics as pgcp_distortion (same kernels, bitwise
+ * the same results), without quantiles (median_abs_d and iqr_abs_d are NaN).
+ * Allocates nothing: the per-workgroup partial sums live in a fixed device
+ * array of the library (about 2 MiB per device, held until the process ends),
+ * which limits a call to pgcp_distortion_noalloc_max_faces() faces
+ * (8,388,608); larger nf is PGCP_E_INVALID, checked before anything else.
+ * Every call on one device shares that array: calls that overlap on one device
+ * (contexts on several streams or threads) race and must be ordered by the
+ * caller.  stats may be NULL (then asynchronous on the context's stream);
+ * otherwise the call copies the final record to the host and synchronises. */
+pgcp_status pgcp_distortion_noalloc(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
+                                    const int32_t* F_dev, int64_t nf, const double* param_dev,
+                                    int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
+                                    pgcp_dist_stats* stats);
+int64_t pgcp_distortion_noalloc_max_faces(void);
+
 /* Section 6, area distortion.  Per face
  *   d_area(T) = log[(A(phi(T)) / sum A(phi)) / (A(T) / sum A)],
  * A the area of the flat triangle through the face's points (in R^3 for the

@@ -66,7 +66,8 @@ EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_s
            "pgcp_lpc_num_params", "pgcp_lpc_create", "pgcp_lpc_get_params", "pgcp_lpc_destroy", "pgcp_lpc_infer",
            "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows",
            "pgcp_part_row_vertices", "pgcp_area_distortion", "pgcp_area_objective", "pgcp_area_mobius_opt",
-           "pgcp_lpc_save", "pgcp_lpc_load", "pgcp_lpc_step", "pgcp_part_solution"]
+           "pgcp_lpc_save", "pgcp_lpc_load", "pgcp_lpc_step", "pgcp_part_solution", "pgcp_distortion_noalloc",
+           "pgcp_distortion_noalloc_max_faces"]
 PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
 SYSTEMS = {"dncp": 0, "harmonic": 1}
 
@@ -101,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         "pgcp_weld": (I32, [P, P, P, P]),
         "pgcp_harmonic_solve": (I32, [P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
         "pgcp_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P, P, I32, ctypes.POINTER(DistStats)]),
+        "pgcp_distortion_noalloc": (I32, [P, P, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(DistStats)]),
+        "pgcp_distortion_noalloc_max_faces": (I64, []),
         "pgcp_lpc_save": (I32, [P, P, ctypes.c_char_p]),
         "pgcp_lpc_load": (I32, [P, ctypes.c_char_p, ctypes.POINTER(P)]),
         "pgcp_lpc_step": (I32, [P, ctypes.POINTER(I64)]),
@@ -468,6 +471,17 @@ def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantil
                                       ctypes.byref(st) if stats else None))
     out = {k: getattr(st, k) for k, _ in DistStats._fields_} if stats else None
     return out, d, mu, flip
+
+
+def distortion_noalloc(ctx: Context, V_dev, F_dev, param_dev, d=None, mu=None, flip=None, stats=True):
+    """pgcp_distortion_noalloc: the distortion check without any allocation in
+    the library (outputs d [nf][3], mu [nf], flip [nf] are the caller's, or None)."""
+    nv, nf = V_dev.shape[0], F_dev.shape[0]
+    st = DistStats()
+    ctx.check(ctx.lib.pgcp_distortion_noalloc(ctx.h, _ptr(V_dev), nv, _ptr(F_dev), nf, _ptr(param_dev),
+                                              param_dev.shape[1], _ptr(d), _ptr(mu), _ptr(flip),
+                                              ctypes.byref(st) if stats else None))
+    return {k: getattr(st, k) for k, _ in DistStats._fields_} if stats else None
 
 
 def area_distortion(ctx: Context, V_dev, F_dev, param_dev, want_d=False):

@@ -64,6 +64,10 @@ pgcp_status pgcp_ctx_create(pgcp_ctx** out, int hip_device, void* hip_stream) {
     c->device = hip_device;
     c->stream = (hipStream_t)hip_stream;
     (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, hip_device);
+    // device address of the fixed scratch array of pgcp_distortion_noalloc,
+    // once per device, with the device current (a failure is reported by that
+    // entry point; every other call works without the array)
+    (void)pgcp::noalloc_scratch_init(hip_device);
     // keep released pool memory for reuse instead of returning it at every
     // synchronisation (plans of a stream of meshes reuse the same sizes)
     hipMemPool_t pool = nullptr;
@@ -220,6 +224,20 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, cons
     return fail(ctx, pgcp::run_distortion(ctx, V_dev, nv, F_dev, nf, param_dev, dim, d_dev, mu_dev, flip_dev,
                                           want_quantiles, stats));
 }
+
+pgcp_status pgcp_distortion_noalloc(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev,
+                                    int64_t nf, const double* param_dev, int32_t dim, double* d_dev, double* mu_dev,
+                                    uint8_t* flip_dev, pgcp_dist_stats* stats) {
+    // the size limit is checked first, so that it holds whatever else is wrong
+    if (nf > pgcp::noalloc_max_faces()) return bad(ctx, "nf exceeds pgcp_distortion_noalloc's fixed scratch array");
+    if (!ctx || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
+    if (dim != 2 && dim != 3) return bad(ctx, "dim must be 2 or 3");
+    if (nf <= 0 || nv <= 0) return bad(ctx, "empty mesh");
+    return fail(ctx, pgcp::run_distortion_noalloc(ctx, V_dev, F_dev, nf, param_dev, dim, d_dev, mu_dev, flip_dev,
+                                                  stats));
+}
+
+int64_t pgcp_distortion_noalloc_max_faces(void) { return pgcp::noalloc_max_faces(); }
 
 static pgcp_status area_args(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
                              const double* X, int32_t dim) {

@@ -2909,6 +2909,76 @@ Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp
     return e;
 }
 
+// Distortion check without allocation (pgcp_distortion_noalloc).  The
+// per-workgroup partial records of k_distortion and the final record live in a
+// fixed device array: kNoAllocBlocks workgroups of BLOCK faces, so at most
+// kNoAllocMaxFaces faces per call (2 MiB + one record per device, held until
+// the process ends).  In host code `scratch` is only a symbol: its device
+// address on each device comes from hipGetSymbolAddress, taken once per device
+// at context creation with that device current.
+constexpr int64_t kNoAllocBlocks = 32768;
+constexpr int64_t kNoAllocMaxFaces = kNoAllocBlocks * BLOCK;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) DistPart scratch[kNoAllocBlocks + 1];
+static DistPart* g_scratch_ptr[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+Error noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return Error{PGCP_E_INVALID, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return Error{PGCP_OK, ""};
+    void* ptr = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (rc != hipSuccess || !ptr) {
+        g_scratch_err[device] = rc != hipSuccess ? rc : hipErrorInvalidSymbol;
+        (void)hipGetLastError();   // the failure belongs to this entry point only
+        return Error{PGCP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(g_scratch_err[device])};
+    }
+    g_scratch_ptr[device] = (DistPart*)ptr;
+    return Error{PGCP_OK, ""};
+}
+
+int64_t noalloc_max_faces() { return kNoAllocMaxFaces; }
+
+Error run_distortion_noalloc(pgcp_ctx* ctx, const double* V, const int32_t* F, int64_t nf, const double* X,
+                             int dim, double* d, double* mu, uint8_t* flip, pgcp_dist_stats* st) {
+    if (nf > kNoAllocMaxFaces) return Error{PGCP_E_INVALID, "more faces than the fixed scratch array holds"};
+    DistPart* part = nullptr;
+    if (ctx->device >= 0 && ctx->device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        part = g_scratch_ptr[ctx->device];
+    }
+    if (!part)
+        return Error{PGCP_E_HIP, std::string("scratch address of this device not set up: ") +
+                                     hipGetErrorString(g_scratch_err[ctx->device])};
+    hipStream_t s = ctx->stream;
+    const int64_t nblk = (nf + BLOCK - 1) / BLOCK;
+    DistPart* fin = part + kNoAllocBlocks;
+    // every record k_dist_final reads ([0, nblk)) is written by k_distortion
+    // first, so nothing needs clearing between calls
+    k_distortion<<<(unsigned)nblk, BLOCK, 0, s>>>(nf, V, F, X, dim, d, mu, flip, part);
+    HIPCHK(hipGetLastError());
+    k_dist_final<<<1, BLOCK, 0, s>>>(nblk, part, fin);
+    HIPCHK(hipGetLastError());
+    if (st) {
+        DistPart h;
+        HIPCHK(hipMemcpyAsync(&h, fin, sizeof(DistPart), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double n = 3.0 * (double)nf;
+        st->mean_abs_d = h.sum / n;
+        st->sd_abs_d = n > 1 ? std::sqrt(std::max(0.0, (h.sum2 - h.sum * h.sum / n) / (n - 1.0))) : 0.0;
+        st->max_abs_d = h.maxd;
+        st->median_abs_d = NAN;
+        st->iqr_abs_d = NAN;
+        st->max_mu = h.maxmu;
+        st->n_flipped = (int64_t)llround(h.nflip);
+        st->n_mu_ge1 = (int64_t)llround(h.nmu1);
+    }
+    return Error{PGCP_OK, ""};
+}
+
 // Distortion check.  Scratch buffers live in the context-independent statics
 // of this call (allocated per call size).
 Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf, const double* X,

@@ -235,6 +235,10 @@ Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, dou
                       pgcp_solve_stats* st);
 Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp_solve_opts* o,
                    double* out, pgcp_solve_stats* st);
+Error noalloc_scratch_init(int device);
+int64_t noalloc_max_faces();
+Error run_distortion_noalloc(pgcp_ctx* ctx, const double* V, const int32_t* F, int64_t nf, const double* X,
+                             int dim, double* d, double* mu, uint8_t* flip, pgcp_dist_stats* st);
 Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
                      const double* X, int dim, double* d, double* mu, uint8_t* flip, int want_q,
                      pgcp_dist_stats* st);

@@ -183,3 +183,13 @@ def test_row_order_is_reverse_breadth_first(make):
         if n >= 4096 and case.mode == "sphere":
             h_rcm, h_glob = _max_halo(local, G), _max_halo(np.arange(n), G)
             assert h_rcm < h_glob, (i, h_rcm, h_glob)
+
+
+def test_noalloc_distortion_limits_on_the_host():
+    """pgcp_distortion_noalloc checks its face limit before anything else and
+    rejects a missing context, so neither case reaches a device."""
+    L = _lib()
+    cap = int(L.pgcp_distortion_noalloc_max_faces())
+    assert cap == 32768 * 256
+    assert L.pgcp_distortion_noalloc(None, None, 3, None, cap + 1, None, 2, None, None, None, None) == -1
+    assert L.pgcp_distortion_noalloc(None, None, 3, None, 1, None, 2, None, None, None, None) == -1
