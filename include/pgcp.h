@@ -141,6 +141,16 @@ typedef struct {
     int64_t n_mu_ge1;                        /* faces with |mu| >= 1 - 1e-8 */
 } pgcp_dist_stats;
 
+/* Report of pgcp_fold_repair. */
+typedef struct {
+    int32_t passes;           /* repair passes run                                   */
+    int32_t pieces_repaired;  /* pieces solved in at least one pass                  */
+    int64_t flips_before;     /* flipped faces of the map given                      */
+    int64_t flips_after;      /* flipped faces of the map returned                   */
+    int64_t total_iters;      /* CG iterations of the repair solves, summed over pieces */
+    double cg_kernel_ms;      /* summed duration of their batched-CG launches        */
+} pgcp_fold_stats;
+
 typedef struct {
     int64_t nv, nf;
     int32_t n_sub;
@@ -254,6 +264,28 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                             const int32_t* F_dev, int64_t nf, const double* param_dev,
                             int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats);
+
+/* Sections 3.5 and 4.5 (last step of Algorithm 3).  Quasi-conformal fold
+ * repair of a planar (free or disk) map.  A map folds exactly where its
+ * Beltrami coefficient has |mu| >= 1 (a flipped face).  Every piece whose map
+ * has a flipped face gets, on its interior vertices, the map with the same
+ * boundary values whose Beltrami coefficient is the map's own with its modulus
+ * cut at 1 - delta (direction kept): the linear Beltrami solver
+ * div(A_mu grad u) = div(A_mu grad v) = 0 with piecewise-linear elements on
+ * the faces' isometric frames (A_0 = identity gives the cotangent Laplacian),
+ * solved for the pieces concerned by the batched CG (Jacobi, opts'
+ * precision and tolerances; opts may be NULL).  Repeated while a piece still
+ * has a flipped face, up to max_passes passes.  Boundary and seam vertices
+ * keep their values, so the pieces still glue.  V_dev [nv][3] and F_dev
+ * [nf][3] are the mesh given to pgcp_partition; param_dev [nv][2] is the map
+ * (pgcp_harmonic_solve's output), repaired in place.  delta in (0, 1), 0.1 is
+ * the usual choice.  Requires pgcp_assemble_cotan; sphere plans are rejected
+ * (PGCP_E_INVALID).  A repair solve that misses the tolerance returns
+ * PGCP_E_NOCONV with the map as the last completed pass left it.  stats may be
+ * NULL.  Synchronous (the flip count of every pass comes back to the host). */
+pgcp_status pgcp_fold_repair(pgcp_ctx* ctx, pgcp_part* part, const double* V_dev, const int32_t* F_dev,
+                             double* param_dev, double delta, int32_t max_passes,
+                             const pgcp_solve_opts* opts, pgcp_fold_stats* stats);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -53,6 +53,11 @@ class DistStats(ctypes.Structure):
                 ("n_flipped", ctypes.c_int64), ("n_mu_ge1", ctypes.c_int64)]
 
 
+class FoldStats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("pieces_repaired", ctypes.c_int32), ("flips_before", ctypes.c_int64),
+                ("flips_after", ctypes.c_int64), ("total_iters", ctypes.c_int64), ("cg_kernel_ms", ctypes.c_double)]
+
+
 class PartInfo(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("nf", ctypes.c_int64), ("n_sub", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("n_rows", ctypes.c_int64), ("n_bdy", ctypes.c_int64), ("n_seam", ctypes.c_int64),
@@ -67,7 +72,7 @@ EXPORTS = ["pgcp_ctx_create", "pgcp_ctx_destroy", "pgcp_last_error", "pgcp_ctx_s
            "pgcp_lpc_export", "pgcp_lpc_grad", "pgcp_lpc_train_step", "pgcp_part_rows",
            "pgcp_part_row_vertices", "pgcp_area_distortion", "pgcp_area_objective", "pgcp_area_mobius_opt",
            "pgcp_lpc_save", "pgcp_lpc_load", "pgcp_lpc_step", "pgcp_part_solution", "pgcp_distortion_noalloc",
-           "pgcp_distortion_noalloc_max_faces"]
+           "pgcp_distortion_noalloc_max_faces", "pgcp_fold_repair"]
 PGCP_PC_JACOBI, PGCP_PC_LEARNED = 0, 1
 SYSTEMS = {"dncp": 0, "harmonic": 1}
 
@@ -102,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "pgcp_weld": (I32, [P, P, P, P]),
         "pgcp_harmonic_solve": (I32, [P, P, P, ctypes.POINTER(SolveOpts), P, ctypes.POINTER(SolveStats)]),
         "pgcp_distortion": (I32, [P, P, I64, P, I64, P, I32, P, P, P, I32, ctypes.POINTER(DistStats)]),
+        "pgcp_fold_repair": (I32, [P, P, P, P, P, D, I32, ctypes.POINTER(SolveOpts), ctypes.POINTER(FoldStats)]),
         "pgcp_distortion_noalloc": (I32, [P, P, I64, P, I64, P, I32, P, P, P, ctypes.POINTER(DistStats)]),
         "pgcp_distortion_noalloc_max_faces": (I64, []),
         "pgcp_lpc_save": (I32, [P, P, ctypes.c_char_p]),
@@ -455,6 +461,16 @@ def harmonic_solve(ctx: Context, plan: Plan, welded_dev, out=None, stats=True, a
     return out, rep
 
 
+def fold_repair(ctx: Context, plan: Plan, V_dev, F_dev, param_dev, delta=0.1, max_passes=5, **opts):
+    """pgcp_fold_repair: quasi-conformal fold repair of a planar map in place;
+    returns the report as a dict."""
+    o = _opts(**opts)
+    st = FoldStats()
+    ctx.check(ctx.lib.pgcp_fold_repair(ctx.h, plan.h, _ptr(V_dev), _ptr(F_dev), _ptr(param_dev), float(delta),
+                                       int(max_passes), ctypes.byref(o), ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in FoldStats._fields_}
+
+
 def distortion(ctx: Context, V_dev, F_dev, param_dev, want_arrays=False, quantiles=False, stats=True):
     import torch
     nv, nf = V_dev.shape[0], F_dev.shape[0]
@@ -647,7 +663,8 @@ def _run_lanes(ctx: Context, cases, lanes: int, kw):
 
 
 def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inner_tol=0.0,
-        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64", lpc=None):
+        V_dev=None, F_dev=None, quantiles=False, plan=None, times=None, dncp_precision="fp64", lpc=None,
+        repair_folds=True):
     """Algorithm 3 end to end; returns (phi_dev, dist_stats, reports).
 
     V, F, label are host arrays (the partition runs on the host); V_dev/F_dev
@@ -657,6 +674,9 @@ def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inn
     near-null space that FP32 CG cannot resolve).  With `lpc` (an LPC) both
     solves use the learned sparse approximate inverse instead of Jacobi; the
     network runs on the device right before each solve (inside the timing).
+    With repair_folds (planar modes), the harmonic maps then go through the
+    quasi-conformal fold repair (pgcp_fold_repair), which costs one flip count
+    when no face is flipped; its report is reports["fold"].
     """
     import torch
     dev = f"cuda:{ctx.device}"
@@ -686,9 +706,14 @@ def run(ctx: Context, V, F, label, mode="free", precision="fp64", tol=1e-10, inn
                                lpc=lpc)
     sync()
     times["harmonic"] = time.perf_counter() - t
+    fold = None
+    if repair_folds and plan.mode != PGCP_SPHERE:
+        t = time.perf_counter()
+        fold = fold_repair(ctx, plan, V_dev, F_dev, phi, precision=precision, tol=tol, inner_tol=inner_tol)
+        times["fold_repair"] = time.perf_counter() - t
     t = time.perf_counter()
     st, _, _, _ = distortion(ctx, V_dev, F_dev, phi, quantiles=quantiles)
     times["distortion"] = time.perf_counter() - t
     if own_plan:
         plan.close()
-    return phi, st, dict(dncp=rep1, harmonic=rep2, times=times, bdy=bdy_h, welded=welded)
+    return phi, st, dict(dncp=rep1, harmonic=rep2, times=times, bdy=bdy_h, welded=welded, fold=fold)

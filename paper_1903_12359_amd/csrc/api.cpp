@@ -214,6 +214,16 @@ pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* P, const double* welde
     return fail(ctx, e);
 }
 
+pgcp_status pgcp_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev, const int32_t* F_dev,
+                             double* param_dev, double delta, int32_t max_passes, const pgcp_solve_opts* opts,
+                             pgcp_fold_stats* stats) {
+    if (!ctx || !P || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
+    if (P->host_only) return bad(ctx, "host-only plan");
+    pgcp::AllocScope scope(ctx->stream);
+    P->stream = ctx->stream;
+    return fail(ctx, pgcp::run_fold_repair(ctx, P, F_dev, V_dev, param_dev, delta, max_passes, opts, stats));
+}
+
 pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
                             const double* param_dev, int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats) {

@@ -63,7 +63,9 @@ void free_part_device(pgcp_part* P) {
                      &P->d_partial, &P->d_bar, &P->d_gen, &P->d_res, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
                      &P->d_flags, &P->d_row0, &P->d_slicepart,
                      &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
-                     &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp};
+                     &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp, &P->d_sl_ori,
+                     &P->d_lbs_val64, &P->d_lbs_val32, &P->d_lbs_diag64, &P->d_lbs_diag32, &P->d_face_sub,
+                     &P->d_fold_cnt};
     for (DevBuf* b : all) dev_free(*b);
     free_workmap(P->wmap32);
     free_workmap(P->wmap64);
@@ -1777,6 +1779,148 @@ __global__ void __launch_bounds__(BLOCK) k_seam_out(int64_t nseam, const int32_t
     }
 }
 
+// ----------------------------------------------------------------- quasi-conformal fold repair
+
+// Flipped faces of a planar map per piece (signed area <= 0).
+__global__ void __launch_bounds__(BLOCK) k_fold_count(int64_t nf, const int32_t* __restrict__ F,
+                                                       const int32_t* __restrict__ face_sub,
+                                                       const double* __restrict__ X, unsigned* __restrict__ cnt) {
+    const int64_t f = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (f >= nf) return;
+    const int64_t a = F[3 * f], b = F[3 * f + 1], c = F[3 * f + 2];
+    const double ax = X[2 * a], ay = X[2 * a + 1];
+    const double o = (X[2 * b] - ax) * (X[2 * c + 1] - ay) - (X[2 * b + 1] - ay) * (X[2 * c] - ax);
+    if (!(o > 0.0)) atomicAdd(cnt + (face_sub ? face_sub[f] : 0), 1u);
+}
+
+// Contribution of face (t0, t1, t2), in the face's own cyclic order, to entry
+// (p, q) of the linear Beltrami solver's matrix: area * grad phi_p . A grad
+// phi_q in the face's isometric frame, with
+//   A = [[(rho-1)^2 + tau^2, -2 tau], [-2 tau, (rho+1)^2 + tau^2]] / (1 - |mu|^2),
+// mu = rho + i tau the map's Beltrami coefficient on the face, its modulus cut
+// at mu_max.  The frame starts at the cycle's smallest vertex id and p, q are
+// taken in ascending order, so both rows of a symmetric pair get the same bits.
+__device__ double lbs_face_entry(const double* __restrict__ V, const double* __restrict__ X, int t0, int t1, int t2,
+                                 int p, int q, double mu_max) {
+    int a = t0, b = t1, c = t2;
+    if (t1 < t0 && t1 < t2) {
+        a = t1;
+        b = t2;
+        c = t0;
+    } else if (t2 < t0 && t2 < t1) {
+        a = t2;
+        b = t0;
+        c = t1;
+    }
+    const double e1x = V[3 * (int64_t)b] - V[3 * (int64_t)a], e1y = V[3 * (int64_t)b + 1] - V[3 * (int64_t)a + 1],
+                 e1z = V[3 * (int64_t)b + 2] - V[3 * (int64_t)a + 2];
+    const double e2x = V[3 * (int64_t)c] - V[3 * (int64_t)a], e2y = V[3 * (int64_t)c + 1] - V[3 * (int64_t)a + 1],
+                 e2z = V[3 * (int64_t)c + 2] - V[3 * (int64_t)a + 2];
+    const double l1 = sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+    const double x3 = (e1x * e2x + e1y * e2y + e1z * e2z) / l1;
+    const double px = e2x - x3 * e1x / l1, py = e2y - x3 * e1y / l1, pz = e2z - x3 * e1z / l1;
+    const double y3 = sqrt(px * px + py * py + pz * pz);
+    // the map on the frame: a z + b conj(z), mu = b / a
+    //   = (l1 d2 - (x3 + i y3) d1) / (d1 (x3 - i y3) - l1 d2)
+    const double d1x = X[2 * (int64_t)b] - X[2 * (int64_t)a], d1y = X[2 * (int64_t)b + 1] - X[2 * (int64_t)a + 1];
+    const double d2x = X[2 * (int64_t)c] - X[2 * (int64_t)a], d2y = X[2 * (int64_t)c + 1] - X[2 * (int64_t)a + 1];
+    const double nx = l1 * d2x - (x3 * d1x - y3 * d1y), ny = l1 * d2y - (x3 * d1y + y3 * d1x);
+    const double dx = d1x * x3 + d1y * y3 - l1 * d2x, dy = d1y * x3 - d1x * y3 - l1 * d2y;
+    const double nn = sqrt(nx * nx + ny * ny), dn = sqrt(dx * dx + dy * dy);
+    double rho = 0.0, tau = 0.0;
+    if (nn >= mu_max * dn) {
+        // |mu| >= mu_max: modulus mu_max, direction of num / den (of num if den = 0)
+        if (nn > 0.0 && dn > 0.0) {
+            rho = mu_max * (nx * dx + ny * dy) / (nn * dn);
+            tau = mu_max * (ny * dx - nx * dy) / (nn * dn);
+        } else if (nn > 0.0) {
+            rho = mu_max * nx / nn;
+            tau = mu_max * ny / nn;
+        }
+    } else {
+        const double dd = dx * dx + dy * dy;
+        rho = (nx * dx + ny * dy) / dd;
+        tau = (ny * dx - nx * dy) / dd;
+    }
+    const double sc = 1.0 / (1.0 - rho * rho - tau * tau);
+    const double A11 = sc * ((rho - 1.0) * (rho - 1.0) + tau * tau), A12 = sc * (-2.0 * tau),
+                 A22 = sc * ((rho + 1.0) * (rho + 1.0) + tau * tau);
+    // corners Q0 = (0, 0), Q1 = (l1, 0), Q2 = (x3, y3); the gradient of corner k
+    // is the opposite edge Q_{k+2} - Q_{k+1} turned by +90 degrees over 2 area
+    const int lo = min(p, q), hi = max(p, q);
+    const int kl = lo == a ? 0 : (lo == b ? 1 : 2), kh = hi == a ? 0 : (hi == b ? 1 : 2);
+    const double Qx[3] = {0.0, l1, x3}, Qy[3] = {0.0, 0.0, y3};
+    const double ex_l = Qx[(kl + 2) % 3] - Qx[(kl + 1) % 3], ey_l = Qy[(kl + 2) % 3] - Qy[(kl + 1) % 3];
+    const double ex_h = Qx[(kh + 2) % 3] - Qx[(kh + 1) % 3], ey_h = Qy[(kh + 2) % 3] - Qy[(kh + 1) % 3];
+    // area * (g_l . A g_h) with g = (-ey, ex) / (2 area), area = l1 y3 / 2
+    const double glx = -ey_l, gly = ex_l, ghx = -ey_h, ghy = ex_h;
+    return (glx * (A11 * ghx + A12 * ghy) + gly * (A12 * ghx + A22 * ghy)) / (2.0 * l1 * y3);
+}
+
+// One thread per packed row: the Beltrami-solver matrix of the current map X
+// on the plan's structure (off-diagonal slot = sum over the edge's one or two
+// faces, diagonal = minus the row's sum).
+__global__ void __launch_bounds__(BLOCK) k_assemble_lbs(
+    int64_t nslices, const int64_t* __restrict__ sl_ptr, const int32_t* __restrict__ sl_w,
+    const int32_t* __restrict__ sl_col, const int32_t* __restrict__ sl_opp, const uint8_t* __restrict__ sl_ori,
+    const int32_t* __restrict__ row_gv, const double* __restrict__ V, const double* __restrict__ X, double mu_max,
+    double* __restrict__ val64, float* __restrict__ val32, double* __restrict__ diag64, float* __restrict__ diag32) {
+    const int64_t row = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    const int64_t s = row >> 6;
+    if (s >= nslices) return;
+    const int lane = (int)(row & 63);
+    const int g = row_gv[row];
+    const int64_t base = sl_ptr[s] + lane;
+    const int w = sl_w[s];
+    double dsum = 0.0;
+    for (int k = 0; k < w; ++k) {
+        const int64_t el = base + (int64_t)k * 64;
+        const int o1 = sl_opp[2 * el], o2 = sl_opp[2 * el + 1];
+        double v = 0.0;
+        if (o1 >= 0 && g >= 0) {
+            const int h = row_gv[sl_col[el]];
+            const int ori = sl_ori[el];
+            v = (ori & 1) ? lbs_face_entry(V, X, g, h, o1, g, h, mu_max) : lbs_face_entry(V, X, h, g, o1, g, h, mu_max);
+            if (o2 >= 0)
+                v += (ori & 2) ? lbs_face_entry(V, X, g, h, o2, g, h, mu_max)
+                               : lbs_face_entry(V, X, h, g, o2, g, h, mu_max);
+        }
+        val64[el] = v;
+        val32[el] = (float)v;
+        dsum -= v;
+    }
+    diag64[row] = dsum;
+    diag32[row] = (float)dsum;
+}
+
+// Dirichlet values of the repair solve: the map's own values on boundary rows,
+// 0 elsewhere.
+__global__ void __launch_bounds__(BLOCK) k_fold_init(int64_t N, const uint8_t* __restrict__ row_kind,
+                                                      const int32_t* __restrict__ row_gv,
+                                                      const double* __restrict__ X, double2* __restrict__ u) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= N) return;
+    double2 v = make_double2(0.0, 0.0);
+    if (row_kind[r] == 1) {
+        const int64_t g = row_gv[r];
+        v = make_double2(X[2 * g], X[2 * g + 1]);
+    }
+    u[r] = v;
+}
+
+// Interior rows of the pieces repaired in this pass write their new value.
+__global__ void __launch_bounds__(BLOCK) k_fold_out(int64_t N, const uint8_t* __restrict__ row_kind,
+                                                     const int32_t* __restrict__ row_gv,
+                                                     const int32_t* __restrict__ slice_sub,
+                                                     const unsigned* __restrict__ cnt,
+                                                     const double2* __restrict__ u, double* __restrict__ X) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= N || row_kind[r] != 0 || cnt[slice_sub[r >> 6]] == 0) return;
+    const int64_t g = row_gv[r];
+    X[2 * g] = u[r].x;
+    X[2 * g + 1] = u[r].y;
+}
+
 // ----------------------------------------------------------------- distortion
 
 __device__ __forceinline__ double angle3(double ux, double uy, double uz, double vx, double vy, double vz) {
@@ -2629,7 +2773,8 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
 // the FP64 residual, then runs one batched PCG (FP64, or FP32 on the scaled
 // residual) on the pieces that have not converged, and adds its correction.
 static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_t* mask,
-                          const pgcp_solve_opts* o, pgcp_solve_stats* st, int system) {
+                          const pgcp_solve_opts* o, pgcp_solve_stats* st, int system,
+                          const int32_t* only = nullptr) {
     hipStream_t s = ctx->stream;
     const int K = P->K;
     // learned preconditioner: network outputs for this system, every piece on
@@ -2729,7 +2874,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
             }
             relres[2 * i] = rel[0];
             relres[2 * i + 1] = rel[1];
-            bool conv = rel[0] <= tol && rel[1] <= tol;
+            bool conv = (only && !only[i]) || (rel[0] <= tol && rel[1] <= tol);   // `only`: pieces to solve
             active[i] = (!conv && !fail[i]) ? 1 : 0;
             n_active += active[i];
             for (int c = 0; c < 2; ++c) {
@@ -2834,7 +2979,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
     }
     bool noconv = false;
     for (int i = 0; i < K; ++i) {
-        bool conv = relres[2 * i] <= tol && relres[2 * i + 1] <= tol;
+        bool conv = (only && !only[i]) || (relres[2 * i] <= tol && relres[2 * i + 1] <= tol);
         if (!conv) noconv = true;
         if (st) {
             if (st->iters) st->iters[i] = it_total[i];
@@ -2906,6 +3051,101 @@ Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp
     k_seam_out<<<grid_for(P->n_seam), BLOCK, 0, s>>>(P->n_seam, (const int32_t*)P->d_seam_gv.p,
                                                       (const double2*)welded, sphere, out);
     HIPCHK(hipGetLastError());
+    return e;
+}
+
+// Quasi-conformal fold repair of the planar maps of every piece (Sections 3.5
+// and 4.5): while a piece's map X has a flipped face, X on its interior is
+// replaced by the solution of the linear Beltrami solver for X's own
+// coefficient cut at modulus 1 - delta, with X's boundary values (batched CG,
+// Jacobi, on the pieces concerned only).
+Error run_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const int32_t* F, const double* V, double* X, double delta,
+                      int max_passes, const pgcp_solve_opts* o, pgcp_fold_stats* fs) {
+    if (!P->assembled) return Error{PGCP_E_INVALID, "pgcp_assemble_cotan has not run"};
+    if (P->mode == PGCP_SPHERE) return Error{PGCP_E_INVALID, "fold repair takes planar (free or disk) maps"};
+    if (!(delta > 0.0 && delta < 1.0)) return Error{PGCP_E_INVALID, "delta must lie in (0, 1)"};
+    if (max_passes < 0) return Error{PGCP_E_INVALID, "max_passes must be >= 0"};
+    hipStream_t s = ctx->stream;
+    const int K = P->K;
+    Error e{PGCP_OK, ""};
+    pgcp_fold_stats out{};
+    if ((e = dev_alloc(P->d_fold_cnt, (size_t)K * 4)).code) return e;
+    // a folding-free map (the usual case) costs one counting pass
+    {
+        unsigned total = 0;
+        k_zero_u32<<<1, 64, 0, s>>>(1, (unsigned*)P->d_fold_cnt.p);
+        k_fold_count<<<grid_for(P->nf), BLOCK, 0, s>>>(P->nf, F, nullptr, X, (unsigned*)P->d_fold_cnt.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&total, P->d_fold_cnt.p, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (total == 0) {
+            if (fs) *fs = out;
+            return e;
+        }
+    }
+    // face -> piece and the slots' face orientation, on first use
+    if (!P->d_face_sub.p && (e = upload(P->d_face_sub, P->face_sub, s)).code) return e;
+    if (!P->d_sl_ori.p && (e = upload(P->d_sl_ori, P->sl_ori, s)).code) return e;
+    if (!P->d_lbs_val64.p) {
+        if ((e = dev_alloc(P->d_lbs_val64, (size_t)P->sell_elems * 8)).code) return e;
+        if ((e = dev_alloc(P->d_lbs_val32, (size_t)P->sell_elems * 4)).code) return e;
+        if ((e = dev_alloc(P->d_lbs_diag64, (size_t)P->N * 8)).code) return e;
+        if ((e = dev_alloc(P->d_lbs_diag32, (size_t)P->N * 4)).code) return e;
+    }
+    pgcp_solve_opts lo{};
+    if (o) lo = *o;
+    lo.precond = PGCP_PC_JACOBI;   // the network was trained on cotangent Laplacians
+    lo.lpc = nullptr;
+    std::vector<unsigned> cnt(K, 0);
+    std::vector<int32_t> only(K, 0), repaired(K, 0);
+    int64_t flips = 0;
+    for (int pass = 0;; ++pass) {
+        k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_fold_cnt.p);
+        k_fold_count<<<grid_for(P->nf), BLOCK, 0, s>>>(P->nf, F, (const int32_t*)P->d_face_sub.p, X,
+                                                        (unsigned*)P->d_fold_cnt.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(cnt.data(), P->d_fold_cnt.p, (size_t)K * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        flips = 0;
+        for (int i = 0; i < K; ++i) flips += cnt[i];
+        if (pass == 0) out.flips_before = flips;
+        if (flips == 0 || pass == max_passes) break;
+        for (int i = 0; i < K; ++i) {
+            only[i] = cnt[i] > 0 ? 1 : 0;
+            repaired[i] |= only[i];
+        }
+        k_assemble_lbs<<<grid_for(P->N), BLOCK, 0, s>>>(
+            P->nslices, (const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
+            (const int32_t*)P->d_sl_opp.p, (const uint8_t*)P->d_sl_ori.p, (const int32_t*)P->d_row_gv.p, V, X,
+            1.0 - delta, (double*)P->d_lbs_val64.p, (float*)P->d_lbs_val32.p, (double*)P->d_lbs_diag64.p,
+            (float*)P->d_lbs_diag32.p);
+        k_fold_init<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p,
+                                                      (const int32_t*)P->d_row_gv.p, X, (double2*)P->d_u64.p);
+        HIPCHK(hipGetLastError());
+        // the solver reads the plan's matrix: lend it the Beltrami-solver values
+        std::swap(P->d_val64, P->d_lbs_val64);
+        std::swap(P->d_val32, P->d_lbs_val32);
+        std::swap(P->d_diag64, P->d_lbs_diag64);
+        std::swap(P->d_diag32, P->d_lbs_diag32);
+        pgcp_solve_stats st{};
+        e = refine_solve(ctx, P, 0, (const uint8_t*)P->d_mask_harm.p, &lo, &st, PGCP_SYS_HARMONIC + 1, only.data());
+        std::swap(P->d_val64, P->d_lbs_val64);
+        std::swap(P->d_val32, P->d_lbs_val32);
+        std::swap(P->d_diag64, P->d_lbs_diag64);
+        std::swap(P->d_diag32, P->d_lbs_diag32);
+        P->solved = -1;
+        out.total_iters += st.total_iters;
+        out.cg_kernel_ms += st.cg_kernel_ms;
+        if (e.code != PGCP_OK) break;
+        k_fold_out<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p,
+                                                     (const int32_t*)P->d_row_gv.p, (const int32_t*)P->d_slice_sub.p,
+                                                     (const unsigned*)P->d_fold_cnt.p, (const double2*)P->d_u64.p, X);
+        HIPCHK(hipGetLastError());
+        out.passes++;
+    }
+    out.flips_after = flips;
+    for (int i = 0; i < K; ++i) out.pieces_repaired += repaired[i];
+    if (fs) *fs = out;
     return e;
 }
 

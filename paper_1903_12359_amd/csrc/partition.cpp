@@ -417,6 +417,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     std::vector<int64_t> rptr(N + 1, 0);
     for (int64_t r = 0; r < N; ++r) rptr[r + 1] = rptr[r] + deg_raw[r];
     bigvec<int32_t> ent_col(rptr[N]), ent_opp(rptr[N]);
+    bigvec<uint8_t> ent_fwd(rptr[N]);   // 1: (row, column, opposite) is the face's own cyclic order
     {
         std::vector<int64_t> fill(rptr.begin(), rptr.end() - 1);
         // rows of different pieces are disjoint: fill piece by piece in parallel
@@ -429,8 +430,10 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
                     int32_t rj = corner_row[3 * f + (c + 2) % 3];
                     int32_t gk = F[3 * f + c];
                     ent_col[fill[ri]] = rj;
+                    ent_fwd[fill[ri]] = 1;
                     ent_opp[fill[ri]++] = gk;
                     ent_col[fill[rj]] = ri;
+                    ent_fwd[fill[rj]] = 0;
                     ent_opp[fill[rj]++] = gk;
                 }
             }
@@ -439,6 +442,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     // merge duplicates: unique columns ascending, up to two opposite vertices
     std::vector<int32_t> deg(N, 0);
     bigvec<int32_t> u_col(rptr[N]), u_o1(rptr[N]), u_o2(rptr[N]);
+    bigvec<uint8_t> u_ori(rptr[N]);
     std::vector<std::string> derr(1);
     bool bad_edge = false;
 #pragma omp parallel for schedule(static)
@@ -447,14 +451,17 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
         // insertion sort by (col, opp): rows are short
         for (int64_t a = s + 1; a < e; ++a) {
             int32_t c = ent_col[a], o = ent_opp[a];
+            uint8_t fw = ent_fwd[a];
             int64_t b = a - 1;
             while (b >= s && (ent_col[b] > c || (ent_col[b] == c && ent_opp[b] > o))) {
                 ent_col[b + 1] = ent_col[b];
                 ent_opp[b + 1] = ent_opp[b];
+                ent_fwd[b + 1] = ent_fwd[b];
                 b--;
             }
             ent_col[b + 1] = c;
             ent_opp[b + 1] = o;
+            ent_fwd[b + 1] = fw;
         }
         int32_t d = 0;
         for (int64_t a = s; a < e;) {
@@ -464,6 +471,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
             u_col[s + d] = ent_col[a];
             u_o1[s + d] = ent_opp[a];
             u_o2[s + d] = (b - a == 2) ? ent_opp[a + 1] : -1;
+            u_ori[s + d] = (uint8_t)(ent_fwd[a] | ((b - a == 2) ? (ent_fwd[a + 1] << 1) : 0));
             d++;
             a = b;
         }
@@ -492,6 +500,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     P->sl_col.resize(P->sell_elems);
     P->sl_opp.resize(2 * P->sell_elems);
     P->sl_rev.resize(P->sell_elems);
+    P->sl_ori.resize(P->sell_elems);
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < P->nslices; ++s) {
         int64_t base = P->sl_ptr[s];
@@ -504,6 +513,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
                     P->sl_col[el] = c;
                     P->sl_opp[2 * el] = u_o1[rptr[r] + k];
                     P->sl_opp[2 * el + 1] = u_o2[rptr[r] + k];
+                    P->sl_ori[el] = u_ori[rptr[r] + k];
                     // the slot of the reverse entry (c, r): columns of a row are ascending
                     const int32_t* cb = u_col.data() + rptr[c];
                     const int32_t kk = (int32_t)(std::lower_bound(cb, cb + deg[c], (int32_t)r) - cb);
@@ -512,6 +522,7 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
                     P->sl_col[el] = (int32_t)r;
                     P->sl_opp[2 * el] = -1;
                     P->sl_opp[2 * el + 1] = -1;
+                    P->sl_ori[el] = 0;
                     P->sl_rev[el] = -1;
                 }
             }

@@ -136,6 +136,8 @@ struct pgcp_part {
     pgcp::bigvec<int32_t> sl_col;                 // [sell_elems] packed column; padding = own row
     pgcp::bigvec<int32_t> sl_opp;                 // [2*sell_elems] opposite vertices (global ids) or -1
     pgcp::bigvec<int32_t> sl_rev;                 // [sell_elems] slot of the reverse entry, -1 for padding
+    pgcp::bigvec<uint8_t> sl_ori;                 // [sell_elems] bit t: (row, column, opposite t) is that
+                                                  // face's own (counter-clockwise) vertex order
     std::vector<int32_t> pin_row;             // [2K] DNCP pins p0, p1 (packed rows)
     std::vector<double> pin_x1;               // [K] x coordinate of p1 (|v_p1 - v_p0|)
     std::vector<int32_t> loop_ptr;            // [K+1]
@@ -145,7 +147,7 @@ struct pgcp_part {
 
     // ---------------- device mirrors
     pgcp::DevBuf d_row_gv, d_row_prev, d_row_next, d_row_kind, d_slice_sub;
-    pgcp::DevBuf d_sl_ptr, d_sl_w, d_sl_col, d_sl_opp, d_sl_rev;
+    pgcp::DevBuf d_sl_ptr, d_sl_w, d_sl_col, d_sl_opp, d_sl_rev, d_sl_ori;
     pgcp::DevBuf d_val64, d_val32, d_diag64, d_diag32;
     pgcp::DevBuf d_pin_row, d_pin_x1, d_loop_ptr, d_loop_row, d_loop_seam, d_seam_gv;
     pgcp::DevBuf d_mask_dncp, d_mask_harm;    // [N] uint8: 1 = Dirichlet row
@@ -156,6 +158,8 @@ struct pgcp_part {
     pgcp::DevBuf d_partial, d_bar, d_gen, d_res, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
+    // quasi-conformal fold repair: Beltrami-solver matrix, face -> piece, per-piece counts
+    pgcp::DevBuf d_lbs_val64, d_lbs_val32, d_lbs_diag64, d_lbs_diag32, d_face_sub, d_fold_cnt;
     pgcp::WorkMap wmap32, wmap64;
 
     // ---------------- learned preconditioner (network states, SPAI values, training work space)
@@ -235,6 +239,8 @@ Error run_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* o, dou
                       pgcp_solve_stats* st);
 Error run_harmonic(pgcp_ctx* ctx, pgcp_part* P, const double* welded, const pgcp_solve_opts* o,
                    double* out, pgcp_solve_stats* st);
+Error run_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const int32_t* F, const double* V, double* X, double delta,
+                      int max_passes, const pgcp_solve_opts* o, pgcp_fold_stats* fs);
 Error noalloc_scratch_init(int device);
 int64_t noalloc_max_faces();
 Error run_distortion_noalloc(pgcp_ctx* ctx, const double* V, const int32_t* F, int64_t nf, const double* X,
