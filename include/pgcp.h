@@ -144,11 +144,14 @@ typedef struct {
 /* Report of pgcp_fold_repair. */
 typedef struct {
     int32_t passes;           /* repair passes run                                   */
-    int32_t pieces_repaired;  /* pieces solved in at least one pass                  */
+    int32_t pieces_repaired;  /* pieces with at least one kept pass                  */
     int64_t flips_before;     /* flipped faces of the map given                      */
     int64_t flips_after;      /* flipped faces of the map returned                   */
     int64_t total_iters;      /* CG iterations of the repair solves, summed over pieces */
     double cg_kernel_ms;      /* summed duration of their batched-CG launches        */
+    int32_t pieces_stopped;   /* pieces whose last pass did not lower their flip count
+                                 and was undone                                       */
+    int32_t reserved;
 } pgcp_fold_stats;
 
 typedef struct {
@@ -275,7 +278,9 @@ pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
  * the faces' isometric frames (A_0 = identity gives the cotangent Laplacian),
  * solved for the pieces concerned by the batched CG (Jacobi, opts'
  * precision and tolerances; opts may be NULL).  Repeated while a piece still
- * has a flipped face, up to max_passes passes.  Boundary and seam vertices
+ * has a flipped face, up to max_passes passes; a pass that does not lower a
+ * piece's count of flipped faces is undone and ends that piece's repair (its
+ * welded boundary itself may fold).  Boundary and seam vertices
  * keep their values, so the pieces still glue.  V_dev [nv][3] and F_dev
  * [nf][3] are the mesh given to pgcp_partition; param_dev [nv][2] is the map
  * (pgcp_harmonic_solve's output), repaired in place.  delta in (0, 1), 0.1 is

@@ -28,7 +28,10 @@ piecewise-linear finite elements in each face's isometric frame, mu constant on
 the face: K_pq = sum over faces T of area(T) grad(phi_p) . A_T grad(phi_q), with
 the boundary rows eliminated as in the harmonic step.  For mu = 0, A is the
 identity and K is the cotangent Laplacian.  The pass is repeated on the result
-while a face of the subdomain is still flipped, up to `max_passes`.
+while a face of the subdomain is still flipped, up to `max_passes`; a pass that
+does not lower the subdomain's count of flipped faces is undone and ends its
+repair (a subdomain whose welded boundary itself folds cannot be unfolded with
+that boundary kept, and chopping there only spreads the fold).
 
 The face's frame follows the face's own vertex order (counter-clockwise on the
 surface): vertex 0 at 0, vertex 1 on the positive real axis, vertex 2 in the
@@ -124,8 +127,8 @@ def beltrami_solve(P, T, loop_local, mu, ub):
 
 
 def fold_repair(P, T, loop_local, X, delta=0.1, max_passes=5):
-    """Repair of one subdomain's planar map X [n, 2].  Returns (X', passes run,
-    flipped faces before each pass and after the last)."""
+    """Repair of one subdomain's planar map X [n, 2].  Returns (X', passes kept,
+    flipped faces before each kept pass and after the last)."""
     X = np.asarray(X, dtype=np.float64).copy()
     B = np.asarray(loop_local, dtype=np.int64)
     flips = [int((orientation(X, T) <= 0.0).sum())]
@@ -133,7 +136,11 @@ def fold_repair(P, T, loop_local, X, delta=0.1, max_passes=5):
     while flips[-1] > 0 and passes < max_passes:
         mu = chop(beltrami(P, T, X), delta)
         z = beltrami_solve(P, T, B, mu, X[B, 0] + 1j * X[B, 1])
-        X = np.column_stack([z.real, z.imag])
+        Y = np.column_stack([z.real, z.imag])
+        n_flip = int((orientation(Y, T) <= 0.0).sum())
+        if n_flip >= flips[-1]:
+            break                    # no progress: keep the previous map
+        X = Y
         passes += 1
-        flips.append(int((orientation(X, T) <= 0.0).sum()))
+        flips.append(n_flip)
     return X, passes, flips

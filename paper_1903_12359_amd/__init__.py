@@ -55,7 +55,8 @@ class DistStats(ctypes.Structure):
 
 class FoldStats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_int32), ("pieces_repaired", ctypes.c_int32), ("flips_before", ctypes.c_int64),
-                ("flips_after", ctypes.c_int64), ("total_iters", ctypes.c_int64), ("cg_kernel_ms", ctypes.c_double)]
+                ("flips_after", ctypes.c_int64), ("total_iters", ctypes.c_int64), ("cg_kernel_ms", ctypes.c_double),
+                ("pieces_stopped", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PartInfo(ctypes.Structure):

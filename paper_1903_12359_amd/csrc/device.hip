@@ -61,11 +61,12 @@ void free_part_device(pgcp_part* P) {
                      &P->d_loop_row, &P->d_loop_seam, &P->d_seam_gv, &P->d_mask_dncp, &P->d_mask_harm,
                      &P->d_chart, &P->d_u64, &P->d_r64, &P->d_e, &P->d_r, &P->d_z, &P->d_p0, &P->d_p1, &P->d_q, &P->d_r2, &P->d_s1,
                      &P->d_partial, &P->d_bar, &P->d_gen, &P->d_res, &P->d_subinfo, &P->d_bnorm, &P->d_rnorm, &P->d_iters,
+                     &P->d_cgs,
                      &P->d_flags, &P->d_row0, &P->d_slicepart,
                      &P->d_scale, &P->d_target, &P->d_active, &P->d_status, &P->d_rrout,
                      &P->d_abort, &P->d_distpart, &P->d_diststat, &P->d_absd, &P->d_sorttmp, &P->d_sl_ori,
                      &P->d_lbs_val64, &P->d_lbs_val32, &P->d_lbs_diag64, &P->d_lbs_diag32, &P->d_face_sub,
-                     &P->d_fold_cnt};
+                     &P->d_fold_cnt, &P->d_fold_prev};
     for (DevBuf* b : all) dev_free(*b);
     free_workmap(P->wmap32);
     free_workmap(P->wmap64);
@@ -131,6 +132,7 @@ Error upload_plan(pgcp_ctx* ctx, pgcp_part* P) {
     if ((e = dev_alloc(P->d_target, K * 2 * 8)).code) return e;
     if ((e = dev_alloc(P->d_rrout, K * 2 * 8)).code) return e;
     if ((e = dev_alloc(P->d_iters, K * 4)).code) return e;
+    if ((e = dev_alloc(P->d_cgs, (size_t)K * 16 * 8)).code) return e;
     if ((e = dev_alloc(P->d_status, K * 4)).code) return e;
     if ((e = dev_alloc(P->d_active, K * 4)).code) return e;
     if ((e = dev_alloc(P->d_bar, K * 4)).code) return e;
@@ -353,7 +355,11 @@ struct CGArgs {
     int* abort_flag;
     int32_t* iters;                // [K] out
     double* rr_out;                // [K*2] out: final recursive |r|^2 / |r0|^2
-    int32_t* status;               // [K] out: 0 ok, 1 breakdown, 2 max_iter, 3 abort, 4 stagnation
+    int32_t* status;               // [K] out: 0 ok, 1 breakdown, 2 max_iter, 3 abort, 4 stagnation,
+                                   //   5 paused at pause_at (streaming kernel; state in cgs)
+    double* cgs;                   // [K][16] streaming kernel: scalar state of a paused piece
+    int pause_at;                  // streaming kernel: pause every piece when its iteration count reaches this
+    int resume;                    // streaming kernel: continue paused pieces from cgs and the vectors
     int coupled;
     int max_iter;
     int n_xcd;                     // workgroup g runs on XCD g % n_xcd (round-robin dispatch)
@@ -1361,62 +1367,93 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
     zero.x = (T)0;
     zero.y = (T)0;
 
-    // ---- start: e = 0, z = D^-1 r, p_old = 0
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int s = s0 + wave; s < s1; s += NW) {
-        const int64_t rw = (int64_t)s * 64 + lane;
-        V2 r = zero, z = zero;
-        if (!a.mask[rw]) {
-            r = a.r[rw];
-            if (spai) {
-                z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
-            } else {
-                const T dinv = (T)1 / a.diag[rw];
-                z.x = dinv * r.x;
-                z.y = dinv * r.y;
-            }
-        }
-        a.e[rw] = zero;
-        st_c(a.z + rw, z);
-        st_c(a.pa + rw, zero);
-        acc[0] += (double)r.x * (double)z.x;
-        acc[1] += (double)r.y * (double)z.y;
-        acc[2] += (double)r.x * (double)r.x;
-        acc[3] += (double)r.y * (double)r.y;
-    }
-    bsum<BLK, 4>(acc, lds, bpar);
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
-    }
-    nbar++;
     double st[4];
-    if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
-                             a.abort_flag, lds_flag, lds, bpar)) {
-        if (leader) a.status[sub] = 3;
-        return;
-    }
-    double rz[2] = {st[0], st[1]};
-    double rr0[2] = {st[2], st[3]};
-    if (a.coupled) {
-        rz[0] = rz[1] = st[0] + st[1];
-        rr0[0] = rr0[1] = st[2] + st[3];
+    double rz[2], rr0[2], rrc[2], beta[2] = {0.0, 0.0};
+    bool done[2];
+    double best;
+    int it_best = 0, it = 0;
+    double* cs = a.cgs + 16 * (int64_t)sub;
+    if (!a.resume) {
+        // ---- start: e = 0, z = D^-1 r, p_old = 0
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = s0 + wave; s < s1; s += NW) {
+            const int64_t rw = (int64_t)s * 64 + lane;
+            V2 r = zero, z = zero;
+            if (!a.mask[rw]) {
+                r = a.r[rw];
+                if (spai) {
+                    z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
+                } else {
+                    const T dinv = (T)1 / a.diag[rw];
+                    z.x = dinv * r.x;
+                    z.y = dinv * r.y;
+                }
+            }
+            a.e[rw] = zero;
+            st_c(a.z + rw, z);
+            st_c(a.pa + rw, zero);
+            acc[0] += (double)r.x * (double)z.x;
+            acc[1] += (double)r.y * (double)z.y;
+            acc[2] += (double)r.x * (double)r.x;
+            acc[3] += (double)r.y * (double)r.y;
+        }
+        bsum<BLK, 4>(acc, lds, bpar);
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc[i]);
+        }
+        nbar++;
+        if (piece_reduce<BLK, 4>(bar, a.gen + sub, nbar, nwg, a.partial, pbase, 2, a.res + 8 * (int64_t)sub, st,
+                                 a.abort_flag, lds_flag, lds, bpar)) {
+            if (leader) a.status[sub] = 3;
+            return;
+        }
+        rz[0] = st[0];
+        rz[1] = st[1];
+        rr0[0] = st[2];
+        rr0[1] = st[3];
+        if (a.coupled) {
+            rz[0] = rz[1] = st[0] + st[1];
+            rr0[0] = rr0[1] = st[2] + st[3];
+        }
+        rrc[0] = rr0[0];
+        rrc[1] = rr0[1];
+    } else {
+        // ---- continue a paused piece: e, r, z and p_old are in memory (which
+        // buffers follows from the iteration count), the scalars in cgs
+        rz[0] = cs[0];
+        rz[1] = cs[1];
+        rr0[0] = cs[2];
+        rr0[1] = cs[3];
+        rrc[0] = cs[4];
+        rrc[1] = cs[5];
+        beta[0] = cs[6];
+        beta[1] = cs[7];
+        it = (int)cs[8];
+        it_best = (int)cs[9];
     }
     const double tgt[2] = {a.target_rel2[2 * sub] * rr0[0], a.target_rel2[2 * sub + 1] * rr0[1]};
-    bool done[2] = {rr0[0] <= tgt[0] || !(rz[0] > 0.0), rr0[1] <= tgt[1] || !(rz[1] > 0.0)};
-    double rrc[2] = {rr0[0], rr0[1]};
-    double beta[2] = {0.0, 0.0};
-    double best = (done[0] ? 0.0 : 1.0) + (done[1] ? 0.0 : 1.0);
-    int it_best = 0;
-    int it = 0;
+    if (!a.resume) {
+        done[0] = rr0[0] <= tgt[0] || !(rz[0] > 0.0);
+        done[1] = rr0[1] <= tgt[1] || !(rz[1] > 0.0);
+        best = (done[0] ? 0.0 : 1.0) + (done[1] ? 0.0 : 1.0);
+    } else {
+        done[0] = cs[10] != 0.0;
+        done[1] = cs[11] != 0.0;
+        best = cs[12];
+    }
     int stat = 0;
-    V2* pold = a.pa;
-    V2* pnew = a.pb;
-    V2* rcur = a.r;
-    V2* rnext = a.r2;
+    V2* pold = (it & 1) ? a.pb : a.pa;
+    V2* pnew = (it & 1) ? a.pa : a.pb;
+    V2* rcur = (spai && (it & 1)) ? a.r2 : a.r;
+    V2* rnext = (spai && (it & 1)) ? a.r : a.r2;
 
     while (!(done[0] && done[1])) {
         if (it >= a.max_iter) {
             stat = 2;
+            break;
+        }
+        if (it >= a.pause_at) {
+            stat = 5;
             break;
         }
         // ---- phase A: p_new = z + beta p_old on the fly for every column; q = A p_new; p.q
@@ -1597,6 +1634,21 @@ __global__ void __launch_bounds__(BLK) k_pcg_stream(CGArgs<T> a) {
         a.status[sub] = stat;
         a.rr_out[2 * sub] = rr0[0] > 0.0 ? rrc[0] / rr0[0] : 0.0;
         a.rr_out[2 * sub + 1] = rr0[1] > 0.0 ? rrc[1] / rr0[1] : 0.0;
+        if (stat == 5) {
+            cs[0] = rz[0];
+            cs[1] = rz[1];
+            cs[2] = rr0[0];
+            cs[3] = rr0[1];
+            cs[4] = rrc[0];
+            cs[5] = rrc[1];
+            cs[6] = beta[0];
+            cs[7] = beta[1];
+            cs[8] = (double)it;
+            cs[9] = (double)it_best;
+            cs[10] = done[0] ? 1.0 : 0.0;
+            cs[11] = done[1] ? 1.0 : 0.0;
+            cs[12] = best;
+        }
     }
 }
 
@@ -1906,6 +1958,20 @@ __global__ void __launch_bounds__(BLOCK) k_fold_init(int64_t N, const uint8_t* _
         v = make_double2(X[2 * g], X[2 * g + 1]);
     }
     u[r] = v;
+}
+
+// Interior rows of the pieces whose pass is undone take back their value from
+// before the pass.
+__global__ void __launch_bounds__(BLOCK) k_fold_undo(int64_t N, const uint8_t* __restrict__ row_kind,
+                                                      const int32_t* __restrict__ row_gv,
+                                                      const int32_t* __restrict__ slice_sub,
+                                                      const unsigned* __restrict__ undo,
+                                                      const double* __restrict__ prev, double* __restrict__ X) {
+    const int64_t r = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (r >= N || row_kind[r] != 0 || undo[slice_sub[r >> 6]] == 0) return;
+    const int64_t g = row_gv[r];
+    X[2 * g] = prev[2 * g];
+    X[2 * g + 1] = prev[2 * g + 1];
 }
 
 // Interior rows of the pieces repaired in this pass write their new value.
@@ -2269,7 +2335,8 @@ static void local_numbering(const pgcp_part* P, const std::vector<std::pair<int3
 // longest-processing-time first (workgroups g with g % n_xcd == x run on XCD x
 // under the hardware's round-robin dispatch), every piece on exactly one XCD,
 // so that its per-piece barrier only involves workgroups sharing one L2.
-static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, WorkMap* W, bool* fits) {
+static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, WorkMap* W, bool* fits,
+                           const int32_t* only = nullptr, double wexp = 1.5) {
     *fits = false;
     int n_cu = 0, coop = 0;
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
@@ -2338,18 +2405,26 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     }
     if (cfg.stream && cfg.R <= 0) {
         // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
-        // in proportion to ns_i^1.5 (its rows times its expected CG iterations,
-        // which grow like sqrt(ns_i) for these Laplacians), at least one and at
-        // most one per slice.  Pieces span all XCDs.
+        // in proportion to ns_i^wexp, at least one and at most one per slice.
+        // wexp = 1.5 (a whole solve in one launch): rows times expected CG
+        // iterations, which grow like sqrt(ns_i) for these Laplacians; 1 (a
+        // phase in which every piece runs the same iterations): equal slices
+        // per workgroup.  Pieces span all XCDs.
+        // (`only`: the pieces to map, the others get no workgroup)
         double tw = 0.0;
-        for (int i = 0; i < K; ++i) tw += std::pow((double)((P->row0[i + 1] - P->row0[i]) / 64), 1.5);
+        int k_on = 0;
+        for (int i = 0; i < K; ++i)
+            if (!only || only[i]) {
+                tw += std::pow((double)((P->row0[i + 1] - P->row0[i]) / 64), wexp);
+                k_on++;
+            }
         int64_t G = 0;
-        for (double target = (double)cap; target >= K; target *= 0.97) {
+        for (double target = (double)cap; target >= k_on; target *= 0.97) {
             G = 0;
             for (int i = 0; i < K; ++i) {
                 const int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
-                const double want = target * std::pow((double)ns, 1.5) / tw;
-                nw[i] = std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)std::floor(want)));
+                const double want = target * std::pow((double)ns, wexp) / tw;
+                nw[i] = (only && !only[i]) ? 0 : std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)std::floor(want)));
                 G += nw[i];
             }
             if (G <= cap) break;
@@ -2531,6 +2606,9 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.iters = (int32_t*)P->d_iters.p;
     a.rr_out = (double*)P->d_rrout.p;
     a.status = (int32_t*)P->d_status.p;
+    a.cgs = (double*)P->d_cgs.p;
+    a.pause_at = INT32_MAX;
+    a.resume = 0;
     a.coupled = coupled;
     a.max_iter = max_iter;
     a.n_xcd = W.n_xcd;
@@ -2558,13 +2636,16 @@ static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
 }
 
 static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t* mask, int coupled, int max_iter,
-                        int stall, hipStream_t s, const int32_t* pc = nullptr, bool single = false) {
+                        int stall, hipStream_t s, const int32_t* pc = nullptr, bool single = false,
+                        int pause_at = INT32_MAX, int resume = 0) {
     single = single && W.cg1 && !W.stream;
     dim3 grid(W.n_wg), block(W.blk);
     if (prec) {
         CGArgs<float> a = cg_args<float>(P, W, mask, coupled, max_iter, (const float*)P->d_val32.p,
                                          (const float*)P->d_diag32.p);
         a.stall = stall;
+        a.pause_at = pause_at;
+        a.resume = resume;
         if (pc) {
             a.pc = pc;
             a.mval = (const float*)P->d_mval32.p;
@@ -2583,6 +2664,8 @@ static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t*
         CGArgs<double> a = cg_args<double>(P, W, mask, coupled, max_iter, (const double*)P->d_val64.p,
                                            (const double*)P->d_diag64.p);
         a.stall = stall;
+        a.pause_at = pause_at;
+        a.resume = resume;
         if (pc) {
             a.pc = pc;
             a.mval = (const float*)P->d_mval32.p;
@@ -2766,6 +2849,22 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     return Error{PGCP_OK, ""};
 }
 
+// Phased streaming solves (PGCP_PCG_PHASES=0 turns them off; PGCP_PCG_PHASE0
+// sets the first phase's iteration cap).
+static bool phases_enabled() {
+    const char* v = getenv("PGCP_PCG_PHASES");
+    return !(v && v[0] == '0');
+}
+static int phase_wide() {   // pieces left below which phases use 512-thread workgroups
+    const char* v = getenv("PGCP_PCG_PHASE_WIDE");
+    return v ? atoi(v) : 16;
+}
+static int phase0_cap() {
+    const char* v = getenv("PGCP_PCG_PHASE0");
+    const int c = v ? atoi(v) : 0;
+    return c > 0 ? c : 1024;
+}
+
 // Iterative refinement driver.  u64 holds the Dirichlet values on masked rows
 // and the current iterate elsewhere; solves A u = 0 on the free rows of every
 // piece to ||r||_2 <= tol ||b||_2 (per coordinate unless coupled), where
@@ -2906,14 +3005,77 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         if ((e = prep_inner(P, prec, s)).code) return e;
         if (learned) HIPCHK(hipMemcpyAsync(P->d_pc.p, pc.data(), K * 4, hipMemcpyHostToDevice, s));
         const bool this_single = single && W.cg1 && !W.stream;
+        // Streaming batches run in phases: every piece pauses when its iteration
+        // count reaches the phase's cap (1,024, then doubling) and the pieces
+        // that have not converged continue, from their state in memory, on a
+        // map over them alone, so that the workgroups of finished pieces go to
+        // the slow ones (with at most 16 pieces left, 512-thread workgroups:
+        // fewer of them meet at each per-piece barrier).
+        const bool phased = W.stream && K > 1 && phases_enabled();
+        int cap = phased ? phase0_cap() : INT32_MAX;
         {
+            // every phase runs its pieces for the same iterations: equal slices per workgroup
+            WorkMap W1;
+            bool fits1 = false;
+            if (phased && (e = build_workmap(ctx, P, prec, PcgCfg{W.blk, 0, 1}, &W1, &fits1, active.data(), 1.0)).code)
+                return e;
             std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
             HIPCHK(hipEventRecord(P->ev0, s));
-            if ((e = launch_pcg(P, W, prec, mask, coupled, max_iter, stall, s,
-                                learned ? (const int32_t*)P->d_pc.p : nullptr, this_single)).code)
-                return e;
-            HIPCHK(hipEventRecord(P->ev1, s));
-            HIPCHK(hipEventSynchronize(P->ev1));
+            e = launch_pcg(P, fits1 ? W1 : W, prec, mask, coupled, max_iter, stall, s,
+                           learned ? (const int32_t*)P->d_pc.p : nullptr, this_single, cap, 0);
+            if (e.code == PGCP_OK) HIPCHK(hipEventRecord(P->ev1, s));
+            if (e.code == PGCP_OK) HIPCHK(hipEventSynchronize(P->ev1));
+            free_workmap(W1);
+            if (e.code) return e;
+        }
+        int n_phase = 1;
+        while (phased) {
+            float pm = 0.f;
+            HIPCHK(hipEventElapsedTime(&pm, P->ev0, P->ev1));
+            cg_ms += pm;
+            cg_launches++;
+            if (verbose) fprintf(stderr, "[pgcp]   phase %d took %.2f ms\n", n_phase, pm);
+            int abort_flag = 0;
+            HIPCHK(hipMemcpyAsync(&abort_flag, P->d_abort.p, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(status.data(), P->d_status.p, K * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (abort_flag) return Error{PGCP_E_HIP, "batched CG barrier timed out"};
+            std::vector<int32_t> paused(K, 0);
+            int n_paused = 0;
+            for (int i = 0; i < K; ++i)
+                if (active[i] && status[i] == 5) {
+                    paused[i] = 1;
+                    n_paused++;
+                }
+            if (n_paused == 0) break;
+            WorkMap Wp;
+            bool fits = false;
+            const PcgCfg pcfg{n_paused <= phase_wide() ? 512 : W.blk, 0, 1};
+            if ((e = build_workmap(ctx, P, prec, pcfg, &Wp, &fits, paused.data(), 1.0)).code) return e;
+            cap = cap > INT32_MAX / 2 ? INT32_MAX : 2 * cap;
+            HIPCHK(hipMemcpyAsync(P->d_active.p, paused.data(), K * 4, hipMemcpyHostToDevice, s));
+            k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_bar.p);
+            k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_gen.p);
+            k_zero_u32<<<1, 64, 0, s>>>(16, (unsigned*)P->d_abort.p);
+            HIPCHK(hipGetLastError());
+            {
+                std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
+                HIPCHK(hipEventRecord(P->ev0, s));
+                e = launch_pcg(P, fits ? Wp : W, prec, mask, coupled, max_iter, stall, s,
+                               learned ? (const int32_t*)P->d_pc.p : nullptr, false, cap, 1);
+                if (e.code == PGCP_OK) HIPCHK(hipEventRecord(P->ev1, s));
+                if (e.code == PGCP_OK) HIPCHK(hipEventSynchronize(P->ev1));
+            }
+            free_workmap(Wp);
+            if (e.code) return e;
+            n_phase++;
+            if (verbose)
+                fprintf(stderr, "[pgcp]   phase %d: %d pieces on %d workgroups of %d threads, pause at %d\n",
+                        n_phase, n_paused, fits ? Wp.n_wg : W.n_wg, fits ? pcfg.blk : W.blk, cap);
+        }
+        if (phased) {
+            // the pass's correction is applied to every piece it started with
+            HIPCHK(hipMemcpyAsync(P->d_active.p, active.data(), K * 4, hipMemcpyHostToDevice, s));
         }
         used_single = this_single;
         if (prec) {
@@ -2936,8 +3098,10 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         if (abort_flag) return Error{PGCP_E_HIP, "batched CG barrier timed out"};
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, P->ev0, P->ev1));
-        cg_ms += ms;
-        cg_launches++;
+        if (!phased) {   // a phased pass has counted each of its launches
+            cg_ms += ms;
+            cg_launches++;
+        }
         if (verbose) {
             int mx = 0, nst[5] = {0, 0, 0, 0, 0};
             for (int i = 0; i < K; ++i)
@@ -2945,8 +3109,8 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
                     mx = std::max(mx, iters[i]);
                     nst[std::min(std::max(status[i], 0), 4)]++;
                 }
-            fprintf(stderr, "[pgcp]   cg launch %.2f ms, max iters %d, status ok/brk/maxit/abort/stall %d/%d/%d/%d/%d\n",
-                    ms, mx, nst[0], nst[1], nst[2], nst[3], nst[4]);
+            fprintf(stderr, "[pgcp]   cg launch %.2f ms (last phase), max iters %d, status ok/brk/maxit/abort/stall "
+                    "%d/%d/%d/%d/%d\n", ms, mx, nst[0], nst[1], nst[2], nst[3], nst[4]);
         }
         bool bad = false;
         for (int i = 0; i < K; ++i)
@@ -3096,8 +3260,10 @@ Error run_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const int32_t* F, const doubl
     if (o) lo = *o;
     lo.precond = PGCP_PC_JACOBI;   // the network was trained on cotangent Laplacians
     lo.lpc = nullptr;
-    std::vector<unsigned> cnt(K, 0);
-    std::vector<int32_t> only(K, 0), repaired(K, 0);
+    // the map before the current pass, for pieces whose pass has to be undone
+    if ((e = dev_alloc(P->d_fold_prev, (size_t)P->nv * 16)).code) return e;
+    std::vector<unsigned> cnt(K, 0), prev(K, 0), undo(K, 0), go(K, 0);
+    std::vector<int32_t> only(K, 0), kept(K, 0), stopped(K, 0);
     int64_t flips = 0;
     for (int pass = 0;; ++pass) {
         k_zero_u32<<<grid_for(K), BLOCK, 0, s>>>(K, (unsigned*)P->d_fold_cnt.p);
@@ -3106,14 +3272,44 @@ Error run_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const int32_t* F, const doubl
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(cnt.data(), P->d_fold_cnt.p, (size_t)K * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (pass > 0) {
+            // a pass that did not lower a piece's flip count is undone and ends
+            // that piece's repair (its welded boundary itself may fold)
+            bool any = false;
+            for (int i = 0; i < K; ++i) {
+                undo[i] = (only[i] && cnt[i] >= prev[i]) ? 1u : 0u;
+                if (undo[i]) {
+                    any = true;
+                    stopped[i] = 1;
+                    cnt[i] = prev[i];
+                } else if (only[i]) {
+                    kept[i] = 1;
+                }
+            }
+            if (any) {
+                HIPCHK(hipMemcpyAsync(P->d_fold_cnt.p, undo.data(), (size_t)K * 4, hipMemcpyHostToDevice, s));
+                k_fold_undo<<<grid_for(P->N), BLOCK, 0, s>>>(P->N, (const uint8_t*)P->d_row_kind.p,
+                                                             (const int32_t*)P->d_row_gv.p,
+                                                             (const int32_t*)P->d_slice_sub.p,
+                                                             (const unsigned*)P->d_fold_cnt.p,
+                                                             (const double*)P->d_fold_prev.p, X);
+                HIPCHK(hipGetLastError());
+            }
+        }
         flips = 0;
         for (int i = 0; i < K; ++i) flips += cnt[i];
         if (pass == 0) out.flips_before = flips;
-        if (flips == 0 || pass == max_passes) break;
+        int n_go = 0;
         for (int i = 0; i < K; ++i) {
-            only[i] = cnt[i] > 0 ? 1 : 0;
-            repaired[i] |= only[i];
+            only[i] = (cnt[i] > 0 && !stopped[i]) ? 1 : 0;
+            n_go += only[i];
         }
+        if (n_go == 0 || pass == max_passes) break;
+        for (int i = 0; i < K; ++i) prev[i] = cnt[i];
+        HIPCHK(hipMemcpyAsync(P->d_fold_prev.p, X, (size_t)P->nv * 16, hipMemcpyDeviceToDevice, s));
+        // the pieces of this pass (k_fold_out reads them from d_fold_cnt)
+        for (int i = 0; i < K; ++i) go[i] = (unsigned)only[i];
+        HIPCHK(hipMemcpyAsync(P->d_fold_cnt.p, go.data(), (size_t)K * 4, hipMemcpyHostToDevice, s));
         k_assemble_lbs<<<grid_for(P->N), BLOCK, 0, s>>>(
             P->nslices, (const int64_t*)P->d_sl_ptr.p, (const int32_t*)P->d_sl_w.p, (const int32_t*)P->d_sl_col.p,
             (const int32_t*)P->d_sl_opp.p, (const uint8_t*)P->d_sl_ori.p, (const int32_t*)P->d_row_gv.p, V, X,
@@ -3144,7 +3340,10 @@ Error run_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const int32_t* F, const doubl
         out.passes++;
     }
     out.flips_after = flips;
-    for (int i = 0; i < K; ++i) out.pieces_repaired += repaired[i];
+    for (int i = 0; i < K; ++i) {
+        out.pieces_repaired += kept[i];     // pieces with at least one kept pass
+        out.pieces_stopped += stopped[i];   // pieces whose last pass was undone
+    }
     if (fs) *fs = out;
     return e;
 }

@@ -157,9 +157,10 @@ struct pgcp_part {
     pgcp::DevBuf d_u64, d_r64, d_e, d_r, d_z, d_p0, d_p1, d_q, d_r2, d_s1;
     pgcp::DevBuf d_partial, d_bar, d_gen, d_res, d_subinfo, d_bnorm, d_rnorm, d_iters, d_flags;
     pgcp::DevBuf d_row0, d_slicepart, d_scale, d_target, d_active, d_status, d_rrout, d_abort;
+    pgcp::DevBuf d_cgs;                       // [K][16] scalar state of pieces paused between phases
     pgcp::DevBuf d_distpart, d_diststat, d_absd, d_sorttmp;
     // quasi-conformal fold repair: Beltrami-solver matrix, face -> piece, per-piece counts
-    pgcp::DevBuf d_lbs_val64, d_lbs_val32, d_lbs_diag64, d_lbs_diag32, d_face_sub, d_fold_cnt;
+    pgcp::DevBuf d_lbs_val64, d_lbs_val32, d_lbs_diag64, d_lbs_diag32, d_face_sub, d_fold_cnt, d_fold_prev;
     pgcp::WorkMap wmap32, wmap64;
 
     // ---------------- learned preconditioner (network states, SPAI values, training work space)

@@ -112,6 +112,40 @@ def test_fold_repair_matches_oracle(ctx, name, prec, tol, bound):
     plan.close()
 
 
+def test_fold_repair_undoes_a_pass_that_does_not_help(ctx):
+    """A piece whose DNCP boundary folds over cannot be unfolded with that
+    boundary kept: its pass raises the flip count, is undone (the piece keeps
+    its map bitwise) and ends its repair; the other pieces are repaired as the
+    oracle repairs them."""
+    import paper_1903_12359_amd as pg
+    V, F, lab = folded_grid(128, 3, seed=6)
+    r = pgcp(V, F, lab, "free")
+    X_or = r["phi"].copy()
+    stopped = []
+    for i, s in enumerate(r["subs"]):
+        Xi, p, fl = oracle_fold_repair(s["P"], s["T"], s["loop_local"], r["phi"][s["verts"]])
+        X_or[s["verts"]] = Xi
+        if fl[-1] > 0:
+            stopped.append(i)
+    assert stopped
+    plan = pg.Plan(ctx, V, F, lab, "free")
+    V_dev, F_dev = _dev(V), _dev(F.astype(np.int32))
+    pg.assemble_cotan(ctx, plan, V_dev)
+    X = _dev(r["phi"])
+    rep = pg.fold_repair(ctx, plan, V_dev, F_dev, X, precision="fp64", tol=1e-13)
+    Xg = X.cpu().numpy()
+    err = np.abs(Xg - X_or).max() / np.abs(X_or).max()
+    n_or = int((orientation(X_or, F) <= 0).sum())
+    say("undo case: flips", rep["flips_before"], "->", rep["flips_after"], "oracle", n_or, "stopped",
+        rep["pieces_stopped"], "err", err)
+    assert rep["pieces_stopped"] == len(stopped) and rep["flips_after"] == n_or < rep["flips_before"]
+    for i in stopped:
+        v = r["subs"][i]["verts"]
+        assert np.array_equal(Xg[v], r["phi"][v])
+    assert err <= 1e-9
+    plan.close()
+
+
 def test_folding_free_map_is_left_alone(ctx):
     import paper_1903_12359_amd as pg
     c = small_grid_case(33, 2, 2, seed=1)
@@ -122,7 +156,7 @@ def test_folding_free_map_is_left_alone(ctx):
     X = _dev(r["phi"])
     rep = pg.fold_repair(ctx, plan, V_dev, _dev(c.F.astype(np.int32)), X)
     assert rep == {"passes": 0, "pieces_repaired": 0, "flips_before": 0, "flips_after": 0, "total_iters": 0,
-                   "cg_kernel_ms": 0.0}
+                   "cg_kernel_ms": 0.0, "pieces_stopped": 0, "reserved": 0}
     assert np.array_equal(X.cpu().numpy(), r["phi"])
 
 

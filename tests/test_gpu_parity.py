@@ -355,6 +355,54 @@ def test_pcg_kernels_match_oracle(ctx, kernel, system, monkeypatch):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("name", ["C2_n128", "S5_k12"])
+@pytest.mark.parametrize("system", ["dncp", "harmonic"])
+@pytest.mark.parametrize("variant", ["fp64", "fp32", "learned-fp64"])
+def test_phased_streaming_solves_match_oracle(ctx, name, system, variant, monkeypatch):
+    """Streaming solves in phases: every piece pauses after 8, 16, 32, ...
+    iterations and the unconverged ones continue from their saved state on a
+    map over them alone (with the learned SPAI too, whose residual buffers
+    alternate); the result is the oracle's."""
+    import paper_1903_12359_amd as pg
+    monkeypatch.setenv("PGCP_PCG_CFG", "256,0,1")
+    monkeypatch.setenv("PGCP_PCG_PHASE0", "8")
+    case = CASES[name]()
+    say("phased", name, system, variant)
+    part, subs, bdy_o, welded = _oracle_stages(case)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    prec = "fp32" if variant == "fp32" else "fp64"
+    tol, bound = (1e-11, 1e-6) if prec == "fp32" else (1e-13, 1e-9)
+    net = _lpc_net(ctx) if variant.startswith("learned") else None
+    try:
+        if system == "dncp":
+            b, rep = pg.local_param(ctx, plan, precision=prec, tol=tol, lpc=net)
+            g = b.cpu().numpy()
+            ob = np.concatenate(bdy_o)
+            err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+        else:
+            seam = plan.export()["seam_gv"]
+            wz = np.array([welded[int(v)] for v in seam])
+            wd = _dev(np.column_stack([wz.real, wz.imag]))
+            phi, rep = pg.harmonic_solve(ctx, plan, wd, precision=prec, tol=tol, lpc=net)
+            vals, _ = harmonic_all(subs, welded, case.mode)
+            from oracle.pipeline import assemble
+            phi_o = assemble(case.nv, subs, vals, welded, case.mode)
+            g = phi.cpu().numpy()
+            if case.mode == "sphere":
+                err = np.linalg.norm(g - phi_o, axis=1).max()
+            else:
+                err = np.abs(g - phi_o).max() / np.abs(phi_o).max()
+    finally:
+        if net is not None:
+            net.close()
+    say("  launches", rep.cg_launches, "refinement passes", rep.refine_steps, "iters", int(rep.iters.max()),
+        "err", err)
+    assert rep.cg_stream == 1 and rep.cg_launches > rep.refine_steps   # paused and continued
+    assert (rep.status == 0).all() and rep.relres.max() <= tol
+    assert err <= bound
+
+
 def test_c2_full_size_stagewise(ctx):
     """C2 at full size (512^2 vertices, 16 pieces): DNCP, weld (the device zipper
     on arcs of up to 512 points) and harmonic against the oracle."""
