@@ -83,12 +83,17 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def make_case(name, blocks=None):
+def make_case(name, blocks=None, parts=None):
     from synth import case_c1, case_c2, case_c3, case_c5
     if blocks is not None:
         if name != "c2":
             raise SystemExit("--blocks applies to the c2 workload only")
-        return case_c2(blocks=blocks)
+        bx, _, by = str(blocks).partition("x")
+        return case_c2(blocks=(int(bx), int(by or bx)))
+    if parts is not None:
+        if name != "c5":
+            raise SystemExit("--parts applies to the c5 workload only")
+        return case_c5(nparts=int(parts))
     return {"c1": case_c1, "c2": case_c2, "c3": case_c3, "c5": case_c5}[name]()
 
 
@@ -320,8 +325,10 @@ def main():
                     help="a second workload timed the same way with --extra-steps steps (extra keys of the line)")
     ap.add_argument("--extra-steps", type=int, default=10)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--blocks", type=int, default=None,
-                    help="c2 only: cut the height field into blocks x blocks pieces (default 4: 16 pieces)")
+    ap.add_argument("--blocks", default=None,
+                    help="c2 only: cut the height field into B x B (or BXxBY) blocks (default 4: 16 pieces)")
+    ap.add_argument("--parts", type=int, default=None,
+                    help="c5 only: number of log-normal guillotine pieces (default 256)")
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
     ap.add_argument("--lpc-steps", type=int, default=500, help="GPU training steps of the learned preconditioner")
     ap.add_argument("--lpc-set", default="c4", choices=["c4", "small"],
@@ -348,7 +355,7 @@ def main():
     pg.load_library()
     dev = "cuda:0"
     t0 = time.perf_counter()
-    case = make_case(args.workload, args.blocks)
+    case = make_case(args.workload, args.blocks, args.parts)
     print(f"[bench] workload {case.name}: nv={case.nv} nf={case.nf} ({time.perf_counter() - t0:.1f}s to generate)",
           file=sys.stderr, flush=True)
     V_dev = torch.from_numpy(case.V).to(dev)
@@ -457,7 +464,8 @@ def measure(pg, torch, ctx, case, V_dev, F_dev, args, dev):
         if k in res:
             res[k]["phi"] = None
 
-    if args.extra != "none" and args.extra != args.workload and args.blocks is None:
+    custom = args.blocks is not None or args.parts is not None
+    if args.extra != "none" and args.extra != args.workload and not custom:
         xc = make_case(args.extra)
         xV = torch.from_numpy(xc.V).to(dev)
         xF = torch.from_numpy(xc.F.astype(np.int32)).to(dev)
@@ -478,7 +486,7 @@ def measure(pg, torch, ctx, case, V_dev, F_dev, args, dev):
         rec["extra"] = {xc.name: xr}
         del xV, xF
 
-    if not args.no_cpu_baseline and args.blocks is None:
+    if not args.no_cpu_baseline and not custom:
         procs = max(1, min(len(os.sched_getaffinity(0)), 16, args.oracle_pieces))
         labels = sample_labels(case.label, args.oracle_pieces)
         print(f"[bench] CPU oracle on {len(labels)} pieces with {procs} worker processes", file=sys.stderr,

@@ -139,8 +139,9 @@ def case_c1() -> MeshCase:
     return MeshCase("C1", V, F, block_labels(n, 2, 2), "disk", dict(n=n, bx=2, by=2))
 
 
-def case_c2(n: int = 512, blocks: int = 4, clip_frac: float = 0.15) -> MeshCase:
-    """512x512 grid, 8 Gaussian bumps, x/y jitter N(0,1e-3) clipped at 0.15 h, 4x4 blocks.
+def case_c2(n: int = 512, blocks=4, clip_frac: float = 0.15) -> MeshCase:
+    """512x512 grid, 8 Gaussian bumps, x/y jitter N(0,1e-3) clipped at 0.15 h, 4x4 blocks
+    (`blocks`: b for b x b blocks, or (bx, by)).
 
     The jitter is drawn per component and truncated to |delta| <= clip_frac*h;
     z is evaluated at the jittered (x, y).  sigma = 1e-3 is 0.51 h on this grid;
@@ -155,8 +156,9 @@ def case_c2(n: int = 512, blocks: int = 4, clip_frac: float = 0.15) -> MeshCase:
     xy = xy + _jitter(rng, n, 1e-3, clip_frac)
     z = f(xy[:, 0], xy[:, 1])
     V = np.column_stack([xy, z])
-    return MeshCase("C2" if n == 512 else f"C2_n{n}", V, F, block_labels(n, blocks, blocks),
-                    "free", dict(n=n, bx=blocks, by=blocks, clip_frac=clip_frac, **meta))
+    bx, by = (blocks, blocks) if np.isscalar(blocks) else blocks
+    return MeshCase("C2" if n == 512 else f"C2_n{n}", V, F, block_labels(n, bx, by),
+                    "free", dict(n=n, bx=bx, by=by, clip_frac=clip_frac, **meta))
 
 
 # ----------------------------------------------------------------------------
