@@ -124,24 +124,33 @@ def _relu(z):
     return np.maximum(z, 0.0)
 
 
-def forward(P: dict, G: dict, keep: bool = False):
-    """Outputs (o_e per directed edge, o_v per vertex); with keep, the activations."""
+def _same(x):
+    return x
+
+
+def forward(P: dict, G: dict, keep: bool = False, rnd=None):
+    """Outputs (o_e per directed edge, o_v per vertex); with keep, the activations.
+
+    rnd (default: none) rounds the stored states where a reduced-precision
+    implementation stores them: the input encodings, every edge message, every
+    mean aggregation and every node state; the network is defined without it."""
+    rnd = rnd or _same
     src, dst, val = G["src"], G["dst"], G["val"]
     n = G["n"]
     zx = G["x"] @ P["W_x"] + P["b_x"]
-    h = _relu(zx)
+    h = rnd(_relu(zx))
     zy = G["y"] @ P["W_y"] + P["b_y"]
-    e = _relu(zy)
+    e = rnd(_relu(zy))
     acts = dict(zx=zx, zy=zy, h=[h], e=[e], ze=[], zv=[], g=[])
     for r in range(ROUNDS):
         X = np.concatenate([h[src], h[dst], e], axis=1)
         ze = X @ P[f"W_e{r}"] + P[f"b_e{r}"]
-        m = _relu(ze)
+        m = rnd(_relu(ze))
         g = np.zeros((n, WIDTH))
         np.add.at(g, src, m)
-        g /= np.maximum(val, 1.0)[:, None]
+        g = rnd(g / np.maximum(val, 1.0)[:, None])
         zv = np.concatenate([h, g], axis=1) @ P[f"W_v{r}"] + P[f"b_v{r}"]
-        h = _relu(zv)
+        h = rnd(_relu(zv))
         e = m
         acts["ze"].append(ze)
         acts["zv"].append(zv)
@@ -206,8 +215,13 @@ def output_grads(G: dict, o_e: np.ndarray, o_v: np.ndarray, A: sp.spmatrix, V: n
     return go_e, go_v
 
 
-def backward(P: dict, G: dict, acts: dict, go_e: np.ndarray, go_v: np.ndarray) -> dict:
-    """Parameter gradients from the output gradients (plain reverse-mode, by hand)."""
+def backward(P: dict, G: dict, acts: dict, go_e: np.ndarray, go_v: np.ndarray, rnd=None) -> dict:
+    """Parameter gradients from the output gradients (plain reverse-mode, by hand).
+
+    rnd (default: none) rounds the pre-activation gradients of the edge and
+    vertex layers, where a reduced-precision implementation feeds them to its
+    matrix products; rounding is otherwise transparent to differentiation."""
+    rnd = rnd or _same
     src, dst, val, rev = G["src"], G["dst"], G["val"], G["rev"]
     n = G["n"]
     grad = {}
@@ -223,7 +237,7 @@ def backward(P: dict, G: dict, acts: dict, go_e: np.ndarray, go_v: np.ndarray) -
     for r in reversed(range(ROUNDS)):
         h_in, e_in = acts["h"][r], acts["e"][r]
         g, zv, ze = acts["g"][r], acts["zv"][r], acts["ze"][r]
-        dzv = dh * (zv > 0)
+        dzv = rnd(dh * (zv > 0))
         Xv = np.concatenate([h_in, g], axis=1)
         grad[f"W_v{r}"] = Xv.T @ dzv
         grad[f"b_v{r}"] = dzv.sum(0)
@@ -231,7 +245,7 @@ def backward(P: dict, G: dict, acts: dict, go_e: np.ndarray, go_v: np.ndarray) -
         dh_in = dXv[:, :WIDTH].copy()
         dg = dXv[:, WIDTH:]
         dm = de + dg[src] / np.maximum(val, 1.0)[src, None]
-        dze = dm * (ze > 0)
+        dze = rnd(dm * (ze > 0))
         Xe = np.concatenate([h_in[src], h_in[dst], e_in], axis=1)
         grad[f"W_e{r}"] = Xe.T @ dze
         grad[f"b_e{r}"] = dze.sum(0)
@@ -249,15 +263,16 @@ def backward(P: dict, G: dict, acts: dict, go_e: np.ndarray, go_v: np.ndarray) -
     return grad
 
 
-def loss_and_grad(P: dict, batch) -> tuple[float, dict]:
-    """Mean loss over a batch of (G, A, V) and its parameter gradient."""
+def loss_and_grad(P: dict, batch, rnd=None) -> tuple[float, dict]:
+    """Mean loss over a batch of (G, A, V) and its parameter gradient (rnd: see
+    forward and backward)."""
     total = 0.0
     grad = {n: np.zeros(s) for n, s in PARAM_SHAPES}
     for G, A, V in batch:
-        o_e, o_v, acts = forward(P, G, keep=True)
+        o_e, o_v, acts = forward(P, G, keep=True, rnd=rnd)
         total += loss(spai(G, o_e, o_v), A, V)
         go_e, go_v = output_grads(G, o_e, o_v, A, V)
-        g = backward(P, G, acts, go_e, go_v)
+        g = backward(P, G, acts, go_e, go_v, rnd=rnd)
         for k in grad:
             grad[k] += g[k]
     nb = len(batch)

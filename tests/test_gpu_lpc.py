@@ -1,14 +1,19 @@
 """Learned SPAI preconditioner on the GPU (libpgcp) against the FP64 oracle.
 
-The network's weight matrices are bf16 on the device; the oracle gets the same
-bf16-rounded values, so what remains is the bf16 rounding of activations and
-gradient tiles (8 significant bits, about 0.4% per rounding) and the order of
-fp32 accumulation: outputs agree to a few percent of their scale and the
-gradient to a few percent in norm, far inside what matters for a
-preconditioner.  Everything the network feeds exactly is checked exactly: zero
-outputs give Jacobi, and a learned solve reaches the same solution as Jacobi to
-the parity bound.  Training on the GPU must lower the loss and cut CG
-iterations on held-out pieces.
+The network keeps its weight matrices, stored states (input encodings, edge
+messages, mean aggregations, node states) and the pre-activation gradients it
+feeds to its matrix products in bf16.  The oracle is given the same bf16
+weights, and its forward and backward passes round at those same points
+(oracle.lpc, `rnd`; edge inputs in fp32 as the device computes them), so what
+remains is the order of fp32 accumulation, which can move a state that sits
+next to a bf16 rounding midpoint by one bf16 step: outputs agree to 1e-3 of
+their scale in RMS (1e-2 at worst), the loss to 1e-4 and every parameter
+block of the gradient to 1e-3 (measured: 1e-5 to 2e-4), tight enough that a
+dropped or mis-scaled term would show.  Against the unrounded FP64 oracle the same gradient is off by
+1-2% (the bf16 rounding itself).  Everything the network feeds exactly is
+checked exactly: zero outputs give Jacobi, and a learned solve reaches the
+same solution as Jacobi to the parity bound.  Training on the GPU must lower
+the loss and cut CG iterations on held-out pieces.
 """
 import sys
 
@@ -61,6 +66,23 @@ def random_params(seed=0):
     return olpc.flatten(P).astype(np.float32)
 
 
+def f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def emulated_graph(G):
+    """The graph's inputs as the device forms them: a in fp32, a^2 of that in
+    fp32, valence / 6 in fp32."""
+    G = dict(G)
+    y = G["y"].copy()
+    a = f32(y[:, 0])
+    y[:, 0], y[:, 1] = a, f32(a * a)
+    x = G["x"].copy()
+    x[:, 2] = f32(x[:, 2])
+    G["x"], G["y"] = x, y
+    return G
+
+
 def oracle_params(theta32):
     """The parameters as the device uses them: weight matrices rounded to bf16."""
     P = olpc.unflatten(theta32.astype(np.float64))
@@ -103,13 +125,18 @@ def test_forward_matches_oracle(ctx, name, system):
     net.infer(plan, system)
     for i, pm in enumerate(piece_masks(case)):
         G = olpc.graph(pm["L"], pm[system])
-        o_e, o_v = olpc.forward(Po, G)
+        o_e, o_v = olpc.forward(Po, emulated_graph(G), rnd=bf16_round)
         M = olpc.spai(G, o_e, o_v)
         go_e, go_v, gm_e, gm_d = net.export(plan, i)
         scale = max(np.abs(o_e).max(), np.abs(o_v).max())
-        err = max(np.abs(go_e - o_e).max(), np.abs(go_v - o_v).max()) / scale
-        say(name, system, "piece", i, "output rel err", err)
-        assert err < 3e-2
+        dev = np.r_[go_e - o_e, go_v - o_v] / scale
+        err, rms = np.abs(dev).max(), np.sqrt(np.mean(dev ** 2))
+        say(name, system, "piece", i, "output rel err max", err, "rms", rms)
+        # a state that lands next to a bf16 rounding midpoint may round the
+        # other way under a different fp32 summation order (one bf16 step,
+        # 2^-8 relative, of that state): a few outputs move by ~1e-3 of the
+        # scale; a wrong term would move all of them
+        assert err < 1e-2 and rms < 1e-3
         # M from the device outputs must be exactly the oracle's formula of them
         off = olpc.spai(G, go_e, go_v).tocsr()
         dm = off.diagonal()
@@ -117,7 +144,7 @@ def test_forward_matches_oracle(ctx, name, system):
         offv = np.asarray(off[G["src"], G["dst"]]).ravel()
         assert np.abs(gm_e - offv).max() <= 1e-12 * max(np.abs(offv).max(), 1e-300)
         # and close to the oracle's M
-        assert np.abs(gm_d - M.diagonal()).max() <= 5e-2 * np.abs(M.diagonal()).max()
+        assert np.abs(gm_d - M.diagonal()).max() <= 1e-2 * np.abs(M.diagonal()).max()
 
 
 def test_zero_network_is_jacobi(ctx):
@@ -158,31 +185,40 @@ def _probe_batch(plan, V, case, system):
     return batch
 
 
+@pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("system", ["harmonic", "dncp"])
-def test_gradient_matches_oracle(ctx, system):
+def test_gradient_matches_oracle(ctx, name, system):
+    """Loss and parameter gradient of the device's training step against the
+    oracle's hand-derived backward pass, both rounding at the same points:
+    every parameter block to 1e-3 relative."""
     import paper_1903_12359_amd as pg
-    case = CASES["g33_2x2"]()
+    case = CASES[name]()
     theta = random_params(2)
     plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
     pg.assemble_cotan(ctx, plan, _dev(case.V))
     net = pg.LPC(ctx, theta)
     V = _probes(plan, 6, seed=5)
     loss, g = net.grad(plan, V, system)
-    lo, go = olpc.loss_and_grad(oracle_params(theta), _probe_batch(plan, V, case, system))
+    batch = [(emulated_graph(G), A, Vi) for G, A, Vi in _probe_batch(plan, V, case, system)]
+    lo, go = olpc.loss_and_grad(oracle_params(theta), batch, rnd=bf16_round)
     go = olpc.flatten(go)
     rel = np.linalg.norm(g - go) / np.linalg.norm(go)
-    cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
-    say(system, "loss", loss, lo, "grad rel err", rel, "cos", cos)
-    assert abs(loss - lo) <= 2e-2 * lo
-    assert rel < 5e-2 and cos > 0.998
-    # every parameter block gets its share of the gradient
+    say(name, system, "loss", loss, lo, "grad rel err", rel)
+    assert abs(loss - lo) <= 1e-4 * lo
+    assert rel <= 3e-4
+    # every parameter block: a dropped or mis-scaled term would move a block by far more
     o = 0
-    for name, shape in olpc.PARAM_SHAPES:
+    worst = 0.0
+    for bn, shape in olpc.PARAM_SHAPES:
         k = int(np.prod(shape, dtype=np.int64))
         a, b = g[o:o + k], go[o:o + k]
-        if np.linalg.norm(b) > 1e-6 * np.linalg.norm(go):
-            assert np.linalg.norm(a - b) <= 0.1 * np.linalg.norm(b) + 1e-6 * np.linalg.norm(go), name
+        nb = np.linalg.norm(b)
+        assert nb > 0.0, bn
+        e = np.linalg.norm(a - b) / nb
+        worst = max(worst, e)
+        assert e <= 1e-3, (bn, e)
         o += k
+    say("  worst parameter block", worst)
 
 
 @pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
