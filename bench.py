@@ -19,10 +19,15 @@ reaches an FP64 relative residual of 1e-10 (per piece; per coordinate for the
 harmonic solve).  Prints one JSON line.
 
 The steps run as a stream (pg.run_stream), as a service that processes a
-stream of meshes would: --lanes N meshes are in flight, each on a host thread
-with its own context and stream, so that the host stages of one (partition,
-weld) overlap the device solves of another; the batched solves themselves take
-the whole device and run one at a time.  Every step still runs every stage;
+stream of meshes would: the host partition of the next mesh runs while the
+current one is on the device (--lanes N > 1 puts N meshes in flight, each on a
+host thread with its own context and stream, so that the host stages of one
+overlap the device solves of another; the batched solves themselves take the
+whole device and run one at a time).  The headline workload runs one lane:
+with several, a streaming batched-CG launch on the 2048^2 field has lost
+workgroups at its first barrier and given up (the library reports it); the
+second workload (--extra, its batches fit the register kernel) runs
+--extra-lanes 3.  Every step still runs every stage;
 `value` is the throughput of the stream (one untimed step on a quiet device
 first lets the autotuner pick the launch shapes, then W warmup steps of the
 stream), and "sequential" reports a few steps run one after the other on one
@@ -60,16 +65,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Per-launch HBM traffic of k_pcg (FETCH_SIZE x2.0 + WRITE_SIZE x1.0 from
-# rocprofv3 counter passes over one timed step, scale factors from a 256 MiB
-# copy), for the kernel and partition sources and launch shapes it was
-# measured with; the summary and commands are in
-# profiles/k_pcg_C2_512x512_16pieces.md.
+# Per-launch HBM traffic of the batched-CG launches (FETCH_SIZE x2.0 +
+# WRITE_SIZE x1.0 from rocprofv3 counter passes over one step, scale factors
+# from a 256 MiB copy), for the kernel and partition sources and launch shapes
+# it was measured with; the summary and commands are in
+# profiles/k_pcg_stream_C5_2048x2048_256pieces.md.
 TRAFFIC = {
-    "c2": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "fc5285c87699e94fd153a2ade192e4d71f9e85c42229fcb514ed8a8930d0b3c0",
-           "pcg_shapes": {"dncp": "256,4,0,0", "harmonic": "256,4,0,0"},
-           "bytes_per_launch": 6.914e9},
+    "c5": {"variant": "learned", "precision": "fp32",
+           "source_sha256": "a3609485775faae897f4a3f6f9f1058fa650a6ad9fbd4ed8caa1543419043687",
+           "pcg_shapes": {"dncp": "512,0,1,0", "harmonic": "256,0,1,0"},
+           "bytes_per_launch": 6.966e11},
 }
 
 
@@ -324,6 +329,8 @@ def main():
     ap.add_argument("--extra", default="c3", choices=["none", "c1", "c2", "c3", "c5"],
                     help="a second workload timed the same way with --extra-steps steps (extra keys of the line)")
     ap.add_argument("--extra-steps", type=int, default=10)
+    ap.add_argument("--extra-lanes", type=int, default=3,
+                    help="meshes in flight for the second workload (its batches fit the register kernel)")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--blocks", default=None,
                     help="c2 only: cut the height field into B x B (or BXxBY) blocks (default 4: 16 pieces)")
@@ -336,7 +343,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-pieces", type=int, default=16,
                     help="pieces of the workload (spread over the size ranking) the CPU oracle runs on")
-    ap.add_argument("--lanes", type=int, default=3, help="meshes in flight in the stream (1: the host partition "
+    ap.add_argument("--lanes", type=int, default=1, help="meshes in flight in the stream (1: the host partition "
                     "of the next mesh overlaps the current one only)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="run the steps one after the other (no host partition of the next step during device work)")
@@ -469,8 +476,10 @@ def measure(pg, torch, ctx, case, V_dev, F_dev, args, dev):
         xc = make_case(args.extra)
         xV = torch.from_numpy(xc.V).to(dev)
         xF = torch.from_numpy(xc.F.astype(np.int32)).to(dev)
-        xargs = argparse.Namespace(**{**vars(args), "steps": args.extra_steps, "warmup": 1})
-        xr = {"nv": xc.nv, "steps": args.extra_steps}
+        xargs = argparse.Namespace(**{**vars(args), "steps": args.extra_steps, "warmup": 1,
+                                      "lanes": args.extra_lanes})
+        xr = {"nv": xc.nv, "steps": args.extra_steps,
+              "lanes": args.extra_lanes if not args.no_pipeline else 1}
         for name, net in (("jacobi", None), ("learned", lpc)):
             if name in res:
                 r = time_variant(pg, ctx, xc, xV, xF, xargs, net, pipeline=not args.no_pipeline)

@@ -187,7 +187,10 @@ pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream);
  * weld merge tree, and uploads it to the device.
  * V_host [nv][3] float64, F_host [nf][3] int32 (counter-clockwise), label_host
  * [nf] int32.  Synchronous.  ctx may be NULL: the plan is then host-only (no
- * device mirrors) and serves pgcp_part_query/export and pgcp_weld only. */
+ * device mirrors) and serves pgcp_part_query/export and pgcp_weld only.
+ * Limits (PGCP_E_INVALID): nv < 2^30, nf < 2^29, at most 134,217,728 vertices
+ * in one piece (the batched CG addresses a piece's vectors with 32-bit byte
+ * offsets). */
 pgcp_status pgcp_partition(pgcp_ctx* ctx, const double* V_host, int64_t nv,
                            const int32_t* F_host, int64_t nf, const int32_t* label_host,
                            int32_t mode, pgcp_part** out);

@@ -336,6 +336,7 @@ struct CGArgs {
     const int32_t* wg_s1;          // [G] end slice
     const int32_t* sub_pbase;      // [K] first partial record of the piece
     const int32_t* sub_nwg;        // [K] workgroups of the piece
+    const int32_t* row0;           // [K+1] first packed row of each piece
     const int32_t* wg_h0;          // [G+1] register kernel: first halo entry of each workgroup
     const int32_t* halo;           // [*] register kernel: packed rows of the halo entries
     const uint16_t* lcol;          // [sell] register kernel: local column of every SELL slot
@@ -441,6 +442,48 @@ __device__ __forceinline__ void st_c(double* p, double v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One piece's rows [row0, row0 + n) of a vector that other workgroups gather
+// or publish within a launch (streaming kernel).  A buffer resource over the
+// piece lets a row's pair (16 bytes in FP64, 8 in FP32) move in one
+// vector-memory instruction with the agent-scope coherence bit (sc1), the same
+// cache policy as the atomics above: an FP64 pair through ld_c / st_c takes two
+// 8-byte instructions, each of which fetches or writes through every line the
+// wave touches, so the pair costs its bytes twice.  Offsets are 32-bit byte
+// counts (pieces hold at most 2^27 rows); an access outside the piece reads 0
+// and a store there is dropped.
+constexpr int kBufWord3 = 0x00020000;   // raw 32-bit elements, no format conversion
+constexpr int kCpolSC1 = 16;            // cache policy: sc1 (coherent at agent scope)
+
+template <typename V2>
+struct PieceVec {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ __forceinline__ PieceVec(const V2* v, int64_t row0, int64_t n)
+        : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<V2*>(v) + row0, 0, (int)(n * (int64_t)sizeof(V2)),
+                                               kBufWord3)) {}
+    __device__ __forceinline__ V2 ld(int lrow) const {
+        V2 r;
+        if constexpr (sizeof(V2) == 16) {
+            const auto u = __builtin_amdgcn_raw_buffer_load_b128(rs, lrow * 16, 0, kCpolSC1);
+            __builtin_memcpy(&r, &u, 16);
+        } else {
+            const auto u = __builtin_amdgcn_raw_buffer_load_b64(rs, lrow * 8, 0, kCpolSC1);
+            __builtin_memcpy(&r, &u, 8);
+        }
+        return r;
+    }
+    __device__ __forceinline__ void st(int lrow, V2 v) const {
+        if constexpr (sizeof(V2) == 16) {
+            __attribute__((ext_vector_type(4))) unsigned u;
+            __builtin_memcpy(&u, &v, 16);
+            __builtin_amdgcn_raw_buffer_store_b128(u, rs, lrow * 16, 0, kCpolSC1);
+        } else {
+            __attribute__((ext_vector_type(2))) unsigned u;
+            __builtin_memcpy(&u, &v, 8);
+            __builtin_amdgcn_raw_buffer_store_b64(u, rs, lrow * 8, 0, kCpolSC1);
+        }
+    }
+};
+
 // Fixed-order sum of the piece's partial records (slots off .. off+NV-1).
 template <int BLK, int NV>
 __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int nwg, int off, double (&out)[NV],
@@ -510,6 +553,58 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
     return z;
 }
 
+// z = M r for one row of the streaming kernel: every column's r through the
+// piece's coherent vector R, or, when Q is given, this iteration's residual
+// rebuilt there as R - alpha Q (see spai_row).  Six slots per batch keep the
+// kernel within its 128 registers with no scratch (a persistent grid must not
+// need scratch: the hardware may run fewer scratch-using waves at once than the
+// grid holds, and the missing workgroups would never reach the barriers).
+template <typename T, typename V2, int NB = 6>
+__device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, V2 rown, int prow0,
+                                              const PieceVec<V2>& R, const PieceVec<V2>* Q = nullptr, T ax = (T)0,
+                                              T ay = (T)0) {
+    const int64_t s = rw >> 6;
+    const int64_t base = a.sl_ptr[s] + (rw & 63);
+    const int w = a.sl_w[s];
+    const T d = (T)a.mdiag[rw];
+    T zx = d * rown.x, zy = d * rown.y;
+    for (int k0 = 0; k0 < w; k0 += NB) {
+        int cc[NB];
+        T mm[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int64_t el = base + (int64_t)(k0 + t) * 64;
+            const bool in = k0 + t < w;
+            mm[t] = in ? (T)a.mval[el] : (T)0;
+            cc[t] = in ? a.sl_col[el] : (int)rw;
+        }
+        V2 rr[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            if (mm[t] == (T)0) {
+                rr[t].x = (T)0;
+                rr[t].y = (T)0;
+            } else {
+                rr[t] = R.ld(cc[t] - prow0);
+                if (Q) {
+                    const V2 qc = Q->ld(cc[t] - prow0);
+                    rr[t].x -= ax * qc.x;
+                    rr[t].y -= ay * qc.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            zx += mm[t] * rr[t].x;
+            zy += mm[t] * rr[t].y;
+        }
+    }
+    V2 z;
+    z.x = zx;
+    z.y = zy;
+    return z;
+}
+
 // Barrier of a piece's workgroups fused with the fixed-order sum of their
 // partial records: the workgroup that arrives last (it sees the counter at
 // target - 1, so every other workgroup's stores have completed) sums the
@@ -549,6 +644,16 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
                     break;
                 }
                 if (spins > SPIN_MAX) {
+                    // the first workgroup to give up records where: the barrier
+                    // it waited at, its piece's workgroups, the arrivals and the
+                    // generation it saw last, its own index
+                    if (__hip_atomic_fetch_add(abort_flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                        abort_flag[2] = (int)nb;
+                        abort_flag[3] = nwg;
+                        abort_flag[4] = (int)__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        abort_flag[5] = (int)__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        abort_flag[6] = (int)blockIdx.x;
+                    }
                     __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ab = 1;
                     break;
@@ -1351,9 +1456,11 @@ __global__ void __launch_bounds__(BLK) k_pcg1(CGArgs<T> a) {
 // Streaming batched PCG, for batches whose rows do not fit in the registers of
 // one cooperative grid.  Same iteration, same per-piece barriers and the same
 // fixed-order reductions as k_pcg, but e, r, z, p and q live in memory and each
-// wave walks any number of its workgroup's slices (s0 + wave + NW j).  z and p
-// are gathered by neighbours, so they are written and read through the
-// coherent path; e, r and q are only touched by the thread that owns the row.
+// wave walks any number of its workgroup's slices (s0 + wave + NW j).  What
+// neighbours gather (z and p; with the SPAI also r and q) is published and
+// gathered through the piece's coherent vectors, one instruction per row pair;
+// a thread reads its own rows back with plain loads (only it writes them within
+// the launch, and a thread sees its own stores).
 template <typename T, int BLK>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(PGCP_STREAM_WPE)))
 k_pcg_stream(CGArgs<T> a) {
@@ -1374,6 +1481,8 @@ k_pcg_stream(CGArgs<T> a) {
     unsigned* bar = a.bar + sub;
     unsigned nbar = 0;
     double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
+    const int prow0 = a.row0[sub];
+    const int64_t prows = (int64_t)a.row0[sub + 1] - prow0;
     V2 zero;
     zero.x = (T)0;
     zero.y = (T)0;
@@ -1393,7 +1502,7 @@ k_pcg_stream(CGArgs<T> a) {
             if (!a.mask[rw]) {
                 r = a.r[rw];
                 if (spai) {
-                    z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, a.r);
+                    z = spai_row_stream<T, V2>(a, rw, r, prow0, PieceVec<V2>(a.r, prow0, prows));
                 } else {
                     const T dinv = (T)1 / a.diag[rw];
                     z.x = dinv * r.x;
@@ -1401,8 +1510,8 @@ k_pcg_stream(CGArgs<T> a) {
                 }
             }
             a.e[rw] = zero;
-            st_c(a.z + rw, z);
-            st_c(a.pa + rw, zero);
+            PieceVec<V2>(a.z, prow0, prows).st((int)(rw - prow0), z);
+            PieceVec<V2>(a.pa, prow0, prows).st((int)(rw - prow0), zero);
             acc[0] += (double)r.x * (double)z.x;
             acc[1] += (double)r.y * (double)z.y;
             acc[2] += (double)r.x * (double)r.x;
@@ -1453,10 +1562,8 @@ k_pcg_stream(CGArgs<T> a) {
         best = cs[12];
     }
     int stat = 0;
-    V2* pold = (it & 1) ? a.pb : a.pa;
-    V2* pnew = (it & 1) ? a.pa : a.pb;
-    V2* rcur = (spai && (it & 1)) ? a.r2 : a.r;
-    V2* rnext = (spai && (it & 1)) ? a.r : a.r2;
+    // p_old / p_new and (SPAI) r / r2 alternate with the iteration count
+    int par = it & 1;
 
     while (!(done[0] && done[1])) {
         if (it >= a.max_iter) {
@@ -1471,13 +1578,16 @@ k_pcg_stream(CGArgs<T> a) {
         const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
         const T cx = done[0] ? (T)0 : (T)1, cy = done[1] ? (T)0 : (T)1;
         double pq[2] = {0.0, 0.0};
+        const V2* pold = par ? a.pb : a.pa;
+        const PieceVec<V2> Zv(a.z, prow0, prows), Pold(pold, prow0, prows), Pnew(par ? a.pa : a.pb, prow0, prows);
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
-            V2 zr = ld_c(a.z + rw), orw = ld_c(pold + rw);
+            const int lr = (int)(rw - prow0);
+            const V2 zr = a.z[rw], orw = pold[rw];
             V2 p;
             p.x = cx * zr.x + bx * orw.x;
             p.y = cy * zr.y + by * orw.y;
-            st_c(pnew + rw, p);
+            Pnew.st(lr, p);
             V2 q = zero;
             if (!a.mask[rw]) {
                 const int64_t base = a.sl_ptr[s] + lane;
@@ -1501,8 +1611,8 @@ k_pcg_stream(CGArgs<T> a) {
                     V2 zz[KS], oo[KS];
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
-                        zz[t] = ld_c(a.z + cc[t]);
-                        oo[t] = ld_c(pold + cc[t]);
+                        zz[t] = Zv.ld(cc[t] - prow0);
+                        oo[t] = Pold.ld(cc[t] - prow0);
                     }
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
@@ -1514,8 +1624,8 @@ k_pcg_stream(CGArgs<T> a) {
                     const int pv = a.rprev[rw];
                     if (pv >= 0) {
                         const int nx = a.rnext[rw];
-                        V2 zn = ld_c(a.z + nx), on = ld_c(pold + nx);
-                        V2 zp = ld_c(a.z + pv), op = ld_c(pold + pv);
+                        const V2 zn = Zv.ld(nx - prow0), on = Pold.ld(nx - prow0);
+                        const V2 zp = Zv.ld(pv - prow0), op = Pold.ld(pv - prow0);
                         const T pNx = cx * zn.x + bx * on.x, pNy = cy * zn.y + by * on.y;
                         const T pPx = cx * zp.x + bx * op.x, pPy = cy * zp.y + by * op.y;
                         qx -= (T)0.5 * (pNy - pPy);
@@ -1528,7 +1638,7 @@ k_pcg_stream(CGArgs<T> a) {
                 pq[1] += (double)p.y * (double)qy;
             }
             if (spai)
-                st_c(a.q + rw, q);   // gathered by the neighbours to rebuild their halo residual
+                PieceVec<V2>(a.q, prow0, prows).st(lr, q);   // gathered by the neighbours to rebuild their residual
             else
                 a.q[rw] = q;
         }
@@ -1566,11 +1676,15 @@ k_pcg_stream(CGArgs<T> a) {
         // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
+        const V2* pnew = par ? a.pa : a.pb;
+        const V2* rcur = (spai && par) ? a.r2 : a.r;
+        const PieceVec<V2> Zw(a.z, prow0, prows);
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
             if (a.mask[rw]) continue;
-            const V2 p = ld_c(pnew + rw), q = spai ? ld_c(a.q + rw) : a.q[rw];
-            V2 e = a.e[rw], r = spai ? ld_c(rcur + rw) : a.r[rw], z;
+            const int lr = (int)(rw - prow0);
+            const V2 p = pnew[rw], q = a.q[rw];
+            V2 e = a.e[rw], r = rcur[rw], z;
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
@@ -1578,9 +1692,10 @@ k_pcg_stream(CGArgs<T> a) {
             a.e[rw] = e;
             if (spai) {
                 // z = M r with the neighbours' new residual rebuilt from rcur and q
-                st_c(rnext + rw, r);
-                z = spai_row<T, V2>(a, rw, r, nullptr, 0, 0, rcur, a.q, ax, ay);
-                st_c(a.z + rw, z);
+                const PieceVec<V2> Qv(a.q, prow0, prows);
+                PieceVec<V2>(par ? a.r : a.r2, prow0, prows).st(lr, r);
+                z = spai_row_stream<T, V2>(a, rw, r, prow0, PieceVec<V2>(rcur, prow0, prows), &Qv, ax, ay);
+                Zw.st(lr, z);
                 acc2[0] += (double)r.x * (double)z.x;
                 acc2[1] += (double)r.y * (double)z.y;
                 acc2[2] += (double)r.x * (double)r.x;
@@ -1591,7 +1706,7 @@ k_pcg_stream(CGArgs<T> a) {
             z.x = dinv * r.x;
             z.y = dinv * r.y;
             a.r[rw] = r;
-            st_c(a.z + rw, z);
+            Zw.st(lr, z);
             acc2[0] += (double)r.x * (double)z.x;
             acc2[1] += (double)r.y * (double)z.y;
             acc2[2] += (double)r.x * (double)r.x;
@@ -1632,14 +1747,7 @@ k_pcg_stream(CGArgs<T> a) {
             stat = 4;
             break;
         }
-        V2* t = pold;
-        pold = pnew;
-        pnew = t;
-        if (spai) {
-            t = rcur;
-            rcur = rnext;
-            rnext = t;
-        }
+        par ^= 1;
     }
     if (leader) {
         a.iters[sub] = it;
@@ -2587,6 +2695,7 @@ static CGArgs<T> cg_args(pgcp_part* P, const WorkMap& W, const uint8_t* mask, in
     a.wg_s1 = (const int32_t*)W.d_wg_s1.p;
     a.sub_pbase = (const int32_t*)W.d_sub_pbase.p;
     a.sub_nwg = (const int32_t*)W.d_sub_nwg.p;
+    a.row0 = (const int32_t*)P->d_row0.p;
     a.wg_h0 = (const int32_t*)W.d_wg_h0.p;
     a.halo = (const int32_t*)W.d_halo.p;
     a.lcol = (const uint16_t*)W.d_lcol.p;
@@ -2647,9 +2756,17 @@ static Error prep_inner(pgcp_part* P, int prec, hipStream_t s) {
     return Error{PGCP_OK, ""};
 }
 
+// The runtime runs cooperative launches on a queue of its own, not on the
+// stream's (a kernel trace of a multi-lane stream shows every lane's batched-CG
+// kernel on one queue and the lanes' other kernels on theirs), so the kernels
+// the stream ran just before (the right-hand side, the zeroed barrier counters
+// and abort words) would be ordered before it only by the runtime's
+// cross-queue dependency.  The host waits for the stream before every
+// cooperative launch instead.
 static Error launch_pcg(pgcp_part* P, const WorkMap& W, int prec, const uint8_t* mask, int coupled, int max_iter,
                         int stall, hipStream_t s, const int32_t* pc = nullptr, bool single = false,
                         int pause_at = INT32_MAX, int resume = 0) {
+    HIPCHK(hipStreamSynchronize(s));
     single = single && W.cg1 && !W.stream;
     dim3 grid(W.n_wg), block(W.blk);
     if (prec) {
@@ -2729,6 +2846,23 @@ static std::mutex g_tuned_mu;
 // the whole device, so two of them must not share it: contexts that solve
 // side by side on their own streams take this lock from the launch to the
 // kernel's end (their other kernels run freely around it).
+// Error for a batched-CG launch whose barrier wait gave up, with the record
+// the first workgroup to give up left in the abort words.
+static Error barrier_error(pgcp_part* P, const std::vector<int32_t>& wg_sub, hipStream_t s, const char* what) {
+    int rec[16] = {0};
+    if (hipMemcpyAsync(rec, P->d_abort.p, sizeof rec, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return Error{PGCP_E_HIP, what};
+    const int wg = rec[6];
+    const int sub = (wg >= 0 && wg < (int)wg_sub.size()) ? wg_sub[wg] : -1;
+    char msg[320];
+    snprintf(msg, sizeof msg,
+             "%s (workgroup %d of %d, piece %d, waited at barrier %d of its piece's %d workgroups: %d arrivals "
+             "of %lld, generation %d)",
+             what, wg, (int)wg_sub.size(), sub, rec[2], rec[3], rec[4], (long long)rec[2] * rec[3], rec[5]);
+    return Error{PGCP_E_HIP, msg};
+}
+
 static std::mutex& coop_mutex(int device) {
     static std::mutex mu[16];
     return mu[(unsigned)device % 16];
@@ -2835,7 +2969,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             HIPCHK(hipEventElapsedTime(&m1, P->ev0, P->ev1));
             int ab = 0;
             HIPCHK(hipMemcpy(&ab, P->d_abort.p, 4, hipMemcpyDeviceToHost));
-            if (ab) return Error{PGCP_E_HIP, "batched CG barrier timed out while tuning"};
+            if (ab) return barrier_error(P, T.wg_sub, s, "batched CG barrier timed out while tuning");
             ms = std::min(ms, m1);
         }
         const char* vb = getenv("PGCP_VERBOSE");
@@ -3025,6 +3159,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         // fewer of them meet at each per-piece barrier).
         const bool phased = W.stream && K > 1 && phases_enabled();
         int cap = phased ? phase0_cap() : INT32_MAX;
+        std::vector<int32_t> last_map;   // piece of every workgroup of the last launch (error reports)
         {
             // every phase runs its pieces for the same iterations: equal slices per workgroup
             WorkMap W1;
@@ -3033,6 +3168,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
                 return e;
             std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
             HIPCHK(hipEventRecord(P->ev0, s));
+            last_map = (fits1 ? W1 : W).wg_sub;
             e = launch_pcg(P, fits1 ? W1 : W, prec, mask, coupled, max_iter, stall, s,
                            learned ? (const int32_t*)P->d_pc.p : nullptr, this_single, cap, 0);
             if (e.code == PGCP_OK) HIPCHK(hipEventRecord(P->ev1, s));
@@ -3051,7 +3187,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
             HIPCHK(hipMemcpyAsync(&abort_flag, P->d_abort.p, 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipMemcpyAsync(status.data(), P->d_status.p, K * 4, hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
-            if (abort_flag) return Error{PGCP_E_HIP, "batched CG barrier timed out"};
+            if (abort_flag) return barrier_error(P, last_map, s, "batched CG barrier timed out");
             std::vector<int32_t> paused(K, 0);
             int n_paused = 0;
             for (int i = 0; i < K; ++i)
@@ -3073,6 +3209,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
             {
                 std::lock_guard<std::mutex> g(coop_mutex(ctx->device));
                 HIPCHK(hipEventRecord(P->ev0, s));
+                last_map = (fits ? Wp : W).wg_sub;
                 e = launch_pcg(P, fits ? Wp : W, prec, mask, coupled, max_iter, stall, s,
                                learned ? (const int32_t*)P->d_pc.p : nullptr, false, cap, 1);
                 if (e.code == PGCP_OK) HIPCHK(hipEventRecord(P->ev1, s));
@@ -3107,7 +3244,7 @@ static Error refine_solve(pgcp_ctx* ctx, pgcp_part* P, int coupled, const uint8_
         HIPCHK(hipMemcpyAsync(iters.data(), P->d_iters.p, K * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(status.data(), P->d_status.p, K * 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (abort_flag) return Error{PGCP_E_HIP, "batched CG barrier timed out"};
+        if (abort_flag) return barrier_error(P, last_map, s, "batched CG barrier timed out");
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, P->ev0, P->ev1));
         if (!phased) {   // a phased pass has counted each of its launches

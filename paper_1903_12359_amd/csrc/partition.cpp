@@ -269,6 +269,9 @@ Error build_plan(pgcp_part* P, const double* V, int64_t nv, const int32_t* F, in
     for (int i = 0; i < K; ++i) {
         P->sub_nv[i] = (int32_t)verts[i].size();
         int64_t padded = (verts[i].size() + 63) / 64 * 64;
+        // the batched CG reaches a piece's vectors through 32-bit byte offsets (16 bytes a row)
+        if (padded > (int64_t(1) << 27))
+            return Error{PGCP_E_INVALID, "a piece has more than 134,217,728 vertices"};
         if ((int64_t)P->row0[i] + padded > INT32_MAX) return Error{PGCP_E_INVALID, "too many rows"};
         P->row0[i + 1] = P->row0[i] + (int32_t)padded;
     }
