@@ -15,7 +15,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpgcp.so")
+# PGCP_LIB names another build of the same library (the host-sanitizer build
+# libpgcp_asan.so in the sanitizer test)
+LIB_PATH = os.environ.get("PGCP_LIB") or os.path.join(HERE, "libpgcp.so")
 
 PGCP_FREE, PGCP_DISK, PGCP_SPHERE = 0, 1, 2
 MODES = {"free": PGCP_FREE, "disk": PGCP_DISK, "sphere": PGCP_SPHERE}
@@ -557,7 +559,11 @@ def run_stream(ctx: Context, cases, lanes: int = 1, **kw):
     batched-CG kernel at a time on a device (they take the whole device); the
     partition, a lane's weld and solve host steps, and its other kernels
     overlap the solves of the other lanes.  phi_dev is on the lane's stream,
-    which has finished with it when it is yielded.
+    which has finished with it when it is yielded.  Batches that need the
+    streaming CG kernel (pieces too large for the register kernel, e.g. the
+    2048^2 field) have lost workgroups at the first barrier of a launch with
+    several lanes in flight; the launch then gives up and the call raises
+    PGCPError ("batched CG barrier timed out ..."); run them with lanes=1.
     """
     if lanes > 1:
         yield from _run_lanes(ctx, cases, lanes, kw)

@@ -1,5 +1,9 @@
 // C ABI of libpgcp: argument checks, error strings and timing around the
 // host (partition, weld) and device (assembly, solves, distortion) stages.
+// Every entry point that does work opens a roctx range named after itself, so
+// `rocprofv3 --marker-trace` shows each call beside the kernels it launched.
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <chrono>
 #include <cstdlib>
@@ -40,6 +44,14 @@ pgcp_status no_ctx_fail(pgcp_status code, const std::string& msg) {
     no_ctx_error = msg;
     return code;
 }
+
+// roctx range over one entry point (a no-op unless a tool is attached)
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 double now() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -91,6 +103,7 @@ pgcp_status pgcp_ctx_set_stream(pgcp_ctx* ctx, void* hip_stream) {
 
 pgcp_status pgcp_partition(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* F, int64_t nf,
                            const int32_t* label, int32_t mode, pgcp_part** out) {
+    Range range("pgcp_partition");
     if (!V || !F || !label || !out) return bad(ctx, "null argument");
     *out = nullptr;
     pgcp_part* P = new (std::nothrow) pgcp_part();
@@ -156,6 +169,7 @@ void pgcp_part_destroy(pgcp_part* P) {
 }
 
 pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev) {
+    Range range("pgcp_assemble_cotan");
     if (!ctx || !P || !V_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -165,6 +179,7 @@ pgcp_status pgcp_assemble_cotan(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev
 
 pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts* opts, double* bdy_uv_dev,
                              pgcp_solve_stats* stats) {
+    Range range("pgcp_local_param");
     if (!ctx || !P || !bdy_uv_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -181,6 +196,7 @@ pgcp_status pgcp_local_param(pgcp_ctx* ctx, pgcp_part* P, const pgcp_solve_opts*
 }
 
 pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv_host, double* welded_uv_host) {
+    Range range("pgcp_weld");
     if (!P || !bdy_uv_host || !welded_uv_host) return bad(ctx, "null argument");
     if (ctx && !P->host_only) {
         pgcp::AllocScope scope(ctx->stream);
@@ -192,6 +208,7 @@ pgcp_status pgcp_weld(pgcp_ctx* ctx, pgcp_part* P, const double* bdy_uv_host, do
 
 pgcp_status pgcp_laplacian_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, int32_t* rowptr,
                                   int32_t* col, double* val) {
+    Range range("pgcp_laplacian_export");
     if (!ctx || !P || !rowptr) return bad(ctx, "null argument");
     if (P->host_only || !P->assembled) return bad(ctx, "plan has no assembled device matrix");
     if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
@@ -201,6 +218,7 @@ pgcp_status pgcp_laplacian_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t pie
 
 pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* P, const double* welded_uv_dev,
                                 const pgcp_solve_opts* opts, double* out_dev, pgcp_solve_stats* stats) {
+    Range range("pgcp_harmonic_solve");
     if (!ctx || !P || !welded_uv_dev || !out_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -217,6 +235,7 @@ pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* P, const double* welde
 pgcp_status pgcp_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev, const int32_t* F_dev,
                              double* param_dev, double delta, int32_t max_passes, const pgcp_solve_opts* opts,
                              pgcp_fold_stats* stats) {
+    Range range("pgcp_fold_repair");
     if (!ctx || !P || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -227,6 +246,7 @@ pgcp_status pgcp_fold_repair(pgcp_ctx* ctx, pgcp_part* P, const double* V_dev, c
 pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
                             const double* param_dev, int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,
                             int32_t want_quantiles, pgcp_dist_stats* stats) {
+    Range range("pgcp_distortion");
     if (!ctx || !V_dev || !F_dev || !param_dev) return bad(ctx, "null argument");
     if (dim != 2 && dim != 3) return bad(ctx, "dim must be 2 or 3");
     if (nf <= 0 || nv <= 0) return bad(ctx, "empty mesh");
@@ -265,6 +285,7 @@ static pgcp_status area_mode(pgcp_ctx* ctx, int32_t mode, int32_t dim) {
 
 pgcp_status pgcp_area_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
                                  const double* param_dev, int32_t dim, double* d_dev, double* mean_abs) {
+    Range range("pgcp_area_distortion");
     pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
     if (r != PGCP_OK) return r;
     if (!mean_abs) return bad(ctx, "null argument");
@@ -275,6 +296,7 @@ pgcp_status pgcp_area_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
 pgcp_status pgcp_area_objective(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
                                 const double* param_dev, int32_t dim, int32_t mode, const double* mobius,
                                 double* value) {
+    Range range("pgcp_area_objective");
     pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
     if (r != PGCP_OK) return r;
     if ((r = area_mode(ctx, mode, dim)) != PGCP_OK) return r;
@@ -286,6 +308,7 @@ pgcp_status pgcp_area_objective(pgcp_ctx* ctx, const double* V_dev, int64_t nv, 
 pgcp_status pgcp_area_mobius_opt(pgcp_ctx* ctx, const double* V_dev, int64_t nv, const int32_t* F_dev, int64_t nf,
                                  const double* param_dev, int32_t dim, int32_t mode, int32_t max_evals,
                                  double* mobius, double* before, double* after, int32_t* n_evals, double* out_dev) {
+    Range range("pgcp_area_mobius_opt");
     pgcp_status r = area_args(ctx, V_dev, nv, F_dev, nf, param_dev, dim);
     if (r != PGCP_OK) return r;
     if ((r = area_mode(ctx, mode, dim)) != PGCP_OK) return r;
@@ -303,6 +326,7 @@ extern "C" {
 int64_t pgcp_lpc_num_params(void) { return pgcp::lpc_num_params(); }
 
 pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** out) {
+    Range range("pgcp_lpc_create");
     if (!ctx || !out) return bad(ctx, "null argument");
     *out = nullptr;
     pgcp::AllocScope scope(ctx->stream);
@@ -310,12 +334,14 @@ pgcp_status pgcp_lpc_create(pgcp_ctx* ctx, const float* params_host, pgcp_lpc** 
 }
 
 pgcp_status pgcp_lpc_get_params(pgcp_ctx* ctx, const pgcp_lpc* lpc, float* params_host) {
+    Range range("pgcp_lpc_get_params");
     if (!ctx || !lpc || !params_host) return bad(ctx, "null argument");
     pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::lpc_get_params(ctx, lpc, params_host));
 }
 
 pgcp_status pgcp_part_solution(pgcp_ctx* ctx, const pgcp_part* P, int32_t* system, double* out_dev) {
+    Range range("pgcp_part_solution");
     if (!ctx || !P || !out_dev) return bad(ctx, "null argument");
     if (P->host_only || P->solved < 0 || !P->d_u64.p) return bad(ctx, "no solve has run on this plan");
     if (system) *system = P->solved;
@@ -325,12 +351,14 @@ pgcp_status pgcp_part_solution(pgcp_ctx* ctx, const pgcp_part* P, int32_t* syste
 }
 
 pgcp_status pgcp_lpc_save(pgcp_ctx* ctx, const pgcp_lpc* lpc, const char* path) {
+    Range range("pgcp_lpc_save");
     if (!ctx || !lpc || !path) return bad(ctx, "null argument");
     pgcp::AllocScope scope(ctx->stream);
     return fail(ctx, pgcp::lpc_save(ctx, lpc, path));
 }
 
 pgcp_status pgcp_lpc_load(pgcp_ctx* ctx, const char* path, pgcp_lpc** out) {
+    Range range("pgcp_lpc_load");
     if (!ctx || !path || !out) return bad(ctx, "null argument");
     *out = nullptr;
     pgcp::AllocScope scope(ctx->stream);
@@ -351,6 +379,7 @@ void pgcp_lpc_destroy(pgcp_lpc* lpc) {
 }
 
 pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* lpc, int32_t system) {
+    Range range("pgcp_lpc_infer");
     if (!ctx || !P || !lpc) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -360,6 +389,7 @@ pgcp_status pgcp_lpc_infer(pgcp_ctx* ctx, pgcp_part* P, const pgcp_lpc* lpc, int
 
 pgcp_status pgcp_lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, double* o_off, double* o_diag,
                             double* m_off, double* m_diag) {
+    Range range("pgcp_lpc_export");
     if (!ctx || !P) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     if (piece < 0 || piece >= P->K) return bad(ctx, "piece out of range");
@@ -369,6 +399,7 @@ pgcp_status pgcp_lpc_export(pgcp_ctx* ctx, const pgcp_part* P, int32_t piece, do
 
 pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t system, const float* probes_dev,
                           int32_t n_probes, double* loss, float* grad_host) {
+    Range range("pgcp_lpc_grad");
     if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     pgcp::AllocScope scope(ctx->stream);
@@ -378,6 +409,7 @@ pgcp_status pgcp_lpc_grad(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t sy
 
 pgcp_status pgcp_lpc_train_step(pgcp_ctx* ctx, pgcp_part* P, pgcp_lpc* lpc, int32_t system,
                                 const float* probes_dev, int32_t n_probes, float lr, double* loss) {
+    Range range("pgcp_lpc_train_step");
     if (!ctx || !P || !lpc || !probes_dev) return bad(ctx, "null argument");
     if (P->host_only) return bad(ctx, "host-only plan");
     if (!(lr > 0.f)) return bad(ctx, "learning rate must be positive");
