@@ -555,11 +555,11 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
 
 // z = M r for one row of the streaming kernel: every column's r through the
 // piece's coherent vector R, or, when Q is given, this iteration's residual
-// rebuilt there as R - alpha Q (see spai_row).  Six slots per batch keep the
+// rebuilt there as R - alpha Q (see spai_row).  Four slots per batch keep the
 // kernel within its 128 registers with no scratch (a persistent grid must not
 // need scratch: the hardware may run fewer scratch-using waves at once than the
 // grid holds, and the missing workgroups would never reach the barriers).
-template <typename T, typename V2, int NB = 6>
+template <typename T, typename V2, int NB = 4>
 __device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, V2 rown, int prow0,
                                               const PieceVec<V2>& R, const PieceVec<V2>* Q = nullptr, T ax = (T)0,
                                               T ay = (T)0) {
@@ -605,6 +605,35 @@ __device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, V2
     return z;
 }
 
+// Thread 0 of a workgroup waits until the piece's generation reaches nb.  The
+// wait is bounded: past SPIN_MAX polls it raises the abort flag (and every
+// other waiter sees it and leaves); the first workgroup to give up records
+// where: the barrier it waited at, its piece's workgroups, the arrivals and
+// the generation it saw last, its own index.  Returns 1 on abort.
+__device__ __forceinline__ int gen_wait(const unsigned* bar, const unsigned* gen, unsigned nb, int nwg,
+                                        int* abort_flag) {
+    long long spins = 0;
+    while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) {
+        ++spins;
+        if ((spins & 255) == 0) {
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
+            if (spins > SPIN_MAX) {
+                if (__hip_atomic_fetch_add(abort_flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                    abort_flag[2] = (int)nb;
+                    abort_flag[3] = nwg;
+                    abort_flag[4] = (int)__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort_flag[5] = (int)__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort_flag[6] = (int)blockIdx.x;
+                }
+                __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return 1;
+            }
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return 0;
+}
+
 // Barrier of a piece's workgroups fused with the fixed-order sum of their
 // partial records: the workgroup that arrives last (it sees the counter at
 // target - 1, so every other workgroup's stores have completed) sums the
@@ -633,41 +662,32 @@ __device__ __forceinline__ bool piece_reduce(unsigned* bar, unsigned* gen, unsig
         }
         return false;
     }
-    if (threadIdx.x == 0) {
-        long long spins = 0;
-        int ab = 0;
-        while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < nb) {
-            ++spins;
-            if ((spins & 255) == 0) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ab = 1;
-                    break;
-                }
-                if (spins > SPIN_MAX) {
-                    // the first workgroup to give up records where: the barrier
-                    // it waited at, its piece's workgroups, the arrivals and the
-                    // generation it saw last, its own index
-                    if (__hip_atomic_fetch_add(abort_flag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                        abort_flag[2] = (int)nb;
-                        abort_flag[3] = nwg;
-                        abort_flag[4] = (int)__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        abort_flag[5] = (int)__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        abort_flag[6] = (int)blockIdx.x;
-                    }
-                    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ab = 1;
-                    break;
-                }
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        lds_flag[0] = ab;
-    }
+    if (threadIdx.x == 0) lds_flag[0] = gen_wait(bar, gen, nb, nwg, abort_flag);
     __syncthreads();
     if (lds_flag[0]) return true;
 #pragma unroll
     for (int i = 0; i < NV; ++i) out[i] = ld_c(res + off + i);
     return false;
+}
+
+// Barrier of a piece's workgroups without sums: the last to arrive bumps the
+// generation, the others wait for it.  Returns true on abort.
+template <int BLK>
+__device__ __forceinline__ bool piece_barrier(unsigned* bar, unsigned* gen, unsigned nb, int nwg, int* abort_flag,
+                                              int* lds_flag) {
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == nb * (unsigned)nwg - 1u) {
+            __hip_atomic_store(gen, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            lds_flag[0] = 0;
+        } else {
+            lds_flag[0] = gen_wait(bar, gen, nb, nwg, abort_flag);
+        }
+    }
+    __syncthreads();
+    return lds_flag[0] != 0;
 }
 
 // Register-resident batched PCG with LDS-staged vectors.  Thread t of a
@@ -1454,13 +1474,22 @@ __global__ void __launch_bounds__(BLK) k_pcg1(CGArgs<T> a) {
 }
 
 // Streaming batched PCG, for batches whose rows do not fit in the registers of
-// one cooperative grid.  Same iteration, same per-piece barriers and the same
-// fixed-order reductions as k_pcg, but e, r, z, p and q live in memory and each
-// wave walks any number of its workgroup's slices (s0 + wave + NW j).  What
-// neighbours gather (z and p; with the SPAI also r and q) is published and
-// gathered through the piece's coherent vectors, one instruction per row pair;
-// a thread reads its own rows back with plain loads (only it writes them within
-// the launch, and a thread sees its own stores).
+// one cooperative grid.  The same preconditioned CG and the same fixed-order
+// reductions as k_pcg, but e, r, z, p and q live in memory and each wave walks
+// any number of its workgroup's slices (s0 + wave + NW j).  An iteration here
+// costs hundreds of microseconds of memory round trips, so the kernel spends
+// barriers to gather one vector per sparse product instead of two:
+//   A1: p = z + beta p (own rows, in place), published;        barrier
+//   A2: q = A p gathering p; partial p.q;                      barrier + sums
+//   B1: e += alpha p; r -= alpha q; Jacobi: z = D^-1 r and the partials
+//       r.z, r.r; SPAI: r published;                            (SPAI: barrier)
+//   B2 (SPAI): z = M r gathering r; partials r.z, r.r;         barrier + sums
+// Only p (and r with the SPAI) is read by other workgroups: it is published
+// and gathered through the piece's coherent vectors, one instruction per row
+// pair; everything else, and a thread's own rows of p and r, use plain
+// accesses (only the owning thread writes a row within the launch, and a
+// thread sees its own stores).  Every vector is updated in place: a row is
+// next written two barriers after its last remote read.
 template <typename T, int BLK>
 __global__ void __launch_bounds__(BLK) __attribute__((amdgpu_waves_per_eu(PGCP_STREAM_WPE)))
 k_pcg_stream(CGArgs<T> a) {
@@ -1510,8 +1539,8 @@ k_pcg_stream(CGArgs<T> a) {
                 }
             }
             a.e[rw] = zero;
-            PieceVec<V2>(a.z, prow0, prows).st((int)(rw - prow0), z);
-            PieceVec<V2>(a.pa, prow0, prows).st((int)(rw - prow0), zero);
+            a.z[rw] = z;
+            a.pa[rw] = zero;
             acc[0] += (double)r.x * (double)z.x;
             acc[1] += (double)r.y * (double)z.y;
             acc[2] += (double)r.x * (double)r.x;
@@ -1538,8 +1567,8 @@ k_pcg_stream(CGArgs<T> a) {
         rrc[0] = rr0[0];
         rrc[1] = rr0[1];
     } else {
-        // ---- continue a paused piece: e, r, z and p_old are in memory (which
-        // buffers follows from the iteration count), the scalars in cgs
+        // ---- continue a paused piece: e, r, z and p are in memory, the
+        // scalars in cgs
         rz[0] = cs[0];
         rz[1] = cs[1];
         rr0[0] = cs[2];
@@ -1562,8 +1591,7 @@ k_pcg_stream(CGArgs<T> a) {
         best = cs[12];
     }
     int stat = 0;
-    // p_old / p_new and (SPAI) r / r2 alternate with the iteration count
-    int par = it & 1;
+    const PieceVec<V2> Pv(a.pa, prow0, prows), Rv(a.r, prow0, prows);
 
     while (!(done[0] && done[1])) {
         if (it >= a.max_iter) {
@@ -1574,73 +1602,82 @@ k_pcg_stream(CGArgs<T> a) {
             stat = 5;
             break;
         }
-        // ---- phase A: p_new = z + beta p_old on the fly for every column; q = A p_new; p.q
+        // ---- A1: p = z + beta p on the own rows (a finished coordinate keeps p = 0)
         const T bx = done[0] ? (T)0 : (T)beta[0], by = done[1] ? (T)0 : (T)beta[1];
         const T cx = done[0] ? (T)0 : (T)1, cy = done[1] ? (T)0 : (T)1;
+        for (int s = s0 + wave; s < s1; s += 2 * NW) {
+            // two slices at a time: both slices' loads before either's store
+            const int64_t rA = (int64_t)s * 64 + lane, rB = rA + 64 * NW;
+            const bool hasB = s + NW < s1;
+            const V2 zA = a.z[rA], oA = a.pa[rA];
+            V2 zB = zero, oB = zero;
+            if (hasB) {
+                zB = a.z[rB];
+                oB = a.pa[rB];
+            }
+            V2 p;
+            p.x = cx * zA.x + bx * oA.x;
+            p.y = cy * zA.y + by * oA.y;
+            Pv.st((int)(rA - prow0), p);
+            if (hasB) {
+                p.x = cx * zB.x + bx * oB.x;
+                p.y = cy * zB.y + by * oB.y;
+                Pv.st((int)(rB - prow0), p);
+            }
+        }
+        nbar++;
+        if (piece_barrier<BLK>(bar, a.gen + sub, nbar, nwg, a.abort_flag, lds_flag)) {
+            stat = 3;
+            break;
+        }
+        // ---- A2: q = A p, gathering p; p.q
         double pq[2] = {0.0, 0.0};
-        const V2* pold = par ? a.pb : a.pa;
-        const PieceVec<V2> Zv(a.z, prow0, prows), Pold(pold, prow0, prows), Pnew(par ? a.pa : a.pb, prow0, prows);
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
-            const int lr = (int)(rw - prow0);
-            const V2 zr = a.z[rw], orw = pold[rw];
-            V2 p;
-            p.x = cx * zr.x + bx * orw.x;
-            p.y = cy * zr.y + by * orw.y;
-            Pnew.st(lr, p);
-            V2 q = zero;
-            if (!a.mask[rw]) {
-                const int64_t base = a.sl_ptr[s] + lane;
-                const int w = a.sl_w[s];
-                const T d = a.diag[rw];
-                T qx = d * p.x, qy = d * p.y;
-                // KS slots per batch: all column and value loads, then all
-                // gathers, then one wait (slots past the width read the own
-                // row with value 0)
-                constexpr int KS = PGCP_STREAM_KB;
-                for (int k0 = 0; k0 < w; k0 += KS) {
-                    int cc[KS];
-                    T vv[KS];
+            if (a.mask[rw]) continue;
+            const V2 p = a.pa[rw];
+            const int64_t base = a.sl_ptr[s] + lane;
+            const int w = a.sl_w[s];
+            const T d = a.diag[rw];
+            T qx = d * p.x, qy = d * p.y;
+            // KS slots per batch: all column and value loads, then all
+            // gathers, then one wait (slots past the width read the own row
+            // with value 0)
+            constexpr int KS = PGCP_STREAM_KB;
+            for (int k0 = 0; k0 < w; k0 += KS) {
+                int cc[KS];
+                T vv[KS];
 #pragma unroll
-                    for (int t = 0; t < KS; ++t) {
-                        const int64_t el = base + (int64_t)(k0 + t) * 64;
-                        const bool in = k0 + t < w;
-                        cc[t] = in ? a.sl_col[el] : (int)rw;
-                        vv[t] = in ? a.val[el] : (T)0;
-                    }
-                    V2 zz[KS], oo[KS];
-#pragma unroll
-                    for (int t = 0; t < KS; ++t) {
-                        zz[t] = Zv.ld(cc[t] - prow0);
-                        oo[t] = Pold.ld(cc[t] - prow0);
-                    }
-#pragma unroll
-                    for (int t = 0; t < KS; ++t) {
-                        qx += vv[t] * (cx * zz[t].x + bx * oo[t].x);
-                        qy += vv[t] * (cy * zz[t].y + by * oo[t].y);
-                    }
+                for (int t = 0; t < KS; ++t) {
+                    const int64_t el = base + (int64_t)(k0 + t) * 64;
+                    const bool in = k0 + t < w;
+                    cc[t] = in ? a.sl_col[el] : (int)rw;
+                    vv[t] = in ? a.val[el] : (T)0;
                 }
-                if (a.coupled) {
-                    const int pv = a.rprev[rw];
-                    if (pv >= 0) {
-                        const int nx = a.rnext[rw];
-                        const V2 zn = Zv.ld(nx - prow0), on = Pold.ld(nx - prow0);
-                        const V2 zp = Zv.ld(pv - prow0), op = Pold.ld(pv - prow0);
-                        const T pNx = cx * zn.x + bx * on.x, pNy = cy * zn.y + by * on.y;
-                        const T pPx = cx * zp.x + bx * op.x, pPy = cy * zp.y + by * op.y;
-                        qx -= (T)0.5 * (pNy - pPy);
-                        qy += (T)0.5 * (pNx - pPx);
-                    }
+                V2 pp[KS];
+#pragma unroll
+                for (int t = 0; t < KS; ++t) pp[t] = Pv.ld(cc[t] - prow0);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    qx += vv[t] * pp[t].x;
+                    qy += vv[t] * pp[t].y;
                 }
-                q.x = qx;
-                q.y = qy;
-                pq[0] += (double)p.x * (double)qx;
-                pq[1] += (double)p.y * (double)qy;
             }
-            if (spai)
-                PieceVec<V2>(a.q, prow0, prows).st(lr, q);   // gathered by the neighbours to rebuild their residual
-            else
-                a.q[rw] = q;
+            if (a.coupled) {
+                const int pv = a.rprev[rw];
+                if (pv >= 0) {
+                    const int nx = a.rnext[rw];
+                    const V2 pN = Pv.ld(nx - prow0), pP = Pv.ld(pv - prow0);
+                    qx -= (T)0.5 * (pN.y - pP.y);
+                    qy += (T)0.5 * (pN.x - pP.x);
+                }
+            }
+            V2 q;
+            q.x = qx;
+            q.y = qy;
+            a.q[rw] = q;
+            pq[0] += (double)p.x * (double)qx;
+            pq[1] += (double)p.y * (double)qy;
         }
         bsum<BLK, 2>(pq, lds, bpar);
         if (threadIdx.x == 0) {
@@ -1673,46 +1710,54 @@ k_pcg_stream(CGArgs<T> a) {
             }
             if (stat) break;
         }
-        // ---- phase B: e += alpha p; r -= alpha q; z = D^-1 r; r.z, r.r
+        // ---- B1: e += alpha p; r -= alpha q; Jacobi: z = D^-1 r, r.z, r.r;
+        // SPAI: r published for B2
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
-        const V2* pnew = par ? a.pa : a.pb;
-        const V2* rcur = (spai && par) ? a.r2 : a.r;
-        const PieceVec<V2> Zw(a.z, prow0, prows);
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
             if (a.mask[rw]) continue;
-            const int lr = (int)(rw - prow0);
-            const V2 p = pnew[rw], q = a.q[rw];
-            V2 e = a.e[rw], r = rcur[rw], z;
+            const V2 p = a.pa[rw], q = a.q[rw];
+            V2 e = a.e[rw], r = a.r[rw];
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
             r.y -= ay * q.y;
             a.e[rw] = e;
             if (spai) {
-                // z = M r with the neighbours' new residual rebuilt from rcur and q
-                const PieceVec<V2> Qv(a.q, prow0, prows);
-                PieceVec<V2>(par ? a.r : a.r2, prow0, prows).st(lr, r);
-                z = spai_row_stream<T, V2>(a, rw, r, prow0, PieceVec<V2>(rcur, prow0, prows), &Qv, ax, ay);
-                Zw.st(lr, z);
-                acc2[0] += (double)r.x * (double)z.x;
-                acc2[1] += (double)r.y * (double)z.y;
-                acc2[2] += (double)r.x * (double)r.x;
-                acc2[3] += (double)r.y * (double)r.y;
+                Rv.st((int)(rw - prow0), r);
                 continue;
             }
             const T dinv = (T)1 / a.diag[rw];
+            V2 z;
             z.x = dinv * r.x;
             z.y = dinv * r.y;
             a.r[rw] = r;
-            Zw.st(lr, z);
+            a.z[rw] = z;
             acc2[0] += (double)r.x * (double)z.x;
             acc2[1] += (double)r.y * (double)z.y;
             acc2[2] += (double)r.x * (double)r.x;
             acc2[3] += (double)r.y * (double)r.y;
         }
-
+        if (spai) {
+            // ---- B2: z = M r, gathering r; r.z, r.r
+            nbar++;
+            if (piece_barrier<BLK>(bar, a.gen + sub, nbar, nwg, a.abort_flag, lds_flag)) {
+                stat = 3;
+                break;
+            }
+            for (int s = s0 + wave; s < s1; s += NW) {
+                const int64_t rw = (int64_t)s * 64 + lane;
+                if (a.mask[rw]) continue;
+                const V2 r = a.r[rw];
+                const V2 z = spai_row_stream<T, V2>(a, rw, r, prow0, Rv);
+                a.z[rw] = z;
+                acc2[0] += (double)r.x * (double)z.x;
+                acc2[1] += (double)r.y * (double)z.y;
+                acc2[2] += (double)r.x * (double)r.x;
+                acc2[3] += (double)r.y * (double)r.y;
+            }
+        }
         bsum<BLK, 4>(acc2, lds, bpar);
         if (threadIdx.x == 0) {
             for (int i = 0; i < 4; ++i) st_c(mypart + 2 + i, acc2[i]);
@@ -1747,7 +1792,6 @@ k_pcg_stream(CGArgs<T> a) {
             stat = 4;
             break;
         }
-        par ^= 1;
     }
     if (leader) {
         a.iters[sub] = it;

@@ -495,9 +495,10 @@ def _kappa(A):
 
 def test_c5_full_size_sampled(ctx):
     """C5 at full size (2048^2 vertices, 256 log-normal pieces): every stage on
-    the GPU, the oracle on sampled pieces (the smallest, the median and the
-    largest): their DNCP boundary coordinates, and their harmonic maps given the
-    boundary values of the GPU weld; no flipped triangle anywhere.
+    the GPU, the oracle on seven pieces stratified by size (the smallest, the
+    largest and the sixths of the size ranking between): their DNCP boundary
+    coordinates, and their harmonic maps given the boundary values of the GPU
+    weld; no flipped triangle anywhere.
 
     The free-boundary DNCP systems are very ill-conditioned (kappa ~1e6 for the
     smallest C5 piece, ~1e10 for the largest, 122k vertices): an FP64 iterative
@@ -521,7 +522,7 @@ def test_c5_full_size_sampled(ctx):
     part, subs = prepare(case.V, case.F, case.label)
     sizes = np.array([len(s["verts"]) for s in subs])
     order = np.argsort(sizes, kind="stable")
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    pick = sorted({int(order[int(round(q * (len(order) - 1)))]) for q in np.linspace(0.0, 1.0, 7)})
     plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
     V_dev = _dev(case.V)
     pg.assemble_cotan(ctx, plan, V_dev)
