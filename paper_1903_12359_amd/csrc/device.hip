@@ -2582,6 +2582,10 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
                 tw += std::pow((double)((P->row0[i + 1] - P->row0[i]) / 64), wexp);
                 k_on++;
             }
+        // every mapped piece needs a workgroup of its own: with more pieces
+        // than the grid holds there is no weighted map (the loop below would
+        // not run and leave G = 0 while the pieces still took a workgroup each)
+        if (k_on == 0 || k_on > cap) return Error{PGCP_OK, ""};
         int64_t G = 0;
         for (double target = (double)cap; target >= k_on; target *= 0.97) {
             G = 0;
@@ -2985,9 +2989,19 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
         reg_fits |= fits;
     }
     if (uneven && !reg_fits) {
-        cands.clear();
-        cands.push_back(PcgCfg{256, 0, 1});
-        cands.push_back(PcgCfg{512, 0, 1});
+        // the weighted maps that fit replace the other candidates; with more
+        // pieces than a weighted grid holds, the streaming shapes with equal
+        // slices per workgroup stay
+        std::vector<PcgCfg> wc;
+        for (int blk : {256, 512}) {
+            WorkMap T;
+            bool fits;
+            Error e = build_workmap(ctx, P, prec, PcgCfg{blk, 0, 1}, &T, &fits);
+            free_workmap(T);
+            if (e.code) return e;
+            if (fits) wc.push_back(PcgCfg{blk, 0, 1});
+        }
+        if (!wc.empty()) cands = wc;
     }
     for (const PcgCfg& c : cands) {
         WorkMap T;

@@ -141,6 +141,31 @@ def test_dncp_matches_oracle(ctx, name, prec, tol, bound):
     assert err <= bound
 
 
+@pytest.mark.parametrize("cfg", ["512,0,1", "256,0,1"])
+def test_more_pieces_than_a_weighted_grid_holds(ctx, cfg, monkeypatch):
+    """600 pieces, more than the 512-thread weighted streaming map has
+    workgroups: asked for that shape, the library must find it does not fit
+    (a workgroup per piece) and solve with a shape that does, to the oracle's
+    DNCP boundary at 1e-9 (regression: the weighted map once left its grid
+    empty and wrote one workgroup per piece past it)."""
+    import paper_1903_12359_amd as pg
+    monkeypatch.setenv("PGCP_PCG_CFG64", cfg)
+    case = small_grid_case(161, 30, 20, seed=4)
+    say("600 pieces, forced shape", cfg)
+    plan = pg.Plan(ctx, case.V, case.F, case.label, case.mode)
+    assert plan.K == 600
+    pg.assemble_cotan(ctx, plan, _dev(case.V))
+    bdy, rep = pg.local_param(ctx, plan, precision="fp64", tol=1e-13)
+    assert (rep.status == 0).all(), rep.relres
+    part, subs = prepare(case.V, case.F, case.label)
+    ob = np.concatenate(local_params(subs))
+    g = bdy.cpu().numpy()
+    err = np.abs(g[:, 0] + 1j * g[:, 1] - ob).max() / np.abs(ob).max()
+    say("  max rel err", err, "iters", rep.total_iters)
+    assert err <= 1e-9
+    plan.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("prec,tol,bound", [("fp64", 1e-13, 1e-9), ("fp32", 1e-11, 1e-6)])
 def test_harmonic_matches_oracle(ctx, name, prec, tol, bound):
