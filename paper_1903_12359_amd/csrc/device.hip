@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply_inner(int64_t N, const int32_t*
 // valences rarely exceed 8; wider rows take several batches).
 constexpr int KB = 8;
 #ifndef PGCP_STREAM_KB
-#define PGCP_STREAM_KB 4
+#define PGCP_STREAM_KB 6
 #endif
 constexpr int KBR = 4;   // register-resident kernel: own columns come from LDS, fewer registers to spare
 
@@ -553,17 +553,17 @@ __device__ __forceinline__ V2 spai_row(const CGArgs<T>& a, int64_t rw, V2 rown, 
     return z;
 }
 
-// z = M r for one row of the streaming kernel: every column's r through the
-// piece's coherent vector R, or, when Q is given, this iteration's residual
-// rebuilt there as R - alpha Q (see spai_row).  Four slots per batch keep the
-// kernel within its 128 registers with no scratch (a persistent grid must not
-// need scratch: the hardware may run fewer scratch-using waves at once than the
-// grid holds, and the missing workgroups would never reach the barriers).
-template <typename T, typename V2, int NB = 4>
-__device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, V2 rown, int prow0,
-                                              const PieceVec<V2>& R, const PieceVec<V2>* Q = nullptr, T ax = (T)0,
-                                              T ay = (T)0) {
-    const int64_t s = rw >> 6;
+// z = M r for one row of the streaming kernel (slice s, uniform across the
+// wave): the row's SPAI values and columns, then every column's r through the
+// piece's coherent vector R, NB slots per batch (slots past the width, or
+// whose value is 0, read the own row or a masked one and add nothing).  Six
+// slots cover a grid mesh's rows in one batch and keep the FP64 kernel within
+// its 128 registers with no scratch (a persistent grid must not need scratch:
+// the hardware may run fewer scratch-using waves at once than the grid holds,
+// and the missing workgroups would never reach the barriers).
+template <typename T, typename V2, int NB = 6>
+__device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, int s, V2 rown, int prow0,
+                                              const PieceVec<V2>& R) {
     const int64_t base = a.sl_ptr[s] + (rw & 63);
     const int w = a.sl_w[s];
     const T d = (T)a.mdiag[rw];
@@ -580,19 +580,7 @@ __device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, V2
         }
         V2 rr[NB];
 #pragma unroll
-        for (int t = 0; t < NB; ++t) {
-            if (mm[t] == (T)0) {
-                rr[t].x = (T)0;
-                rr[t].y = (T)0;
-            } else {
-                rr[t] = R.ld(cc[t] - prow0);
-                if (Q) {
-                    const V2 qc = Q->ld(cc[t] - prow0);
-                    rr[t].x -= ax * qc.x;
-                    rr[t].y -= ay * qc.y;
-                }
-            }
-        }
+        for (int t = 0; t < NB; ++t) rr[t] = R.ld(cc[t] - prow0);
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             zx += mm[t] * rr[t].x;
@@ -1506,7 +1494,8 @@ k_pcg_stream(CGArgs<T> a) {
     const int pbase = a.sub_pbase[sub], nwg = a.sub_nwg[sub];
     const bool leader = rank == 0 && threadIdx.x == 0;
     const bool spai = a.pc != nullptr && a.pc[sub] != 0;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index as a uniform value: slice numbers, widths and offsets stay in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
     unsigned* bar = a.bar + sub;
     unsigned nbar = 0;
     double* mypart = a.partial + 8 * (int64_t)(pbase + rank);
@@ -1531,7 +1520,7 @@ k_pcg_stream(CGArgs<T> a) {
             if (!a.mask[rw]) {
                 r = a.r[rw];
                 if (spai) {
-                    z = spai_row_stream<T, V2>(a, rw, r, prow0, PieceVec<V2>(a.r, prow0, prows));
+                    z = spai_row_stream<T, V2>(a, rw, s, r, prow0, PieceVec<V2>(a.r, prow0, prows));
                 } else {
                     const T dinv = (T)1 / a.diag[rw];
                     z.x = dinv * r.x;
@@ -1630,23 +1619,50 @@ k_pcg_stream(CGArgs<T> a) {
             stat = 3;
             break;
         }
-        // ---- A2: q = A p, gathering p; p.q
+        // ---- A2: q = A p, gathering p; p.q.  Per slice two memory round
+        // trips: the row's own data, its slots' columns and values and its
+        // loop neighbours together (no branch on the mask before them), then
+        // every gather of p (the first KS slots and the loop neighbours).
         double pq[2] = {0.0, 0.0};
         for (int s = s0 + wave; s < s1; s += NW) {
             const int64_t rw = (int64_t)s * 64 + lane;
-            if (a.mask[rw]) continue;
+            const bool msk = a.mask[rw] != 0;
             const V2 p = a.pa[rw];
+            const T d = a.diag[rw];
             const int64_t base = a.sl_ptr[s] + lane;
             const int w = a.sl_w[s];
-            const T d = a.diag[rw];
-            T qx = d * p.x, qy = d * p.y;
-            // KS slots per batch: all column and value loads, then all
-            // gathers, then one wait (slots past the width read the own row
-            // with value 0)
+            int ix = (int)rw, iy = (int)rw;
+            bool lp = false;
+            if (a.coupled) {
+                const int pv = a.rprev[rw];
+                lp = pv >= 0;
+                if (lp) {
+                    ix = a.rnext[rw];
+                    iy = pv;
+                }
+            }
             constexpr int KS = PGCP_STREAM_KB;
-            for (int k0 = 0; k0 < w; k0 += KS) {
-                int cc[KS];
-                T vv[KS];
+            int cc[KS];
+            T vv[KS];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int64_t el = base + (int64_t)t * 64;
+                const bool in = t < w;
+                cc[t] = in ? a.sl_col[el] : (int)rw;
+                vv[t] = in ? a.val[el] : (T)0;
+            }
+            V2 pp[KS];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) pp[t] = Pv.ld(cc[t] - prow0);
+            const V2 pN = Pv.ld(ix - prow0), pP = Pv.ld(iy - prow0);
+            T qx = d * p.x, qy = d * p.y;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                qx += vv[t] * pp[t].x;
+                qy += vv[t] * pp[t].y;
+            }
+            // rows wider than KS slots (few): the rest in further batches
+            for (int k0 = KS; k0 < w; k0 += KS) {
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
                     const int64_t el = base + (int64_t)(k0 + t) * 64;
@@ -1654,7 +1670,6 @@ k_pcg_stream(CGArgs<T> a) {
                     cc[t] = in ? a.sl_col[el] : (int)rw;
                     vv[t] = in ? a.val[el] : (T)0;
                 }
-                V2 pp[KS];
 #pragma unroll
                 for (int t = 0; t < KS; ++t) pp[t] = Pv.ld(cc[t] - prow0);
 #pragma unroll
@@ -1663,14 +1678,13 @@ k_pcg_stream(CGArgs<T> a) {
                     qy += vv[t] * pp[t].y;
                 }
             }
-            if (a.coupled) {
-                const int pv = a.rprev[rw];
-                if (pv >= 0) {
-                    const int nx = a.rnext[rw];
-                    const V2 pN = Pv.ld(nx - prow0), pP = Pv.ld(pv - prow0);
-                    qx -= (T)0.5 * (pN.y - pP.y);
-                    qy += (T)0.5 * (pN.x - pP.x);
-                }
+            if (lp) {
+                qx -= (T)0.5 * (pN.y - pP.y);
+                qy += (T)0.5 * (pN.x - pP.x);
+            }
+            if (msk) {
+                qx = (T)0;
+                qy = (T)0;
             }
             V2 q;
             q.x = qx;
@@ -1715,10 +1729,13 @@ k_pcg_stream(CGArgs<T> a) {
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
         for (int s = s0 + wave; s < s1; s += NW) {
+            // every load of the row at once; a masked row keeps its values
             const int64_t rw = (int64_t)s * 64 + lane;
-            if (a.mask[rw]) continue;
+            const bool msk = a.mask[rw] != 0;
             const V2 p = a.pa[rw], q = a.q[rw];
             V2 e = a.e[rw], r = a.r[rw];
+            const T dg = a.diag[rw];
+            if (msk) continue;
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
@@ -1728,7 +1745,7 @@ k_pcg_stream(CGArgs<T> a) {
                 Rv.st((int)(rw - prow0), r);
                 continue;
             }
-            const T dinv = (T)1 / a.diag[rw];
+            const T dinv = (T)1 / dg;
             V2 z;
             z.x = dinv * r.x;
             z.y = dinv * r.y;
@@ -1748,9 +1765,10 @@ k_pcg_stream(CGArgs<T> a) {
             }
             for (int s = s0 + wave; s < s1; s += NW) {
                 const int64_t rw = (int64_t)s * 64 + lane;
-                if (a.mask[rw]) continue;
+                const bool msk = a.mask[rw] != 0;
                 const V2 r = a.r[rw];
-                const V2 z = spai_row_stream<T, V2>(a, rw, r, prow0, Rv);
+                const V2 z = spai_row_stream<T, V2>(a, rw, s, r, prow0, Rv);
+                if (msk) continue;
                 a.z[rw] = z;
                 acc2[0] += (double)r.x * (double)z.x;
                 acc2[1] += (double)r.y * (double)z.y;
