@@ -72,9 +72,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_pcg_stream_C5_2048x2048_256pieces.md.
 TRAFFIC = {
     "c5": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "a3609485775faae897f4a3f6f9f1058fa650a6ad9fbd4ed8caa1543419043687",
-           "pcg_shapes": {"dncp": "512,0,1,0", "harmonic": "256,0,1,0"},
-           "bytes_per_launch": 6.966e11},
+           "source_sha256": "c1510c9eb3b608569e02c84fd78f72bfe90bc83f1bd40b86c59368621fb030b7",
+           "pcg_shapes": {"dncp": "256,0,1,0", "harmonic": "256,0,1,0"},
+           "bytes_per_launch": 7.620e11},
 }
 
 
