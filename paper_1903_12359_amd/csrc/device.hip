@@ -2587,7 +2587,7 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     }
     if (cfg.stream && cfg.R <= 0) {
         // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
-        // in proportion to ns_i^wexp, at least one and at most one per slice.
+        // in proportion to ns_i^wexp, at least one and at most one per NW slices.
         // wexp = 1.5 (a whole solve in one launch): rows times expected CG
         // iterations, which grow like sqrt(ns_i) for these Laplacians; 1 (a
         // phase in which every piece runs the same iterations): equal slices
@@ -2604,13 +2604,18 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         // than the grid holds there is no weighted map (the loop below would
         // not run and leave G = 0 while the pieces still took a workgroup each)
         if (k_on == 0 || k_on > cap) return Error{PGCP_OK, ""};
+        // at most one workgroup per NW slices (a slice for every wave): more
+        // would leave waves idle and only add participants to the piece's
+        // barriers (it matters when a few large pieces are left alone)
+        const int64_t nwv = cfg.blk / 64;
         int64_t G = 0;
         for (double target = (double)cap; target >= k_on; target *= 0.97) {
             G = 0;
             for (int i = 0; i < K; ++i) {
                 const int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
                 const double want = target * std::pow((double)ns, wexp) / tw;
-                nw[i] = (only && !only[i]) ? 0 : std::min<int64_t>(ns, std::max<int64_t>(1, (int64_t)std::floor(want)));
+                const int64_t most = std::max<int64_t>(1, ns / nwv);
+                nw[i] = (only && !only[i]) ? 0 : std::min<int64_t>(most, std::max<int64_t>(1, (int64_t)std::floor(want)));
                 G += nw[i];
             }
             if (G <= cap) break;
