@@ -165,6 +165,10 @@ def test_mobius_search_reaches_the_known_optimum(ctx, mode):
     assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-12 * max(1.0, np.abs(Yo).max())
     m, _ = pg.area_distortion(ctx, _dev(V), _dev(F), Y)
     assert abs(m - after) <= 1e-10
+    # every evaluation adds its block sums in a fixed order, whichever
+    # workgroup finishes last: a second search takes the same steps bitwise
+    p2, before2, after2, evals2, _ = pg.area_mobius_opt(ctx, _dev(V), _dev(F), _dev(X), mode, max_evals=budget)
+    assert np.array_equal(p2, p) and before2 == before and after2 == after and evals2 == evals
 
 
 def test_full_size_objective_c2_c3(ctx):
@@ -183,6 +187,7 @@ def test_full_size_objective_c2_c3(ctx):
             o = area.objective(V, F, X, mode, p)
             say("full", name, mode, g, o)
             assert abs(g - o) <= 1e-12 * max(1.0, abs(o))
+            assert pg.area_objective(ctx, Vd, Fd, Xd, mode, p) == g   # bitwise reproducible
 
 
 def test_degenerate_and_invalid_inputs(ctx):
