@@ -33,7 +33,10 @@
  *    batched-CG launch needs every workgroup of the device resident, so the
  *    library runs one such launch per device at a time (a lock held from launch
  *    to completion); all other work of the contexts overlaps.  Autotuned launch
- *    shapes are shared by the contexts of a device.
+ *    shapes are shared by the contexts of a device (and kept in the file that
+ *    the environment variable PGCP_TUNE_CACHE names, if set).  Use one process
+ *    per GPU: a second process's cooperative launches have failed with
+ *    PGCP_E_HIP while another process held the GPU.
  *  - Coordinates are float64.  Indices are int32.  Planar coordinates are stored
  *    as interleaved (x, y) pairs; spherical ones as (x, y, z) triples.
  *  - Boundary arrays ("bdy") list every piece's boundary loop, piece by piece
@@ -265,7 +268,8 @@ pgcp_status pgcp_harmonic_solve(pgcp_ctx* ctx, pgcp_part* part, const double* we
  * area <= 0 in the plane, det[phi_i, phi_j, phi_k] <= 0 on the sphere).
  * V_dev [nv][3], F_dev [nf][3], param_dev [nv][dim], dim 2 or 3.  d_dev [nf][3],
  * mu_dev [nf], flip_dev [nf] may be NULL.  want_quantiles != 0 also computes the
- * median and IQR of |d| (device sort).  stats may be NULL (then async). */
+ * median and IQR of |d| (exact order statistics by a device radix select).
+ * stats may be NULL (then async). */
 pgcp_status pgcp_distortion(pgcp_ctx* ctx, const double* V_dev, int64_t nv,
                             const int32_t* F_dev, int64_t nf, const double* param_dev,
                             int32_t dim, double* d_dev, double* mu_dev, uint8_t* flip_dev,

@@ -33,15 +33,19 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <fstream>
 #include <limits>
 #include <map>
 #include <mutex>
+#include <set>
+#include <sstream>
+#include <string>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
 
 // Streaming kernel: four waves per SIMD (at most 128 VGPRs), with its slot
 // batches of PGCP_STREAM_KB entries sized to fit without spills; measured on
@@ -2332,9 +2336,85 @@ __global__ void __launch_bounds__(BLOCK) k_dist_final(int64_t nblk, const DistPa
     }
 }
 
-__global__ void __launch_bounds__(BLOCK) k_absd(int64_t n, const double* __restrict__ d, double* __restrict__ o) {
-    int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i < n) o[i] = fabs(d[i]);
+// Order statistics of |d| for the median and the quartiles (Section 5's
+// distortion summaries): a radix select, most significant digit first, on the
+// bit patterns of |d|.  For non-negative IEEE doubles (+inf and NaN included)
+// the unsigned order of the bit patterns is the numeric order, NaN last.  Each
+// pass counts, per target, the 8-bit digit at `shift` of every element whose
+// higher digits equal the target's prefix; one workgroup then picks the digit
+// bucket that holds the target's rank.  Eight passes fix all 64 bits, so a
+// target ends as the exact bit pattern of its order statistic.
+constexpr int kQSelMax = 6;
+constexpr int kQSelGrid = 2048;
+
+struct QSelState {
+    uint64_t prefix[kQSelMax];   // digits fixed so far, lower bits zero
+    int64_t rank[kQSelMax];      // 0-based rank among the elements sharing prefix
+};
+
+__global__ void __launch_bounds__(BLOCK) k_qsel_hist(int64_t n, const double* __restrict__ d, int nq, int shift,
+                                                     const QSelState* __restrict__ qs, unsigned* __restrict__ hist) {
+    __shared__ unsigned lh[kQSelMax * 256];
+    __shared__ uint64_t pre[kQSelMax];
+    for (int i = threadIdx.x; i < nq * 256; i += BLOCK) lh[i] = 0u;
+    if ((int)threadIdx.x < nq) pre[threadIdx.x] = qs->prefix[threadIdx.x];
+    __syncthreads();
+    const uint64_t hi = shift >= 56 ? 0ull : ~0ull << (shift + 8);
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * BLOCK;
+    // the trip count is the same for the whole workgroup, so every lane takes
+    // part in the ballots below
+    for (int64_t base = (int64_t)blockIdx.x * BLOCK; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool ok = i < n;
+        const uint64_t key = ok ? (uint64_t)__double_as_longlong(fabs(d[i])) : 0ull;
+        const unsigned dig = (unsigned)(key >> shift) & 255u;
+        for (int t = 0; t < nq; ++t) {
+            bool m = ok && (key & hi) == pre[t];
+            // one LDS atomic per distinct digit among the wave's matching lanes
+            unsigned long long todo = __ballot(m);
+            while (todo) {
+                const int lead = __ffsll(todo) - 1;
+                const unsigned ld = __shfl(dig, lead, 64);
+                const unsigned long long same = __ballot(m && dig == ld);
+                if (lane == lead) atomicAdd(&lh[t * 256 + ld], (unsigned)__popcll(same));
+                m = m && dig != ld;
+                todo &= ~same;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nq * 256; i += BLOCK)
+        if (lh[i]) atomicAdd(&hist[i], lh[i]);
+}
+
+// One workgroup of 256 threads, one per digit value.  Clears the histogram for
+// the next pass; after the last pass (shift 0) writes each target's value.
+__global__ void __launch_bounds__(256) k_qsel_pick(int nq, int shift, QSelState* qs, unsigned* hist, double* out) {
+    __shared__ int64_t sc[256];
+    const int tid = threadIdx.x;
+    for (int t = 0; t < nq; ++t) {
+        const unsigned c = hist[t * 256 + tid];
+        hist[t * 256 + tid] = 0u;
+        sc[tid] = c;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const int64_t v = tid >= off ? sc[tid - off] : 0;
+            __syncthreads();
+            sc[tid] += v;
+            __syncthreads();
+        }
+        const int64_t incl = sc[tid], excl = incl - (int64_t)c;
+        const int64_t r = qs->rank[t];
+        __syncthreads();   // every thread has read the rank before its owner rewrites it
+        if (excl <= r && r < incl) {
+            const uint64_t pf = qs->prefix[t] | ((uint64_t)tid << shift);
+            qs->rank[t] = r - excl;
+            qs->prefix[t] = pf;
+            if (shift == 0) out[t] = __longlong_as_double((long long)pf);
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void k_zero_u32(int64_t n, unsigned* p) {
@@ -2909,7 +2989,7 @@ static Error stream_fit(pgcp_ctx* ctx, pgcp_part* P, int prec, int blk, int* R) 
 // time a batch of that shape is solved on the device, and the fastest (by more
 // than 3% over the earlier candidates) is kept
 // for every context on that device (contexts that solve side by side share
-// it).  The streaming kernel is tried with the fewest and twice the fewest
+// it), and in the PGCP_TUNE_CACHE file if one is named.  The streaming kernel is tried with the fewest and twice the fewest
 // slices per wave that fit.
 static std::mutex g_tuned_mu;
 
@@ -2940,6 +3020,49 @@ static std::mutex& coop_mutex(int device) {
 }
 static std::map<std::string, std::array<int, 3>> g_tuned;   // {threads per workgroup, slices per wave, streaming}
 
+// PGCP_TUNE_CACHE names a text file that keeps tuned shapes across processes,
+// one line per batch: "<tag> <batch key> <threads> <slices per wave>
+// <streaming>".  The tag is the device's architecture and compute-unit count
+// and the time this library was built, so lines written for another GPU or by
+// another build are ignored.  The file is read once per process (under
+// g_tuned_mu) and each new result is appended as one line.
+static std::string tune_tag(pgcp_ctx* ctx) {
+    hipDeviceProp_t pr;
+    std::string t = hipGetDeviceProperties(&pr, ctx->device) == hipSuccess ? pr.gcnArchName : "unknown";
+    t += "/" + std::to_string(ctx->n_cu) + "/" __DATE__ "/" __TIME__;
+    for (char& c : t)
+        if (c == ' ') c = '_';
+    return t;
+}
+
+static void tune_cache_load(pgcp_ctx* ctx) {   // g_tuned_mu held
+    static std::set<std::string> loaded;       // "<device>|<path>"
+    const char* path = getenv("PGCP_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    if (!loaded.insert(std::to_string(ctx->device) + "|" + path).second) return;
+    std::ifstream in(path);
+    const std::string tag = tune_tag(ctx);
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string t, bkey;
+        std::array<int, 3> v{};
+        if (!(ls >> t >> bkey >> v[0] >> v[1] >> v[2]) || t != tag) continue;
+        g_tuned[std::to_string(ctx->device) + "/" + bkey] = v;
+    }
+}
+
+static void tune_cache_append(pgcp_ctx* ctx, const std::string& bkey, const std::array<int, 3>& v) {
+    const char* path = getenv("PGCP_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    const std::string line = tune_tag(ctx) + " " + bkey + " " + std::to_string(v[0]) + " " +
+                             std::to_string(v[1]) + " " + std::to_string(v[2]) + "\n";
+    if (FILE* f = fopen(path, "a")) {   // one write per line: appends from several processes do not interleave
+        fwrite(line.data(), 1, line.size(), f);
+        fclose(f);
+    }
+}
+
 static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t* mask, int coupled) {
     WorkMap& W = prec ? P->wmap32 : P->wmap64;
     if (W.n_wg > 0) return Error{PGCP_OK, ""};
@@ -2955,13 +3078,14 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
             if (fits) return Error{PGCP_OK, ""};
         }
     }
-    std::string key = std::to_string(ctx->device) + "/" + std::to_string(prec) + ":" + std::to_string(coupled) +
-                      ":" + std::to_string(P->K);
-    for (int i = 0; i < P->K; ++i) key += "," + std::to_string((P->row0[i + 1] - P->row0[i]) / 64);
+    std::string bkey = std::to_string(prec) + ":" + std::to_string(coupled) + ":" + std::to_string(P->K);
+    for (int i = 0; i < P->K; ++i) bkey += "," + std::to_string((P->row0[i + 1] - P->row0[i]) / 64);
+    const std::string key = std::to_string(ctx->device) + "/" + bkey;
     bool known = false;
     std::array<int, 3> shape{};
     {
         std::lock_guard<std::mutex> g(g_tuned_mu);
+        tune_cache_load(ctx);
         auto hit = g_tuned.find(key);
         if (hit != g_tuned.end()) {
             known = true;
@@ -3072,6 +3196,7 @@ static Error choose_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, const uint8_t
     {
         std::lock_guard<std::mutex> g(g_tuned_mu);
         g_tuned[key] = {best.blk, best.R, best.stream};
+        if (do_tune) tune_cache_append(ctx, bkey, g_tuned[key]);
     }
     return Error{PGCP_OK, ""};
 }
@@ -3655,7 +3780,7 @@ Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* 
     (void)nv;
     hipStream_t s = ctx->stream;
     const int64_t nblk = (nf + BLOCK - 1) / BLOCK;
-    DevBuf part, fin, dtmp, abs_d, sorted, cubtmp;
+    DevBuf part, fin, dtmp, qsel;
     Error e{PGCP_OK, ""};
     if ((e = dev_alloc(part, nblk * sizeof(DistPart))).code) return e;
     if ((e = dev_alloc(fin, sizeof(DistPart))).code) return e;
@@ -3670,38 +3795,45 @@ Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* 
     HIPCHK(hipGetLastError());
     double med = NAN, iqr = NAN;
     if (want_q) {
+        // midpoint-rule percentiles: position q*n + 1/2 (1-based), linear
+        // between its two neighbours in sorted order; the six order
+        // statistics come from one radix select
         const int64_t n = 3 * nf;
-        if ((e = dev_alloc(abs_d, n * 8)).code) return e;
-        if ((e = dev_alloc(sorted, n * 8)).code) return e;
-        k_absd<<<grid_for(n), BLOCK, 0, s>>>(n, dd, (double*)abs_d.p);
-        size_t tmp_bytes = 0;
-        HIPCHK(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, (const double*)abs_d.p, (double*)sorted.p,
-                                                 (int)n, 0, 64, s));
-        if ((e = dev_alloc(cubtmp, tmp_bytes)).code) return e;
-        HIPCHK(hipcub::DeviceRadixSort::SortKeys(cubtmp.p, tmp_bytes, (const double*)abs_d.p, (double*)sorted.p,
-                                                 (int)n, 0, 64, s));
-        // midpoint-rule percentiles: position q*n + 1/2 (1-based), linear between neighbours
-        auto pct = [&](double q, double* out) -> Error {
-            double pos = q * (double)n + 0.5;
-            int64_t lo = (int64_t)std::floor(pos);
-            double t = pos - (double)lo;
-            double v[2];
-            int64_t i0 = std::min<int64_t>(std::max<int64_t>(lo, 1), n) - 1;
-            int64_t i1 = std::min<int64_t>(std::max<int64_t>(lo + 1, 1), n) - 1;
-            HIPCHK(hipMemcpyAsync(&v[0], (double*)sorted.p + i0, 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(&v[1], (double*)sorted.p + i1, 8, hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (pos <= 1.0) *out = v[0];
-            else if (pos >= (double)n) *out = v[1];
-            else *out = v[0] + t * (v[1] - v[0]);
-            return Error{PGCP_OK, ""};
-        };
-        double p25, p50, p75;
-        if ((e = pct(0.25, &p25)).code) return e;
-        if ((e = pct(0.50, &p50)).code) return e;
-        if ((e = pct(0.75, &p75)).code) return e;
-        med = p50;
-        iqr = p75 - p25;
+        const double qv[3] = {0.25, 0.50, 0.75};
+        QSelState h0{};
+        double tpos[3];
+        for (int j = 0; j < 3; ++j) {
+            const double pos = qv[j] * (double)n + 0.5;
+            const int64_t lo = (int64_t)std::floor(pos);
+            tpos[j] = pos;
+            h0.rank[2 * j] = std::min<int64_t>(std::max<int64_t>(lo, 1), n) - 1;
+            h0.rank[2 * j + 1] = std::min<int64_t>(std::max<int64_t>(lo + 1, 1), n) - 1;
+        }
+        const size_t hist_bytes = kQSelMax * 256 * sizeof(unsigned);
+        if ((e = dev_alloc(qsel, sizeof(QSelState) + hist_bytes + kQSelMax * sizeof(double))).code) return e;
+        QSelState* qs = (QSelState*)qsel.p;
+        unsigned* hist = (unsigned*)((char*)qsel.p + sizeof(QSelState));
+        double* qout = (double*)((char*)hist + hist_bytes);
+        HIPCHK(hipMemcpyAsync(qs, &h0, sizeof(QSelState), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(hist, 0, hist_bytes, s));
+        const unsigned g = (unsigned)std::min<int64_t>((n + BLOCK - 1) / BLOCK, kQSelGrid);
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            k_qsel_hist<<<g, BLOCK, 0, s>>>(n, dd, kQSelMax, shift, qs, hist);
+            HIPCHK(hipGetLastError());
+            k_qsel_pick<<<1, 256, 0, s>>>(kQSelMax, shift, qs, hist, qout);
+            HIPCHK(hipGetLastError());
+        }
+        double v[kQSelMax];
+        HIPCHK(hipMemcpyAsync(v, qout, sizeof(v), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double p[3];
+        for (int j = 0; j < 3; ++j) {
+            const double pos = tpos[j], t = pos - std::floor(pos);
+            const double v0 = v[2 * j], v1 = v[2 * j + 1];
+            p[j] = pos <= 1.0 ? v0 : pos >= (double)n ? v1 : v0 + t * (v1 - v0);
+        }
+        med = p[1];
+        iqr = p[2] - p[0];
     }
     if (st) {
         DistPart h;
@@ -3721,9 +3853,7 @@ Error run_distortion(pgcp_ctx* ctx, const double* V, int64_t nv, const int32_t* 
     dev_free(part);
     dev_free(fin);
     dev_free(dtmp);
-    dev_free(abs_d);
-    dev_free(sorted);
-    dev_free(cubtmp);
+    dev_free(qsel);
     return Error{PGCP_OK, ""};
 }
 

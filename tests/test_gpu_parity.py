@@ -218,6 +218,24 @@ def test_distortion_flips_and_affine(ctx):
     assert st["n_flipped"] == case.nf and flip.cpu().numpy().all()
 
 
+
+@pytest.mark.parametrize("n,jitter,scale", [(20, 0.0, (2.0, 1.0)), (20, 0.3, (1.0, 1.0)), (300, 0.3, (1.5, 0.5))])
+def test_distortion_quantiles_match_oracle(ctx, n, jitter, scale):
+    """Median and IQR of |d| (midpoint-rule percentiles) against the oracle's.
+    The unjittered grid under a scaling has few distinct |d| values (long runs
+    of ties around every percentile position); the 300 x 300 grid has 536,406
+    angles, more than one pass of the selection's grid over the data."""
+    import paper_1903_12359_amd as pg
+    from oracle.distortion import distortion as oracle_distortion
+    case = small_grid_case(n, 1, 1, seed=5, flat=True, jitter=jitter)
+    X = case.V[:, :2] * np.array(scale)
+    o = oracle_distortion(case.V, case.F, X)["stats"]
+    st, _, _, _ = pg.distortion(ctx, _dev(case.V), _dev(case.F.astype(np.int32)), _dev(X), quantiles=True)
+    say("quantiles", n, jitter, scale, st["median_abs_d"], o["median_abs_d"], st["iqr_abs_d"], o["iqr_abs_d"])
+    for k in ("median_abs_d", "iqr_abs_d", "max_abs_d"):
+        assert abs(st[k] - o[k]) <= 1e-9 * max(1.0, abs(o[k])), k
+
+
 _E2E = {}
 
 
