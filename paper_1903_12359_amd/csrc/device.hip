@@ -1732,14 +1732,9 @@ k_pcg_stream(CGArgs<T> a) {
         // SPAI: r published for B2
         const T ax = (T)alpha[0], ay = (T)alpha[1];
         double acc2[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int s = s0 + wave; s < s1; s += NW) {
-            // every load of the row at once; a masked row keeps its values
-            const int64_t rw = (int64_t)s * 64 + lane;
-            const bool msk = a.mask[rw] != 0;
-            const V2 p = a.pa[rw], q = a.q[rw];
-            V2 e = a.e[rw], r = a.r[rw];
-            const T dg = a.diag[rw];
-            if (msk) continue;
+        // one row's update from its loaded values; a masked row keeps its values
+        auto b1_row = [&](int64_t rw, bool msk, V2 p, V2 q, V2 e, V2 r, T dg) {
+            if (msk) return;
             e.x += ax * p.x;
             e.y += ay * p.y;
             r.x -= ax * q.x;
@@ -1747,7 +1742,7 @@ k_pcg_stream(CGArgs<T> a) {
             a.e[rw] = e;
             if (spai) {
                 Rv.st((int)(rw - prow0), r);
-                continue;
+                return;
             }
             const T dinv = (T)1 / dg;
             V2 z;
@@ -1759,6 +1754,29 @@ k_pcg_stream(CGArgs<T> a) {
             acc2[1] += (double)r.y * (double)z.y;
             acc2[2] += (double)r.x * (double)r.x;
             acc2[3] += (double)r.y * (double)r.y;
+        };
+        for (int s = s0 + wave; s < s1; s += 2 * NW) {
+            // two slices at a time, every load of both before either's
+            // stores: one memory round trip per pair (the sums keep the
+            // order of the slices)
+            const int64_t rA = (int64_t)s * 64 + lane, rB = rA + 64 * NW;
+            const bool hasB = s + NW < s1;
+            const bool mA = a.mask[rA] != 0;
+            const V2 pA = a.pa[rA], qA = a.q[rA], eA = a.e[rA], xA = a.r[rA];
+            const T dA = a.diag[rA];
+            bool mB = true;
+            V2 pB = zero, qB = zero, eB = zero, xB = zero;
+            T dB = (T)1;
+            if (hasB) {
+                mB = a.mask[rB] != 0;
+                pB = a.pa[rB];
+                qB = a.q[rB];
+                eB = a.e[rB];
+                xB = a.r[rB];
+                dB = a.diag[rB];
+            }
+            b1_row(rA, mA, pA, qA, eA, xA, dA);
+            if (hasB) b1_row(rB, mB, pB, qB, eB, xB, dB);
         }
         if (spai) {
             // ---- B2: z = M r, gathering r; r.z, r.r
