@@ -72,9 +72,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_pcg_stream_C5_2048x2048_256pieces.md.
 TRAFFIC = {
     "c5": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "fd24d0f17d25f576ef524c6513823266201e455d33e619993a8a11c49647fdee",
+           "source_sha256": "95d70106b64cdd851328796f23c429ae26877bcb5f730d9f887289d5fe41e977",
            "pcg_shapes": {"dncp": "256,0,1,0", "harmonic": "256,0,1,0"},
-           "bytes_per_launch": 7.654e11},
+           "bytes_per_launch": 7.662e11},
 }
 
 
