@@ -488,6 +488,56 @@ struct PieceVec {
     }
 };
 
+// Slot offsets and widths of a wave's slices s, s + nw, s + 2 nw, ... (the
+// streaming kernel's walk): lane l holds those of the wave's (j0 + l)-th
+// slice, so one load serves 64 slices and a slice reads its own from a lane.
+struct SliceMeta {
+    int lo = 0, hi = 0, w = 0;
+    __device__ __forceinline__ void load(const int64_t* sl_ptr, const int32_t* sl_w, int s, int nw, int s1,
+                                         int lane) {
+        const int sl = s + lane * nw;
+        int64_t b = 0;
+        int ww = 0;
+        if (sl < s1) {
+            b = sl_ptr[sl];
+            ww = sl_w[sl];
+        }
+        lo = (int)b;
+        hi = (int)(b >> 32);
+        w = ww;
+        // wait for them here, once per block: a wait at their first read
+        // inside the slice loop would run every slice (and wait for that
+        // slice's stores too)
+        __asm__ volatile("" ::"v"(lo), "v"(hi), "v"(w));
+    }
+    __device__ __forceinline__ int64_t base(int jj) const {
+        return ((int64_t)__builtin_amdgcn_readlane(hi, jj) << 32) | (uint32_t)__builtin_amdgcn_readlane(lo, jj);
+    }
+    __device__ __forceinline__ int width(int jj) const { return __builtin_amdgcn_readlane(w, jj); }
+};
+
+// A buffer resource over one slice's slots of a SELL array (w slots of 64
+// lanes): slot t of lane l is at byte (64 t + l) sizeof(E), a slot past the
+// width reads 0.
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const E* arr, int64_t sbase, int w) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<E*>(arr) + sbase, 0, w * 64 * (int)sizeof(E), kBufWord3);
+}
+template <typename E>
+__device__ __forceinline__ E slot_ld(__amdgpu_buffer_rsrc_t rs, int lane, int t) {
+    if constexpr (sizeof(E) == 8) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(rs, lane * 8, t * 512, 0);
+        E v;
+        __builtin_memcpy(&v, &u, 8);
+        return v;
+    } else {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b32(rs, lane * 4, t * 256, 0);
+        E v;
+        __builtin_memcpy(&v, &u, 4);
+        return v;
+    }
+}
+
 // Fixed-order sum of the piece's partial records (slots off .. off+NV-1).
 template <int BLK, int NV>
 __device__ __forceinline__ void piece_sum(const double* partial, int pbase, int nwg, int off, double (&out)[NV],
@@ -574,12 +624,12 @@ __device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, in
     T zx = d * rown.x, zy = d * rown.y;
     for (int k0 = 0; k0 < w; k0 += NB) {
         int cc[NB];
-        T mm[NB];
+        float mf[NB];   // widened where used, not next to each guarded load
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
             const int64_t el = base + (int64_t)(k0 + t) * 64;
             const bool in = k0 + t < w;
-            mm[t] = in ? (T)a.mval[el] : (T)0;
+            mf[t] = in ? a.mval[el] : 0.0f;
             cc[t] = in ? a.sl_col[el] : (int)rw;
         }
         V2 rr[NB];
@@ -587,8 +637,8 @@ __device__ __forceinline__ V2 spai_row_stream(const CGArgs<T>& a, int64_t rw, in
         for (int t = 0; t < NB; ++t) rr[t] = R.ld(cc[t] - prow0);
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-            zx += mm[t] * rr[t].x;
-            zy += mm[t] * rr[t].y;
+            zx += (T)mf[t] * rr[t].x;
+            zy += (T)mf[t] * rr[t].y;
         }
     }
     V2 z;
@@ -1626,34 +1676,46 @@ k_pcg_stream(CGArgs<T> a) {
         // ---- A2: q = A p, gathering p; p.q.  Per slice two memory round
         // trips: the row's own data, its slots' columns and values and its
         // loop neighbours together (no branch on the mask before them), then
-        // every gather of p (the first KS slots and the loop neighbours).
+        // every gather of p (the first KS slots and the loop neighbours).  The
+        // slice's slot offset and width were loaded one slice ahead, so the
+        // slot loads wait for nothing.
         double pq[2] = {0.0, 0.0};
-        for (int s = s0 + wave; s < s1; s += NW) {
+        SliceMeta sm;
+        // blocks of 64 of the wave's slices: their offsets and widths in one
+        // load, outside the slice loop (whose readlanes then wait for nothing)
+        for (int sb = s0 + wave; sb < s1; sb += 64 * NW) {
+          sm.load(a.sl_ptr, a.sl_w, sb, NW, s1, lane);
+          const int se = min(s1, sb + 64 * NW);
+          for (int j = 0, s = sb; s < se; ++j, s += NW) {
+            const int64_t sbase = sm.base(j);
+            const int w = sm.width(j);
             const int64_t rw = (int64_t)s * 64 + lane;
+            const int64_t base = sbase + lane;
+            const __amdgpu_buffer_rsrc_t rcol = slice_rsrc(a.sl_col, sbase, w), rval = slice_rsrc(a.val, sbase, w);
             const bool msk = a.mask[rw] != 0;
             const V2 p = a.pa[rw];
             const T d = a.diag[rw];
-            const int64_t base = a.sl_ptr[s] + lane;
-            const int w = a.sl_w[s];
-            int ix = (int)rw, iy = (int)rw;
-            bool lp = false;
-            if (a.coupled) {
-                const int pv = a.rprev[rw];
-                lp = pv >= 0;
-                if (lp) {
-                    ix = a.rnext[rw];
-                    iy = pv;
-                }
-            }
             constexpr int KS = PGCP_STREAM_KB;
             int cc[KS];
             T vv[KS];
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
-                const int64_t el = base + (int64_t)t * 64;
-                const bool in = t < w;
-                cc[t] = in ? a.sl_col[el] : (int)rw;
-                vv[t] = in ? a.val[el] : (T)0;
+                // through the slice's buffer resources: no branch, one
+                // address register for every slot; a slot past the width
+                // reads column 0 and value 0, so it adds 0 (its gather reads
+                // the piece's first row, or 0 outside the piece)
+                cc[t] = slot_ld<int>(rcol, lane, t);
+                vv[t] = slot_ld<T>(rval, lane, t);
+            }
+            // the loop neighbours after the slot loads, both at once, so that
+            // waiting for them does not hold the slot loads back
+            int ix = (int)rw, iy = (int)rw;
+            bool lp = false;
+            if (a.coupled) {
+                const int pv = a.rprev[rw], nx = a.rnext[rw];
+                lp = pv >= 0;
+                ix = lp ? nx : (int)rw;
+                iy = lp ? pv : (int)rw;
             }
             V2 pp[KS];
 #pragma unroll
@@ -1696,6 +1758,7 @@ k_pcg_stream(CGArgs<T> a) {
             a.q[rw] = q;
             pq[0] += (double)p.x * (double)qx;
             pq[1] += (double)p.y * (double)qy;
+          }
         }
         bsum<BLK, 2>(pq, lds, bpar);
         if (threadIdx.x == 0) {
@@ -1785,17 +1848,72 @@ k_pcg_stream(CGArgs<T> a) {
                 stat = 3;
                 break;
             }
-            for (int s = s0 + wave; s < s1; s += NW) {
+            // per slice two memory round trips, as in A2: the row's own data
+            // and its first NB slots' values and columns together, then their
+            // gathers (the products in spai_row_stream's order).  The FP32
+            // values are loaded without a branch and widened where they are
+            // used: a conversion inside each guarded load's branch made every
+            // load wait for the one before it.
+            constexpr int NB = 6;
+            SliceMeta sm;
+            for (int sb = s0 + wave; sb < s1; sb += 64 * NW) {   // as in A2
+              sm.load(a.sl_ptr, a.sl_w, sb, NW, s1, lane);
+              const int se = min(s1, sb + 64 * NW);
+              for (int j = 0, s = sb; s < se; ++j, s += NW) {
+                const int64_t sbase = sm.base(j);
+                const int w = sm.width(j);
                 const int64_t rw = (int64_t)s * 64 + lane;
+                const int64_t base = sbase + lane;
+                const __amdgpu_buffer_rsrc_t rcol = slice_rsrc(a.sl_col, sbase, w),
+                                             rmv = slice_rsrc(a.mval, sbase, w);
                 const bool msk = a.mask[rw] != 0;
                 const V2 r = a.r[rw];
-                const V2 z = spai_row_stream<T, V2>(a, rw, s, r, prow0, Rv);
+                const float dmf = a.mdiag[rw];
+                int cc[NB];
+                float mf[NB];
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    // as in A2: a slot past the width reads column 0 and
+                    // value 0 and adds 0
+                    cc[t] = slot_ld<int>(rcol, lane, t);
+                    mf[t] = slot_ld<float>(rmv, lane, t);
+                }
+                V2 rr[NB];
+#pragma unroll
+                for (int t = 0; t < NB; ++t) rr[t] = Rv.ld(cc[t] - prow0);
+                const T dm = (T)dmf;
+                T zx = dm * r.x, zy = dm * r.y;
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    zx += (T)mf[t] * rr[t].x;
+                    zy += (T)mf[t] * rr[t].y;
+                }
+                for (int k0 = NB; k0 < w; k0 += NB) {   // rows wider than NB slots (few)
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) {
+                        const int64_t el = base + (int64_t)(k0 + t) * 64;
+                        const bool in = k0 + t < w;
+                        mf[t] = in ? a.mval[el] : 0.0f;
+                        cc[t] = in ? a.sl_col[el] : (int)rw;
+                    }
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) rr[t] = Rv.ld(cc[t] - prow0);
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) {
+                        zx += (T)mf[t] * rr[t].x;
+                        zy += (T)mf[t] * rr[t].y;
+                    }
+                }
                 if (msk) continue;
+                V2 z;
+                z.x = zx;
+                z.y = zy;
                 a.z[rw] = z;
                 acc2[0] += (double)r.x * (double)z.x;
                 acc2[1] += (double)r.y * (double)z.y;
                 acc2[2] += (double)r.x * (double)r.x;
                 acc2[3] += (double)r.y * (double)r.y;
+              }
             }
         }
         bsum<BLK, 4>(acc2, lds, bpar);
