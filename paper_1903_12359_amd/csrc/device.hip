@@ -41,6 +41,7 @@
 #include <limits>
 #include <map>
 #include <mutex>
+#include <queue>
 #include <set>
 #include <sstream>
 #include <string>
@@ -2580,6 +2581,19 @@ Error launch_assemble(pgcp_ctx* ctx, pgcp_part* P, const double* V) {
     return Error{PGCP_OK, ""};
 }
 
+// Size-weighted streaming maps fill the grid (PGCP_STREAM_FILL=0: leave the
+// rounding's leftover workgroups idle); PGCP_STREAM_WGCU caps the streaming
+// kernel's workgroups per CU below what its registers allow.
+static bool stream_fill_enabled() {
+    const char* v = getenv("PGCP_STREAM_FILL");
+    return !(v && v[0] == '0');
+}
+static int stream_wg_per_cu() {
+    const char* v = getenv("PGCP_STREAM_WGCU");
+    const int n = v ? atoi(v) : 0;
+    return n > 0 ? n : 1 << 20;
+}
+
 // Launch shapes of the batched PCG: threads per workgroup, 64-row slices per
 // wave, and which kernel (register-resident, or streaming through memory).
 struct PcgCfg {
@@ -2792,6 +2806,7 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     const void* kern = cfg.stream ? (prec == 0 ? pcg_stream_kernel<double>(cfg.blk) : pcg_stream_kernel<float>(cfg.blk))
                                   : (prec == 0 ? pcg_kernel<double>(cfg.blk, cfg.R) : pcg_kernel<float>(cfg.blk, cfg.R));
     HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, cfg.blk, lds_bytes));
+    if (cfg.stream) per_cu = std::min(per_cu, stream_wg_per_cu());
     const int64_t cap = (int64_t)per_cu * n_cu;
     int64_t cap1 = 0;
     if (cg1) {
@@ -2837,6 +2852,23 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
             if (G <= cap) break;
         }
         if (G > cap) return Error{PGCP_OK, ""};
+        if (stream_fill_enabled()) {
+            // the workgroups the rounding left over go, one at a time, to the
+            // piece with the most slices per workgroup that can take one: the
+            // grid is then full, so every CU holds the same number of them
+            std::priority_queue<std::pair<double, int>> pq;
+            for (int i = 0; i < K; ++i)
+                if (nw[i] > 0) pq.push({(double)((P->row0[i + 1] - P->row0[i]) / 64) / (double)nw[i], i});
+            while (G < cap && !pq.empty()) {
+                const int i = pq.top().second;
+                pq.pop();
+                const int64_t ns = (P->row0[i + 1] - P->row0[i]) / 64;
+                if (nw[i] >= std::max<int64_t>(1, ns / nwv)) continue;
+                nw[i]++;
+                G++;
+                pq.push({(double)ns / (double)nw[i], i});
+            }
+        }
         W->blk = cfg.blk;
         W->rows_per_thread = 0;
         W->stream = 1;
