@@ -72,9 +72,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_pcg_stream_C5_2048x2048_256pieces.md.
 TRAFFIC = {
     "c5": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "95d70106b64cdd851328796f23c429ae26877bcb5f730d9f887289d5fe41e977",
+           "source_sha256": "8180f3744430d6f858766c386f2f661168c939c738a9045b1c61e590e9003956",
            "pcg_shapes": {"dncp": "256,0,1,0", "harmonic": "256,0,1,0"},
-           "bytes_per_launch": 7.662e11},
+           "bytes_per_launch": 7.660e11},
 }
 
 
