@@ -2588,6 +2588,14 @@ static bool stream_fill_enabled() {
     const char* v = getenv("PGCP_STREAM_FILL");
     return !(v && v[0] == '0');
 }
+// Weighted maps give a piece at most one workgroup per PGCP_STREAM_MINSPW x NW
+// slices (default 2: when a few large pieces are left, fewer and fuller
+// workgroups meet at their barriers faster than they lose in work per wave).
+static int stream_min_spw() {
+    const char* v = getenv("PGCP_STREAM_MINSPW");
+    const int n = v ? atoi(v) : 0;
+    return n > 0 ? n : 2;
+}
 static int stream_wg_per_cu() {
     const char* v = getenv("PGCP_STREAM_WGCU");
     const int n = v ? atoi(v) : 0;
@@ -2818,7 +2826,7 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
     }
     if (cfg.stream && cfg.R <= 0) {
         // Streaming, weighted: fill the cooperative grid, giving piece i workgroups
-        // in proportion to ns_i^wexp, at least one and at most one per NW slices.
+        // in proportion to ns_i^wexp, at least one and at most one per 2 NW slices.
         // wexp = 1.5 (a whole solve in one launch): rows times expected CG
         // iterations, which grow like sqrt(ns_i) for these Laplacians; 1 (a
         // phase in which every piece runs the same iterations): equal slices
@@ -2835,10 +2843,11 @@ static Error build_workmap(pgcp_ctx* ctx, pgcp_part* P, int prec, PcgCfg cfg, Wo
         // than the grid holds there is no weighted map (the loop below would
         // not run and leave G = 0 while the pieces still took a workgroup each)
         if (k_on == 0 || k_on > cap) return Error{PGCP_OK, ""};
-        // at most one workgroup per NW slices (a slice for every wave): more
-        // would leave waves idle and only add participants to the piece's
-        // barriers (it matters when a few large pieces are left alone)
-        const int64_t nwv = cfg.blk / 64;
+        // at most one workgroup per stream_min_spw() x NW slices (two slices
+        // for every wave): more would leave waves short of work and only add
+        // participants to the piece's barriers (it matters when a few large
+        // pieces are left alone)
+        const int64_t nwv = (int64_t)(cfg.blk / 64) * stream_min_spw();
         int64_t G = 0;
         for (double target = (double)cap; target >= k_on; target *= 0.97) {
             G = 0;
