@@ -72,9 +72,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/k_pcg_stream_C5_2048x2048_256pieces.md.
 TRAFFIC = {
     "c5": {"variant": "learned", "precision": "fp32",
-           "source_sha256": "8180f3744430d6f858766c386f2f661168c939c738a9045b1c61e590e9003956",
+           "source_sha256": "3b2d910c59cd023dda620042b05e34e0f463fefeba56fd2b92994134f6eea3ed",
            "pcg_shapes": {"dncp": "256,0,1,0", "harmonic": "256,0,1,0"},
-           "bytes_per_launch": 7.660e11},
+           "bytes_per_launch": 7.620e11},
 }
 
 
